@@ -1,0 +1,189 @@
+/*
+ * stm.h — C ABI of libstm.so: exact space-time hypergraph matching on AMD
+ * MI355X (gfx950).
+ *
+ * The library solves the matching problem of Lombardi, Wolf, Celiktutan and
+ * Sankur, "Activity recognition from videos with parallel hypergraph matching
+ * on GPUs" (arXiv 1505.00581), Section 2: assign each of the M time-ordered
+ * points of a model action to a scene point so that the energy
+ *
+ *   E(z) = lambda1 * sum_i U(z_i) + lambda2 * sum_{i>=3} D(z_i, z_{i-1}, z_{i-2})   (Eq. 1, 9)
+ *
+ * is minimal, where U is the Euclidean descriptor distance (Eq. 2) and
+ * D = D^t + lambda3 * D^g is the temporal plus angular distortion of the
+ * triangle of three consecutive points (Eq. 3-6), under causality (Eq. 7:
+ * consecutive points map to strictly increasing scene frames) and temporal
+ * closeness (Eq. 8: consecutive scene frames less than T apart).  The exact
+ * minimum is found by the second-order min-sum dynamic programme with
+ * backtracking of Section 2.2 (Eq. 10-13), solved here in forward form.
+ *
+ * One "matching" is one model against one scene at one time offset tau: model
+ * point i is searched among the scene points whose frame is within `window`
+ * frames of tau + (t_i - t_1), keeping at most k_max of them (the first by
+ * |frame difference|, then node id).  This bounded per-point search replaces
+ * the paper's pruning of the trellis by causality and closeness (Sections 3.2
+ * and 3.4).  Every offset is an independent matching.
+ *
+ * Conventions
+ *  - Every function returns an int status: STM_OK (0) or a negative code; it
+ *    never throws and never aborts.  stm_last_error() describes the last
+ *    failure of the calling thread.
+ *  - The caller owns every input and output buffer.  The context owns its
+ *    device scratch (frame index, unary table, back-pointers), grows it on
+ *    demand and frees it in stm_destroy.  On STM_ENOMEM nothing was written.
+ *  - Pointers are host pointers unless params->flags has STM_DEVICE_PTRS;
+ *    then every input and output pointer of the call is a device pointer on
+ *    the context's device, the work is queued on `hip_stream` (NULL: the HIP
+ *    default stream) and the call returns once the inputs have been
+ *    validated (one small device-to-host read) and the kernels are queued.
+ *    With host pointers the call is synchronous.
+ *  - One context per host thread; calls on one context must not overlap.
+ *  - An offset with no admissible assignment is not an error: its energies
+ *    are +inf and its assignment row is all -1.
+ *  - Indices are 0-based: model points 0..M-1, scene nodes 0..S-1 in the
+ *    order given (sorted by frame), offsets tau in [0, n_frames - span) with
+ *    span = t_{M-1} - t_0.
+ */
+#ifndef STM_H
+#define STM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define STM_OK            0
+#define STM_EINVAL       -1  /* invalid argument or input data (see stm_last_error) */
+#define STM_ENOMEM       -2  /* device or host allocation failed; nothing written   */
+#define STM_EHIP         -3  /* a HIP runtime call failed (message has its string)  */
+#define STM_EUNSUPPORTED -4  /* flag combination or size not supported by this build */
+
+/* ---- limits ------------------------------------------------------------- */
+/* Candidate cap: one 64-lane wavefront covers the candidates of one model
+ * point, and back-pointers are stored in one byte. */
+#define STM_K_LIMIT 64
+
+/* ---- flags (stm_params.flags) ------------------------------------------- */
+#define STM_DEVICE_PTRS 0x1u  /* all pointers of the call are device pointers           */
+#define STM_K_DENSITY   0x4u  /* per-point cap from the local density of scene points:
+                                 rho = points in frames f-1..f+1 around the shifted
+                                 model frame f, K = clamp(floor((56 rho - 1170) / 60),
+                                 8, 64), never above k_max                                */
+
+/* ---- types -------------------------------------------------------------- */
+typedef struct stm_ctx stm_ctx;
+
+/* A point set (Section 2): `n` points with image coordinates, frame numbers and
+ * appearance descriptors.  Models: t strictly increasing (one point per model
+ * frame, Section 2.1), n >= 3.  Scenes: t non-decreasing with 0 <= t <
+ * n_frames (points sorted by frame), n >= 1.  All arrays row-major,
+ * caller-owned, read-only. */
+typedef struct {
+  int32_t n;            /* number of points                                      */
+  int32_t dim;          /* descriptor length (the paper's HoG/HoF: 162)          */
+  int32_t n_frames;     /* scenes: frame count; models: ignored                  */
+  int32_t reserved;     /* must be 0                                             */
+  const float* xy;      /* [n][2] pixel coordinates (x, y)                        */
+  const int32_t* t;     /* [n] frame numbers                                     */
+  const float* desc;    /* [n][dim] descriptors                                  */
+} stm_points;
+
+/* Energy weights and search limits.  The paper's values (Section 4):
+ * lambda1 = 0.6, lambda2 = 0.2, lambda3 = 5, T = 10. */
+typedef struct {
+  double lambda1;       /* weight of the appearance term U (Eq. 1), >= 0           */
+  double lambda2;       /* weight of the geometric term D (Eq. 1), >= 0            */
+  double lambda3;       /* weight of D^g inside D (Eq. 3), >= 0                    */
+  int32_t T;            /* temporal closeness in frames (Eq. 8); <= 0: no limit    */
+  int32_t window;       /* candidate window half-width in frames, >= 0             */
+  int32_t k_max;        /* candidate cap K, 1..STM_K_LIMIT                         */
+  uint32_t flags;       /* STM_DEVICE_PTRS | STM_K_DENSITY                          */
+} stm_params;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device `hip_device`.  *out receives the context.
+ * Work is queued on the stream each call names (NULL: the HIP default
+ * stream). */
+int stm_create(stm_ctx** out, int hip_device);
+
+/* Waits for the device, then frees the context and all its device scratch.
+ * NULL is a no-op. */
+void stm_destroy(stm_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none).  The string
+ * stays valid until the next call on this thread. */
+const char* stm_last_error(void);
+
+/* ---- offsets ------------------------------------------------------------ */
+
+/* The offsets at which the whole model fits in the scene: [*begin, *end) =
+ * [0, max(0, scene->n_frames - (t_{M-1} - t_0))).  `flags` may hold
+ * STM_DEVICE_PTRS (then model->t is read from the device of `ctx`). */
+int stm_offsets(stm_ctx* ctx, const stm_points* model, const stm_points* scene, uint32_t flags,
+                int32_t* begin, int32_t* end);
+
+/* ---- the exact matching ------------------------------------------------- */
+
+/* Exact optimum of E(z) (Eq. 1 and 9 under Eq. 7 and 8) at every offset in
+ * [tau_begin, tau_end), found by the min-sum recursion with backtracking of
+ * Section 2.2 (Eq. 10-13).  The recursion runs in FP32; the returned
+ * assignment is re-scored from the definition in FP64.
+ * Outputs, each [n_tau] with n_tau = tau_end - tau_begin (assign [n_tau][M]):
+ *   energy32   FP32 optimum of the recursion, +inf if infeasible     (required)
+ *   energy64   FP64 energy of the returned assignment (Eq. 1)         (nullable)
+ *   energy_u64 FP64 appearance part lambda1 * sum_i U(z_i) (Eq. 2)    (nullable)
+ *   assign     scene node id of every model point, -1 if infeasible   (required)
+ * Ties are broken towards the lowest candidate index inside each minimum and
+ * the first (row-major) final state pair.
+ * Errors: STM_EINVAL for n < 3 (model) or < 1 (scene), dim mismatch, model
+ * frames not strictly increasing, scene frames decreasing or outside
+ * [0, n_frames), non-finite coordinates or descriptors, window < 0, k_max
+ * outside 1..STM_K_LIMIT, a negative or non-finite lambda, or an offset range
+ * outside [0, n_frames - span). */
+int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+              const stm_params* params, int32_t tau_begin, int32_t tau_end,
+              float* energy32, double* energy64, double* energy_u64, int32_t* assign,
+              void* hip_stream);
+
+/* ---- the steps of the path, exposed for checking ------------------------- */
+
+/* Candidate lists of every model point at every offset in [tau_begin,
+ * tau_end): cand [n_tau][M][k_max] scene node ids in ascending order (unused
+ * slots -1) and count [n_tau][M].  Same rule and validation as stm_match. */
+int stm_candidates(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+                   const stm_params* params, int32_t tau_begin, int32_t tau_end,
+                   int32_t* cand, int32_t* count, void* hip_stream);
+
+/* FP32 unary table U [M][S]: U[i][n] = ||f_i - g_n||_2 (Eq. 2, without
+ * lambda1), the look-up table of Section 3.3. */
+int stm_unary(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+              const stm_params* params, float* U, void* hip_stream);
+
+/* Work of the recursion over [tau_begin, tau_end), written to counts[4]
+ * (host memory, always): dense cells sum_i K_{i-1} K_i, feasible cells (the
+ * pair is admissible), dense relaxations sum_i K_{i-2} K_{i-1} K_i and
+ * feasible relaxations (both consecutive pairs admissible).  Synchronous. */
+int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+                   const stm_params* params, int32_t tau_begin, int32_t tau_end,
+                   int64_t* counts, void* hip_stream);
+
+/* ---- kernel timing for benchmarks -------------------------------------------- */
+
+/* Enables (1) or disables (0) timing and resets the totals.  While enabled,
+ * every launch of the recursion kernel (the fast variant) is bracketed by two
+ * HIP events recorded on the stream it is launched on. */
+int stm_profile_enable(stm_ctx* ctx, int enable);
+
+/* Waits for the recorded events and writes the summed kernel time in
+ * milliseconds, the number of launches and the number of matchings they
+ * processed.  Any output pointer may be NULL. */
+int stm_profile_read(stm_ctx* ctx, double* dp_ms, int64_t* dp_launches, int64_t* dp_matchings);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STM_H */

@@ -1,0 +1,15 @@
+"""Exact space-time hypergraph matching (arXiv 1505.00581) on AMD MI355X.
+
+The compute path is libstm.so (hand-written HIP kernels for gfx950 behind the
+C ABI in include/stm.h); this package is its Python binding and the seeded
+synthetic workloads.  Build the library with
+`python -m paper_1505_00581_amd.build`.
+"""
+from ._binding import (EXPORTS, LIB_PATH, STM_DEVICE_PTRS, STM_EHIP, STM_EINVAL, STM_ENOMEM,
+                       STM_EUNSUPPORTED, STM_K_DENSITY, STM_K_LIMIT, STM_OK, Context,
+                       DevicePoints, StmError, load)
+from .synth import Params, Points
+
+__all__ = ["Context", "DevicePoints", "Params", "Points", "StmError", "load", "EXPORTS",
+           "LIB_PATH", "STM_OK", "STM_EINVAL", "STM_ENOMEM", "STM_EHIP", "STM_EUNSUPPORTED",
+           "STM_K_LIMIT", "STM_DEVICE_PTRS", "STM_K_DENSITY"]

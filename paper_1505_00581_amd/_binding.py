@@ -1,0 +1,273 @@
+"""ctypes binding of libstm.so (include/stm.h).  Argument marshalling only:
+every step of the matching runs in the library's HIP kernels.
+
+Point sets are any objects with `xy` [n,2] float32, `t` [n] int32, `desc`
+[n,dim] float32 and (scenes) `n_frames`.  numpy arrays give a synchronous
+host-pointer call; torch CUDA tensors (see `DevicePoints`) give a call on the
+current torch stream with device outputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libstm.so")
+
+STM_OK, STM_EINVAL, STM_ENOMEM, STM_EHIP, STM_EUNSUPPORTED = 0, -1, -2, -3, -4
+STM_K_LIMIT = 64
+STM_DEVICE_PTRS = 0x1
+STM_K_DENSITY = 0x4
+
+EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_match",
+           "stm_candidates", "stm_unary", "stm_count_work", "stm_profile_enable",
+           "stm_profile_read")
+
+
+class StmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"stm error {code}: {msg}")
+        self.code = code
+
+
+class _Points(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_frames", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("xy", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("desc", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double),
+                ("lambda3", ctypes.c_double), ("T", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("k_max", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libstm.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1505_00581_amd.build` (no CPU fallback exists)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, i32 = ctypes.c_void_p, ctypes.c_int32
+        lib.stm_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        lib.stm_destroy.argtypes = [P]
+        lib.stm_destroy.restype = None
+        lib.stm_last_error.restype = ctypes.c_char_p
+        lib.stm_offsets.argtypes = [P, ctypes.POINTER(_Points), ctypes.POINTER(_Points),
+                                    ctypes.c_uint32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        lib.stm_match.argtypes = [P, ctypes.POINTER(_Points), ctypes.POINTER(_Points),
+                                  ctypes.POINTER(_Params), i32, i32, P, P, P, P, P]
+        lib.stm_candidates.argtypes = [P, ctypes.POINTER(_Points), ctypes.POINTER(_Points),
+                                       ctypes.POINTER(_Params), i32, i32, P, P, P]
+        lib.stm_unary.argtypes = [P, ctypes.POINTER(_Points), ctypes.POINTER(_Points),
+                                  ctypes.POINTER(_Params), P, P]
+        lib.stm_count_work.argtypes = [P, ctypes.POINTER(_Points), ctypes.POINTER(_Points),
+                                       ctypes.POINTER(_Params), i32, i32, P, P]
+        lib.stm_profile_enable.argtypes = [P, ctypes.c_int]
+        lib.stm_profile_read.argtypes = [P, P, P, P]
+        for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
+                     "stm_count_work", "stm_profile_enable", "stm_profile_read"):
+            getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != STM_OK:
+        raise StmError(rc, load().stm_last_error().decode())
+
+
+@dataclasses.dataclass
+class DevicePoints:
+    """A point set resident in device memory (torch CUDA tensors)."""
+
+    xy: "object"
+    t: "object"
+    desc: "object"
+    n_frames: int = 0
+
+    @staticmethod
+    def from_host(p, device="cuda"):
+        import torch
+        return DevicePoints(torch.as_tensor(np.ascontiguousarray(p.xy, np.float32), device=device),
+                            torch.as_tensor(np.ascontiguousarray(p.t, np.int32), device=device),
+                            torch.as_tensor(np.ascontiguousarray(p.desc, np.float32), device=device),
+                            int(getattr(p, "n_frames", 0)))
+
+
+def _is_device(p) -> bool:
+    return isinstance(p, DevicePoints)
+
+
+def _ptr(a) -> int:
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _points(p, keep: list) -> _Points:
+    if _is_device(p):
+        xy, t, d = p.xy.contiguous(), p.t.contiguous(), p.desc.contiguous()
+        assert str(xy.dtype) == "torch.float32" and str(t.dtype) == "torch.int32"
+    else:
+        xy = np.ascontiguousarray(p.xy, np.float32)
+        t = np.ascontiguousarray(p.t, np.int32)
+        d = np.ascontiguousarray(p.desc, np.float32)
+    keep += [xy, t, d]
+    n, dim = int(t.shape[0]), int(d.shape[1])
+    return _Points(n, dim, int(getattr(p, "n_frames", 0)), 0, _ptr(xy), _ptr(t), _ptr(d))
+
+
+def _params(params, device: bool) -> _Params:
+    flags = (STM_DEVICE_PTRS if device else 0) | (STM_K_DENSITY if params.k_density else 0)
+    return _Params(params.lambda1, params.lambda2, params.lambda3, params.T, params.window,
+                   params.k_max, flags)
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Context:
+    """Owns a libstm context (device scratch).  Device calls are queued on the
+    current torch stream."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.stm_create(ctypes.byref(h), device))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.stm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- offsets ----------------------------------------------------------------
+    def offsets(self, model, scene) -> tuple:
+        keep = []
+        pm, ps = _points(model, keep), _points(scene, keep)
+        b, e = ctypes.c_int32(), ctypes.c_int32()
+        flags = STM_DEVICE_PTRS if _is_device(model) else 0
+        _check(self._lib.stm_offsets(self.handle, ctypes.byref(pm), ctypes.byref(ps), flags,
+                                     ctypes.byref(b), ctypes.byref(e)))
+        return b.value, e.value
+
+    def _range(self, model, scene, tau_begin, tau_end):
+        if tau_begin is None or tau_end is None:
+            b, e = self.offsets(model, scene)
+            tau_begin = b if tau_begin is None else tau_begin
+            tau_end = e if tau_end is None else tau_end
+        return int(tau_begin), int(tau_end)
+
+    # -- the exact matching -------------------------------------------------------
+    def match(self, model, scene, params, tau_begin=None, tau_end=None, out=None):
+        """Exact optimum at every offset in [tau_begin, tau_end) (default: all).
+
+        Returns dict(energy32, energy64, energy_u64, assign, tau_begin, tau_end);
+        numpy arrays for host inputs, torch tensors for DevicePoints (then the
+        work is queued on the current torch stream and this returns after the
+        input validation)."""
+        b, e = self._range(model, scene, tau_begin, tau_end)
+        n, M = e - b, int(model.t.shape[0])
+        keep = []
+        pm, ps = _points(model, keep), _points(scene, keep)
+        dev = _is_device(model)
+        if dev:
+            import torch
+            d = model.xy.device
+            if out is None:
+                out = dict(energy32=torch.empty(n, dtype=torch.float32, device=d),
+                           energy64=torch.empty(n, dtype=torch.float64, device=d),
+                           energy_u64=torch.empty(n, dtype=torch.float64, device=d),
+                           assign=torch.empty((n, M), dtype=torch.int32, device=d))
+            stream = _stream()
+        else:
+            out = dict(energy32=np.empty(n, np.float32), energy64=np.empty(n, np.float64),
+                       energy_u64=np.empty(n, np.float64), assign=np.empty((n, M), np.int32))
+            stream = None
+        pp = _params(params, dev)
+        _check(self._lib.stm_match(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                   ctypes.byref(pp), b, e, _ptr(out["energy32"]),
+                                   _ptr(out["energy64"]), _ptr(out["energy_u64"]),
+                                   _ptr(out["assign"]), stream))
+        out["tau_begin"], out["tau_end"] = b, e
+        return out
+
+    def candidates(self, model, scene, params, tau_begin=None, tau_end=None):
+        b, e = self._range(model, scene, tau_begin, tau_end)
+        n, M = e - b, int(model.t.shape[0])
+        keep = []
+        pm, ps = _points(model, keep), _points(scene, keep)
+        dev = _is_device(model)
+        if dev:
+            import torch
+            d = model.xy.device
+            cand = torch.empty((n, M, params.k_max), dtype=torch.int32, device=d)
+            cnt = torch.empty((n, M), dtype=torch.int32, device=d)
+            stream = _stream()
+        else:
+            cand = np.empty((n, M, params.k_max), np.int32)
+            cnt = np.empty((n, M), np.int32)
+            stream = None
+        pp = _params(params, dev)
+        _check(self._lib.stm_candidates(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                        ctypes.byref(pp), b, e, _ptr(cand), _ptr(cnt), stream))
+        return cand, cnt
+
+    def unary(self, model, scene, params):
+        keep = []
+        pm, ps = _points(model, keep), _points(scene, keep)
+        dev = _is_device(model)
+        M, S = int(model.t.shape[0]), int(scene.t.shape[0])
+        if dev:
+            import torch
+            U = torch.empty((M, S), dtype=torch.float32, device=model.xy.device)
+            stream = _stream()
+        else:
+            U = np.empty((M, S), np.float32)
+            stream = None
+        pp = _params(params, dev)
+        _check(self._lib.stm_unary(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                   ctypes.byref(pp), _ptr(U), stream))
+        return U
+
+    def count_work(self, model, scene, params, tau_begin=None, tau_end=None) -> dict:
+        b, e = self._range(model, scene, tau_begin, tau_end)
+        keep = []
+        pm, ps = _points(model, keep), _points(scene, keep)
+        dev = _is_device(model)
+        c = np.zeros(4, np.int64)
+        pp = _params(params, dev)
+        _check(self._lib.stm_count_work(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                        ctypes.byref(pp), b, e, c.ctypes.data,
+                                        _stream() if dev else None))
+        return dict(dense_cells=int(c[0]), feasible_cells=int(c[1]), dense_relax=int(c[2]),
+                    feasible_relax=int(c[3]))
+
+    # -- kernel timing ------------------------------------------------------------
+    def profile_enable(self, enable: bool = True):
+        _check(self._lib.stm_profile_enable(self.handle, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        ms = ctypes.c_double()
+        nl, nm = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.stm_profile_read(self.handle, ctypes.addressof(ms), ctypes.addressof(nl),
+                                          ctypes.addressof(nm)))
+        return dict(dp_ms=ms.value, dp_launches=nl.value, dp_matchings=nm.value)

@@ -1,0 +1,448 @@
+// Host side of libstm.so: argument and data validation, the context and its
+// device scratch, and the order of the kernels on the stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "stm.h"
+#include "stm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define STM_HIP(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(STM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct stm_ctx {
+  int device = 0;
+  // scratch
+  DevBuf fstart, theta, U, bp, last2, degen, val, counts;
+  // staging for host-pointer calls
+  DevBuf mxy, mt, mdesc, sxy, st, sdesc;
+  DevBuf o_e32, o_e64, o_eu, o_assign, o_cand, o_cnt;
+  size_t bp_chunk_bytes = size_t(1) << 30;  // back-pointer scratch per chunk of offsets
+  // kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
+  size_t prof_used = 0;             // events in use
+  int64_t prof_matchings = 0;
+};
+
+namespace {
+
+// Grows `b` to at least `bytes`; the old contents are not kept.
+int grow(stm_ctx* ctx, DevBuf& b, size_t bytes, hipStream_t st) {
+  if (bytes <= b.cap) return STM_OK;
+  if (b.p) {
+    STM_HIP(hipStreamSynchronize(st));
+    STM_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 8 + 256;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(STM_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+  }
+  b.cap = want;
+  return STM_OK;
+}
+
+void release(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+bool finite_lambda(double v) { return std::isfinite(v) && v >= 0.0; }
+
+// Checks that do not need the data.
+int check_shapes(const stm_points* m, const stm_points* s, const stm_params* p) {
+  if (!m || !s || !p) return fail(STM_EINVAL, "null model, scene or params");
+  if (m->n < 3) return fail(STM_EINVAL, "model needs at least 3 points");
+  if (s->n < 1) return fail(STM_EINVAL, "scene needs at least 1 point");
+  if (m->dim < 1 || m->dim != s->dim) return fail(STM_EINVAL, "descriptor dims differ or are < 1");
+  if (m->dim > 256) return fail(STM_EUNSUPPORTED, "descriptor dim above 256");
+  if (s->n_frames < 1) return fail(STM_EINVAL, "scene needs n_frames >= 1");
+  if (m->reserved != 0 || s->reserved != 0) return fail(STM_EINVAL, "reserved field must be 0");
+  if (!m->xy || !m->t || !m->desc || !s->xy || !s->t || !s->desc)
+    return fail(STM_EINVAL, "null point array");
+  if (p->k_max < 1 || p->k_max > STM_K_LIMIT) return fail(STM_EINVAL, "k_max outside 1..64");
+  if (p->window < 0) return fail(STM_EINVAL, "window < 0");
+  if (!finite_lambda(p->lambda1) || !finite_lambda(p->lambda2) || !finite_lambda(p->lambda3))
+    return fail(STM_EINVAL, "lambdas must be finite and >= 0");
+  if (p->flags & ~(STM_DEVICE_PTRS | STM_K_DENSITY)) return fail(STM_EUNSUPPORTED, "unknown flag");
+  return STM_OK;
+}
+
+const char* bit_message(int bits) {
+  if (bits & 1) return "model frames not strictly increasing";
+  if (bits & 2) return "scene frames not sorted (non-decreasing)";
+  if (bits & 4) return "scene frame outside [0, n_frames)";
+  if (bits & 8) return "non-finite model coordinate or descriptor";
+  if (bits & 16) return "non-finite scene coordinate or descriptor";
+  return "invalid input";
+}
+
+int host_validate(const stm_points* m, const stm_points* s) {
+  int bits = 0;
+  for (int i = 0; i < m->n; ++i) {
+    if (i > 0 && m->t[i] <= m->t[i - 1]) bits |= 1;
+    if (!std::isfinite(m->xy[2 * i]) || !std::isfinite(m->xy[2 * i + 1])) bits |= 8;
+  }
+  for (size_t i = 0; i < (size_t)m->n * m->dim; ++i)
+    if (!std::isfinite(m->desc[i])) bits |= 8;
+  for (int i = 0; i < s->n; ++i) {
+    if (i > 0 && s->t[i] < s->t[i - 1]) bits |= 2;
+    if (s->t[i] < 0 || s->t[i] >= s->n_frames) bits |= 4;
+    if (!std::isfinite(s->xy[2 * i]) || !std::isfinite(s->xy[2 * i + 1])) bits |= 16;
+  }
+  for (size_t i = 0; i < (size_t)s->n * s->dim; ++i)
+    if (!std::isfinite(s->desc[i])) bits |= 16;
+  return bits;
+}
+
+// Inputs on the device, validated, with the frame index built.
+struct Prepared {
+  stm::ModelView m;
+  stm::SceneView s;
+  stm::SearchParams sp;
+  int32_t span = 0;
+  hipStream_t st = nullptr;
+  bool device = false;
+};
+
+template <class T>
+int stage(stm_ctx* ctx, DevBuf& b, const T* host, size_t count, hipStream_t st) {
+  int rc = grow(ctx, b, count * sizeof(T), st);
+  if (rc) return rc;
+  STM_HIP(hipMemcpyAsync(b.p, host, count * sizeof(T), hipMemcpyHostToDevice, st));
+  return STM_OK;
+}
+
+int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_params* p,
+            void* hip_stream, Prepared& out) {
+  int rc = check_shapes(m, s, p);
+  if (rc) return rc;
+  if (!(p->flags & STM_DEVICE_PTRS)) {
+    const int bits = host_validate(m, s);
+    if (bits) return fail(STM_EINVAL, bit_message(bits));
+  }
+  if (!ctx) return fail(STM_EINVAL, "null context");
+  STM_HIP(hipSetDevice(ctx->device));
+  out.st = static_cast<hipStream_t>(hip_stream);
+  out.device = (p->flags & STM_DEVICE_PTRS) != 0;
+  const int M = m->n, S = s->n, D = m->dim, F = s->n_frames;
+  if (out.device) {
+    out.m = {reinterpret_cast<const float2*>(m->xy), m->t, m->desc, M};
+    out.s = {reinterpret_cast<const float2*>(s->xy), s->t, s->desc, nullptr, S, F, D};
+    if ((rc = grow(ctx, ctx->val, 2 * sizeof(int32_t), out.st))) return rc;
+    STM_HIP(hipMemsetAsync(ctx->val.p, 0, 2 * sizeof(int32_t), out.st));
+    STM_HIP(stm::launch_validate(out.m, out.s, static_cast<int32_t*>(ctx->val.p), out.st));
+    int32_t hv[2] = {0, 0};
+    STM_HIP(hipMemcpyAsync(hv, ctx->val.p, sizeof(hv), hipMemcpyDeviceToHost, out.st));
+    STM_HIP(hipStreamSynchronize(out.st));
+    if (hv[0]) return fail(STM_EINVAL, bit_message(hv[0]));
+    out.span = hv[1];
+  } else {
+    out.span = m->t[M - 1] - m->t[0];
+    if ((rc = stage(ctx, ctx->mxy, m->xy, (size_t)M * 2, out.st))) return rc;
+    if ((rc = stage(ctx, ctx->mt, m->t, (size_t)M, out.st))) return rc;
+    if ((rc = stage(ctx, ctx->mdesc, m->desc, (size_t)M * D, out.st))) return rc;
+    if ((rc = stage(ctx, ctx->sxy, s->xy, (size_t)S * 2, out.st))) return rc;
+    if ((rc = stage(ctx, ctx->st, s->t, (size_t)S, out.st))) return rc;
+    if ((rc = stage(ctx, ctx->sdesc, s->desc, (size_t)S * D, out.st))) return rc;
+    out.m = {static_cast<const float2*>(ctx->mxy.p), static_cast<const int32_t*>(ctx->mt.p),
+             static_cast<const float*>(ctx->mdesc.p), M};
+    out.s = {static_cast<const float2*>(ctx->sxy.p), static_cast<const int32_t*>(ctx->st.p),
+             static_cast<const float*>(ctx->sdesc.p), nullptr, S, F, D};
+  }
+  if ((rc = grow(ctx, ctx->fstart, ((size_t)F + 1) * sizeof(int32_t), out.st))) return rc;
+  STM_HIP(stm::launch_fstart(out.s.t, S, F, static_cast<int32_t*>(ctx->fstart.p), out.st));
+  out.s.fstart = static_cast<const int32_t*>(ctx->fstart.p);
+  // a window wider than the scene adds only empty frames
+  out.sp = {p->T, std::min(p->window, F), p->k_max, (p->flags & STM_K_DENSITY) ? 1 : 0};
+  return STM_OK;
+}
+
+int check_range(const Prepared& pr, int32_t tau_begin, int32_t tau_end) {
+  const long long n_off = std::max(0LL, (long long)pr.s.F - pr.span);
+  if (tau_begin < 0 || tau_end < tau_begin || tau_end > n_off)
+    return fail(STM_EINVAL, "offset range [" + std::to_string(tau_begin) + ", " +
+                                std::to_string(tau_end) + ") outside [0, " + std::to_string(n_off) + ")");
+  return STM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stm_create(stm_ctx** out, int hip_device) {
+  g_err.clear();
+  if (!out) return fail(STM_EINVAL, "null output pointer");
+  *out = nullptr;
+  int n = 0;
+  STM_HIP(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n) return fail(STM_EINVAL, "no such HIP device");
+  STM_HIP(hipSetDevice(hip_device));
+  stm_ctx* c = new (std::nothrow) stm_ctx();
+  if (!c) return fail(STM_ENOMEM, "host allocation failed");
+  c->device = hip_device;
+  *out = c;
+  return STM_OK;
+}
+
+void stm_destroy(stm_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&ctx->fstart, &ctx->theta, &ctx->U,     &ctx->bp,    &ctx->last2, &ctx->degen,
+                    &ctx->val,    &ctx->counts, &ctx->mxy,  &ctx->mt,    &ctx->mdesc, &ctx->sxy,
+                    &ctx->st,     &ctx->sdesc,  &ctx->o_e32, &ctx->o_e64, &ctx->o_eu, &ctx->o_assign,
+                    &ctx->o_cand, &ctx->o_cnt};
+  for (DevBuf* b : bufs) release(*b);
+  for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
+  delete ctx;
+}
+
+const char* stm_last_error(void) { return g_err.c_str(); }
+
+int stm_offsets(stm_ctx* ctx, const stm_points* model, const stm_points* scene, uint32_t flags,
+                int32_t* begin, int32_t* end) {
+  g_err.clear();
+  if (!model || !scene || !begin || !end || !model->t) return fail(STM_EINVAL, "null argument");
+  if (model->n < 1) return fail(STM_EINVAL, "empty model");
+  int32_t t0 = 0, t1 = 0;
+  if (flags & STM_DEVICE_PTRS) {
+    if (!ctx) return fail(STM_EINVAL, "device pointers need a context");
+    STM_HIP(hipSetDevice(ctx->device));
+    STM_HIP(hipMemcpy(&t0, model->t, sizeof(int32_t), hipMemcpyDeviceToHost));
+    STM_HIP(hipMemcpy(&t1, model->t + model->n - 1, sizeof(int32_t), hipMemcpyDeviceToHost));
+  } else {
+    t0 = model->t[0];
+    t1 = model->t[model->n - 1];
+  }
+  *begin = 0;
+  const long long e = (long long)scene->n_frames - ((long long)t1 - t0);
+  *end = static_cast<int32_t>(e > 0 ? e : 0);
+  return STM_OK;
+}
+
+int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+              const stm_params* params, int32_t tau_begin, int32_t tau_end, float* energy32,
+              double* energy64, double* energy_u64, int32_t* assign, void* hip_stream) {
+  g_err.clear();
+  Prepared pr;
+  int rc = prepare(ctx, model, scene, params, hip_stream, pr);
+  if (rc) return rc;
+  if ((rc = check_range(pr, tau_begin, tau_end))) return rc;
+  const int n_tau = tau_end - tau_begin;
+  if (n_tau == 0) return STM_OK;
+  if (!energy32 || !assign) return fail(STM_EINVAL, "energy32 and assign are required");
+  const int M = pr.m.M, S = pr.s.S, K = pr.sp.K;
+  const hipStream_t st = pr.st;
+
+  // outputs: caller's device buffers, or staging for host pointers
+  float* d_e32 = energy32;
+  double* d_e64 = energy64;
+  double* d_eu = energy_u64;
+  int32_t* d_as = assign;
+  if (!pr.device) {
+    if ((rc = grow(ctx, ctx->o_e32, (size_t)n_tau * sizeof(float), st))) return rc;
+    if ((rc = grow(ctx, ctx->o_assign, (size_t)n_tau * M * sizeof(int32_t), st))) return rc;
+    d_e32 = static_cast<float*>(ctx->o_e32.p);
+    d_as = static_cast<int32_t*>(ctx->o_assign.p);
+    if (energy64) {
+      if ((rc = grow(ctx, ctx->o_e64, (size_t)n_tau * sizeof(double), st))) return rc;
+      d_e64 = static_cast<double*>(ctx->o_e64.p);
+    }
+    if (energy_u64) {
+      if ((rc = grow(ctx, ctx->o_eu, (size_t)n_tau * sizeof(double), st))) return rc;
+      d_eu = static_cast<double*>(ctx->o_eu.p);
+    }
+  }
+
+  // model angles and the unary table (Section 3.3)
+  if ((rc = grow(ctx, ctx->theta, (size_t)M * sizeof(float2), st))) return rc;
+  STM_HIP(stm::launch_model_angles(pr.m, static_cast<float2*>(ctx->theta.p), st));
+  if ((rc = grow(ctx, ctx->U, (size_t)M * S * sizeof(float), st))) return rc;
+  STM_HIP(stm::launch_unary_f32(pr.m, pr.s, static_cast<float*>(ctx->U.p), st));
+
+  // the recursion, in chunks of offsets bounded by the back-pointer scratch
+  const size_t per_tau = (size_t)(M - 2) * K * K;
+  int chunk = static_cast<int>(std::min<size_t>(n_tau, std::max<size_t>(1, ctx->bp_chunk_bytes / per_tau)));
+  if ((rc = grow(ctx, ctx->bp, per_tau * chunk, st))) return rc;
+  if ((rc = grow(ctx, ctx->last2, (size_t)chunk * sizeof(int2), st))) return rc;
+  if ((rc = grow(ctx, ctx->degen, (size_t)chunk * sizeof(int32_t), st))) return rc;
+  for (int c0 = 0; c0 < n_tau; c0 += chunk) {
+    const int nc = std::min(chunk, n_tau - c0);
+    stm::DPLaunch a;
+    a.m = pr.m;
+    a.s = pr.s;
+    a.sp = pr.sp;
+    a.U = static_cast<const float*>(ctx->U.p);
+    a.theta = static_cast<const float2*>(ctx->theta.p);
+    a.lambda1 = static_cast<float>(params->lambda1);
+    a.lambda2 = static_cast<float>(params->lambda2);
+    a.w = static_cast<float>(params->lambda2 * params->lambda3);
+    a.tau0 = tau_begin + c0;
+    a.n_tau = nc;
+    a.bp = static_cast<uint8_t*>(ctx->bp.p);
+    a.e32 = d_e32 + c0;
+    a.last2 = static_cast<int2*>(ctx->last2.p);
+    a.degen = static_cast<int32_t*>(ctx->degen.p);
+    if (ctx->prof) {
+      if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
+        for (int q = 0; q < 2; ++q) {
+          hipEvent_t ev;
+          STM_HIP(hipEventCreate(&ev));
+          ctx->prof_ev.push_back(ev);
+        }
+      }
+      STM_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used], st));
+      STM_HIP(stm::launch_dp_fast(a, st));
+      STM_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used + 1], st));
+      ctx->prof_used += 2;
+      ctx->prof_matchings += nc;
+    } else {
+      STM_HIP(stm::launch_dp_fast(a, st));
+    }
+    STM_HIP(stm::launch_dp_degenerate(a, st));
+    STM_HIP(stm::launch_backtrack(a, d_as + (size_t)c0 * M, st));
+    STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp.T, params->lambda1, params->lambda2,
+                                params->lambda3, d_as + (size_t)c0 * M, nc,
+                                d_e64 ? d_e64 + c0 : nullptr, d_eu ? d_eu + c0 : nullptr, st));
+  }
+
+  if (!pr.device) {
+    STM_HIP(hipMemcpyAsync(energy32, d_e32, (size_t)n_tau * sizeof(float), hipMemcpyDeviceToHost, st));
+    STM_HIP(hipMemcpyAsync(assign, d_as, (size_t)n_tau * M * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (energy64)
+      STM_HIP(hipMemcpyAsync(energy64, d_e64, (size_t)n_tau * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (energy_u64)
+      STM_HIP(hipMemcpyAsync(energy_u64, d_eu, (size_t)n_tau * sizeof(double), hipMemcpyDeviceToHost, st));
+    STM_HIP(hipStreamSynchronize(st));
+  }
+  return STM_OK;
+}
+
+int stm_candidates(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+                   const stm_params* params, int32_t tau_begin, int32_t tau_end, int32_t* cand,
+                   int32_t* count, void* hip_stream) {
+  g_err.clear();
+  Prepared pr;
+  int rc = prepare(ctx, model, scene, params, hip_stream, pr);
+  if (rc) return rc;
+  if ((rc = check_range(pr, tau_begin, tau_end))) return rc;
+  const int n_tau = tau_end - tau_begin;
+  if (n_tau == 0) return STM_OK;
+  if (!cand || !count) return fail(STM_EINVAL, "null output");
+  const size_t nc = (size_t)n_tau * pr.m.M * pr.sp.K, nn = (size_t)n_tau * pr.m.M;
+  int32_t* d_c = cand;
+  int32_t* d_n = count;
+  if (!pr.device) {
+    if ((rc = grow(ctx, ctx->o_cand, nc * sizeof(int32_t), pr.st))) return rc;
+    if ((rc = grow(ctx, ctx->o_cnt, nn * sizeof(int32_t), pr.st))) return rc;
+    d_c = static_cast<int32_t*>(ctx->o_cand.p);
+    d_n = static_cast<int32_t*>(ctx->o_cnt.p);
+  }
+  STM_HIP(stm::launch_candidates(pr.m, pr.s, pr.sp, tau_begin, n_tau, d_c, d_n, pr.st));
+  if (!pr.device) {
+    STM_HIP(hipMemcpyAsync(cand, d_c, nc * sizeof(int32_t), hipMemcpyDeviceToHost, pr.st));
+    STM_HIP(hipMemcpyAsync(count, d_n, nn * sizeof(int32_t), hipMemcpyDeviceToHost, pr.st));
+    STM_HIP(hipStreamSynchronize(pr.st));
+  }
+  return STM_OK;
+}
+
+int stm_unary(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+              const stm_params* params, float* U, void* hip_stream) {
+  g_err.clear();
+  Prepared pr;
+  int rc = prepare(ctx, model, scene, params, hip_stream, pr);
+  if (rc) return rc;
+  if (!U) return fail(STM_EINVAL, "null output");
+  const size_t n = (size_t)pr.m.M * pr.s.S;
+  float* d_u = U;
+  if (!pr.device) {
+    if ((rc = grow(ctx, ctx->U, n * sizeof(float), pr.st))) return rc;
+    d_u = static_cast<float*>(ctx->U.p);
+  }
+  STM_HIP(stm::launch_unary_f32(pr.m, pr.s, d_u, pr.st));
+  if (!pr.device) {
+    STM_HIP(hipMemcpyAsync(U, d_u, n * sizeof(float), hipMemcpyDeviceToHost, pr.st));
+    STM_HIP(hipStreamSynchronize(pr.st));
+  }
+  return STM_OK;
+}
+
+int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+                   const stm_params* params, int32_t tau_begin, int32_t tau_end, int64_t* counts,
+                   void* hip_stream) {
+  g_err.clear();
+  Prepared pr;
+  int rc = prepare(ctx, model, scene, params, hip_stream, pr);
+  if (rc) return rc;
+  if ((rc = check_range(pr, tau_begin, tau_end))) return rc;
+  if (!counts) return fail(STM_EINVAL, "null output");
+  if ((rc = grow(ctx, ctx->counts, 4 * sizeof(unsigned long long), pr.st))) return rc;
+  STM_HIP(hipMemsetAsync(ctx->counts.p, 0, 4 * sizeof(unsigned long long), pr.st));
+  STM_HIP(stm::launch_count(pr.m, pr.s, pr.sp, tau_begin, tau_end - tau_begin,
+                            static_cast<unsigned long long*>(ctx->counts.p), pr.st));
+  unsigned long long h[4];
+  STM_HIP(hipMemcpyAsync(h, ctx->counts.p, sizeof(h), hipMemcpyDeviceToHost, pr.st));
+  STM_HIP(hipStreamSynchronize(pr.st));
+  for (int i = 0; i < 4; ++i) counts[i] = static_cast<int64_t>(h[i]);
+  return STM_OK;
+}
+
+int stm_profile_enable(stm_ctx* ctx, int enable) {
+  g_err.clear();
+  if (!ctx) return fail(STM_EINVAL, "null context");
+  STM_HIP(hipSetDevice(ctx->device));
+  ctx->prof = enable != 0;
+  ctx->prof_used = 0;
+  ctx->prof_matchings = 0;
+  return STM_OK;
+}
+
+int stm_profile_read(stm_ctx* ctx, double* dp_ms, int64_t* dp_launches, int64_t* dp_matchings) {
+  g_err.clear();
+  if (!ctx) return fail(STM_EINVAL, "null context");
+  STM_HIP(hipSetDevice(ctx->device));
+  double total = 0.0;
+  for (size_t q = 0; q + 1 < ctx->prof_used; q += 2) {
+    STM_HIP(hipEventSynchronize(ctx->prof_ev[q + 1]));
+    float ms = 0.f;
+    STM_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[q], ctx->prof_ev[q + 1]));
+    total += ms;
+  }
+  if (dp_ms) *dp_ms = total;
+  if (dp_launches) *dp_launches = static_cast<int64_t>(ctx->prof_used / 2);
+  if (dp_matchings) *dp_matchings = ctx->prof_matchings;
+  return STM_OK;
+}
+
+}  // extern "C"

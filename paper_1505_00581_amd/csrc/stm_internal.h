@@ -1,0 +1,152 @@
+// Internal declarations shared by the HIP sources of libstm.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stm {
+
+// Device view of one model and one scene.  Scene nodes are sorted by frame;
+// fstart[f] is the first node of frame f (the paper's minnode(f), Section
+// 3.4), fstart[F] = S.
+struct SceneView {
+  const float2* xy;
+  const int32_t* t;
+  const float* desc;
+  const int32_t* fstart;
+  int32_t S, F, dim;
+};
+
+struct ModelView {
+  const float2* xy;
+  const int32_t* t;
+  const float* desc;
+  int32_t M;
+};
+
+struct SearchParams {
+  int32_t T, W, K, kdensity;
+};
+
+// Candidate list of one model point at one offset, as two ascending node
+// ranges: [s1, s1 + k1) then [s2, s2 + k2), with s1 + k1 <= s2.
+struct CandRange {
+  int32_t s1, k1, s2, k2;
+};
+
+__device__ __forceinline__ int32_t fs_at(const int32_t* __restrict__ fstart, int32_t F, int32_t f) {
+  f = f < 0 ? 0 : (f > F ? F : f);
+  return fstart[f];
+}
+
+// Per-point cap from the local density: rho = nodes in frames f0-1..f0+1,
+// K = clamp(floor((56 rho - 1170) / 60), 8, 64) (8 + 56 (rho - 30) / 60 rounded
+// half up), never above k_max.
+__device__ __forceinline__ int32_t density_cap(const int32_t* __restrict__ fstart, int32_t F,
+                                               int32_t f0, int32_t kmax) {
+  int32_t rho = fs_at(fstart, F, f0 + 2) - fs_at(fstart, F, f0 - 1);
+  int32_t num = 56 * rho - 1170;
+  int32_t k = num >= 0 ? num / 60 : -((-num + 59) / 60);
+  k = k < 8 ? 8 : (k > 64 ? 64 : k);
+  return k < kmax ? k : kmax;
+}
+
+// The first K nodes within W frames of frame f0, ordered by (|frame - f0|,
+// node id), returned in ascending node order.  Frames are visited in the
+// order f0, f0-1, f0+1, f0-2, f0+2, ...: whole frames are taken while they fit,
+// the first frame that does not fit contributes its lowest node ids.  The
+// whole frames form one contiguous frame interval, so the kept set is at most
+// two contiguous node ranges.
+__device__ __forceinline__ CandRange cand_range(const int32_t* __restrict__ fstart, int32_t F,
+                                                int32_t f0, int32_t W, int32_t K) {
+  int32_t taken = 0, lo_f = f0, hi_f = f0 - 1;
+  CandRange r;
+  for (int32_t step = 0; step <= 2 * W; ++step) {
+    const int32_t d = step == 0 ? 0 : ((step & 1) ? -((step + 1) >> 1) : (step >> 1));
+    const int32_t f = f0 + d;
+    const int32_t cnt = (f >= 0 && f < F) ? fstart[f + 1] - fstart[f] : 0;
+    if (taken + cnt <= K) {
+      taken += cnt;
+      if (d <= 0) lo_f = f;
+      if (d >= 0) hi_f = f;
+    } else {
+      const int32_t kp = K - taken;
+      const int32_t s = fstart[f];
+      const int32_t a = fs_at(fstart, F, lo_f), b = fs_at(fstart, F, hi_f + 1);
+      if (d < 0) {
+        r.s1 = s; r.k1 = kp; r.s2 = a; r.k2 = b - a;
+      } else {
+        r.s1 = a; r.k1 = b - a; r.s2 = s; r.k2 = kp;
+      }
+      return r;
+    }
+  }
+  const int32_t a = fs_at(fstart, F, lo_f), b = fs_at(fstart, F, hi_f + 1);
+  r.s1 = a; r.k1 = b - a; r.s2 = b; r.k2 = 0;
+  return r;
+}
+
+__device__ __forceinline__ CandRange point_candidates(const int32_t* __restrict__ fstart, int32_t F,
+                                                      int32_t f0, const SearchParams& sp) {
+  const int32_t K = sp.kdensity ? density_cap(fstart, F, f0, sp.K) : sp.K;
+  return cand_range(fstart, F, f0, sp.W, K);
+}
+
+__device__ __forceinline__ int32_t cand_node(const CandRange& c, int32_t a) {
+  return a < c.k1 ? c.s1 + a : c.s2 + (a - c.k1);
+}
+
+// Causality (strictly increasing scene frames, Eq. 7) and temporal closeness
+// (consecutive scene frames less than T apart, Eq. 8; T <= 0: no limit).
+__device__ __forceinline__ bool admissible(int32_t tp_prev, int32_t tp_cur, int32_t T) {
+  return tp_prev < tp_cur && (T <= 0 || tp_cur - tp_prev < T);
+}
+
+// Oriented angle at vertex b of the triangle (a, b, c), from ray b->a to ray
+// b->c, in FP64; 0 when a side has zero length (Eq. 6).
+__device__ __forceinline__ double ang64(double ax, double ay, double bx, double by, double cx,
+                                        double cy) {
+  const double ux = ax - bx, uy = ay - by, vx = cx - bx, vy = cy - by;
+  if ((ux == 0.0 && uy == 0.0) || (vx == 0.0 && vy == 0.0)) return 0.0;
+  return atan2(ux * vy - uy * vx, ux * vx + uy * vy);
+}
+
+// ---- launchers (return hipError_t of the launch) ---------------------------
+
+// Validation of inputs: flags bits (see api.cpp) are OR-ed into out[0]; the
+// model span t[M-1] - t[0] is written to out[1] by one thread.
+hipError_t launch_validate(const ModelView& m, const SceneView& s, int32_t* out, hipStream_t st);
+hipError_t launch_fstart(const int32_t* t, int32_t S, int32_t F, int32_t* fstart, hipStream_t st);
+hipError_t launch_candidates(const ModelView& m, const SceneView& s, const SearchParams& sp,
+                             int32_t tau0, int32_t n_tau, int32_t* cand, int32_t* count,
+                             hipStream_t st);
+hipError_t launch_unary_f32(const ModelView& m, const SceneView& s, float* U, hipStream_t st);
+hipError_t launch_count(const ModelView& m, const SceneView& s, const SearchParams& sp,
+                        int32_t tau0, int32_t n_tau, unsigned long long* counts, hipStream_t st);
+hipError_t launch_model_angles(const ModelView& m, float2* theta, hipStream_t st);
+
+struct DPLaunch {
+  ModelView m;
+  SceneView s;
+  SearchParams sp;
+  const float* U;       // [M][S] raw distances
+  const float2* theta;  // [M] model angles (mid, end) of the triangle ending at i
+  float lambda1, lambda2, w;  // w = lambda2 * lambda3
+  int32_t tau0, n_tau;
+  uint8_t* bp;          // [n_tau][M-2][K][K]
+  float* e32;           // [n_tau]
+  int2* last2;          // [n_tau]
+  int32_t* degen;       // [n_tau], zeroed before the launch
+};
+// The fast variant over every matching of the launch, then the variant for
+// degenerate triangles, which only recomputes the matchings flagged by the first.
+hipError_t launch_dp_fast(const DPLaunch& a, hipStream_t st);
+hipError_t launch_dp_degenerate(const DPLaunch& a, hipStream_t st);
+
+hipError_t launch_backtrack(const DPLaunch& a, int32_t* assign, hipStream_t st);
+
+hipError_t launch_rescore(const ModelView& m, const SceneView& s, int32_t T, double lambda1,
+                          double lambda2, double lambda3, const int32_t* assign, int32_t n_tau,
+                          double* e64, double* eu64, hipStream_t st);
+
+}  // namespace stm

@@ -1,0 +1,320 @@
+"""Parity of the HIP path (through the C ABI of libstm.so) with the FP64 CPU
+oracle, element by element on seeded inputs.
+
+Tolerances.  Energies: 1e-5 relative, with an absolute floor of 1e-4 for
+energies near 0 (each FP32 direction carries up to ~2.4e-7 rad of rounding,
+so a chain of up to ~150 triangles with lambda2 * lambda3 = 1 can accumulate
+~1e-4 even when the exact energy is 0).  Assignments: identical, or, where
+several optima exist or the optimum's margin is below the tolerance, the
+oracle's FP64 energy of the GPU assignment must equal the optimum within the
+same tolerance.  The GPU's FP64 re-score must equal the oracle's literal
+energy of the same assignment to 1e-9.  Candidate lists and work counts are
+integers: bit-exact.
+"""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1505_00581_amd as stm
+from paper_1505_00581_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+ATOL = 1e-4
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = stm.Context(0)
+    yield c
+    c.close()
+
+
+def _np(x):
+    if hasattr(x, "cpu"):
+        return x.cpu().numpy()
+    return np.asarray(x)
+
+
+def check(m, s, p, res, ora, rows=None):
+    """Compare GPU results (rows of `res`, default all) with oracle results."""
+    e32 = _np(res["energy32"]).astype(np.float64)
+    e64 = _np(res["energy64"])
+    eu64 = _np(res["energy_u64"])
+    A = _np(res["assign"])
+    if rows is not None:
+        e32, e64, eu64, A = e32[rows], e64[rows], eu64[rows], A[rows]
+    E, Z = ora["energy"], ora["assign"]
+    inf_g, inf_o = ~np.isfinite(e32), ~np.isfinite(E)
+    assert (inf_g == inf_o).all(), (np.nonzero(inf_g != inf_o)[0][:10])
+    assert (A[inf_g] == -1).all()
+    assert (~np.isfinite(e64[inf_g])).all()
+    fin = ~inf_o
+    if not fin.any():
+        return dict(n=len(E), feasible=0, agree=1.0, max_rel=0.0)
+    tol = np.maximum(RTOL * np.abs(E[fin]), ATOL)
+    err = np.abs(e32[fin] - E[fin])
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, f"energy mismatch at {bad[:5]}: gpu {e32[fin][bad[:5]]} oracle {E[fin][bad[:5]]}"
+    Af, Zf = A[fin], Z[fin]
+    same = (Af == Zf).all(1)
+    eg, eu = oracle.energies(m, s, p, Af)
+    if not same.all():
+        d = np.abs(eg[~same] - E[fin][~same])
+        assert (d <= tol[~same]).all(), f"different assignment with energy gap {d.max()}"
+    assert np.allclose(e64[fin], eg, rtol=1e-9, atol=1e-9), np.abs(e64[fin] - eg).max()
+    assert np.allclose(eu64[fin], eu, rtol=1e-9, atol=1e-9)
+    return dict(n=len(E), feasible=int(fin.sum()), agree=float(same.mean()),
+                max_rel=float((err / np.maximum(np.abs(E[fin]), 1e-30)).max()))
+
+
+# ---------------------------------------------------------------------------
+# The plain exact DP workload: 1 model (M=20) vs a 100-frame scene, K=16.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_config1_all_offsets(ctx, seed):
+    w = synth.config1(seed)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    say(f"[config1 seed={seed}] M={m.n} S={s.n} K={p.k_max}")
+    res = ctx.match(m, s, p)
+    ora = oracle.match(m, s, p)
+    st = check(m, s, p, res, ora)
+    say(f"  {st}")
+    assert st["feasible"] > 0
+
+
+def test_config1_device_pointers_equal_host_pointers(ctx):
+    import torch
+    w = synth.config1(7)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    host = ctx.match(m, s, p)
+    dm, ds = stm.DevicePoints.from_host(m), stm.DevicePoints.from_host(s)
+    dev = ctx.match(dm, ds, p)
+    torch.cuda.synchronize()
+    for k in ("energy32", "energy64", "energy_u64", "assign"):
+        np.testing.assert_array_equal(_np(dev[k]), host[k])
+
+
+def test_deterministic(ctx):
+    w = synth.config1(8)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    r1, r2 = ctx.match(m, s, p), ctx.match(m, s, p)
+    for k in ("energy32", "energy64", "assign"):
+        np.testing.assert_array_equal(r1[k], r2[k])
+
+
+# ---------------------------------------------------------------------------
+# The steps of the path.
+# ---------------------------------------------------------------------------
+
+def test_candidates_bit_exact(ctx):
+    for w, taus in [(synth.config1(0), None), (synth.config2(0, n_models=2), [0, 1, 700, 1350])]:
+        p = w.params
+        for m in w.models:
+            s = w.scenes[0]
+            b, e = ctx.offsets(m, s)
+            sel = range(b, e) if taus is None else [t for t in taus if t < e]
+            cand, cnt = ctx.candidates(m, s, p)
+            for tau in sel:
+                for i in range(m.n):
+                    want = oracle.candidate_list(m, s, p, tau, i)
+                    assert cnt[tau, i] == want.size
+                    assert (cand[tau, i, :want.size] == want).all()
+                    assert (cand[tau, i, want.size:] == -1).all()
+
+
+def test_unary_table(ctx):
+    from scipy.spatial.distance import cdist
+    w = synth.config1(1)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    U = ctx.unary(m, s, p)
+    ref = cdist(m.desc.astype(np.float64), s.desc.astype(np.float64))
+    np.testing.assert_allclose(U, ref, rtol=2e-6, atol=1e-7)
+
+
+def test_work_counts_equal_oracle(ctx):
+    for seed in range(3):
+        w = synth.config1(seed)
+        m, s, p = w.models[0], w.scenes[0], w.params
+        assert ctx.count_work(m, s, p) == oracle.match(m, s, p)["counts"]
+    w = synth.tiny(5)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    assert ctx.count_work(m, s, p) == oracle.match(m, s, p)["counts"]
+
+
+# ---------------------------------------------------------------------------
+# Edge cases: tiny random inputs (brute-force-checked oracle), ragged caps,
+# infeasible offsets, T = infinity, tight T, degenerate triangles.
+# ---------------------------------------------------------------------------
+
+def test_tiny_cases(ctx):
+    n_inf = n = 0
+    for seed in range(120):
+        T = [4, 2, 0, 3][seed % 4]
+        w = synth.tiny(seed, T=T)
+        m, s, p = w.models[0], w.scenes[0], w.params
+        b, e = ctx.offsets(m, s)
+        if e == 0:
+            continue
+        res = ctx.match(m, s, p)
+        st = check(m, s, p, res, oracle.match(m, s, p))
+        n += st["n"]
+        n_inf += st["n"] - st["feasible"]
+    say(f"  tiny: {n} offsets, {n_inf} infeasible")
+    assert n > 200 and n_inf > 10
+
+
+def test_degenerate_coincident_points(ctx):
+    hits = 0
+    for seed in range(60):
+        w = synth.tiny(1000 + seed, int_coords=True, max_per_frame=3)
+        w.scenes[0].xy[:] = np.round(w.scenes[0].xy / 8.0) * 8.0
+        w.models[0].xy[:] = np.round(w.models[0].xy / 8.0) * 8.0
+        m, s, p = w.models[0], w.scenes[0], w.params
+        if ctx.offsets(m, s)[1] == 0:
+            continue
+        res = ctx.match(m, s, p)
+        st = check(m, s, p, res, oracle.match(m, s, p))
+        hits += st["feasible"]
+    assert hits > 20
+
+
+def test_all_points_coincide_in_space(ctx):
+    # every scene point at the same pixel: all scene angles are 0
+    rng = np.random.Generator(np.random.PCG64(4))
+    m = synth.make_model(rng, 6, 40, 40, 10, frame_hi=8)
+    counts = rng.integers(1, 4, size=14)
+    xy, t, d = synth.clutter(rng, counts, 40, 40, m.dim)
+    xy[:] = 17.0
+    s = synth.assemble_scene([xy], [t], [d], 14)
+    p = synth.Params(window=1, k_max=8, T=6)
+    check(m, s, p, ctx.match(m, s, p), oracle.match(m, s, p))
+
+
+@pytest.mark.parametrize("K", [1, 2, 5, 37, 63, 64])
+def test_ragged_caps(ctx, K):
+    w = synth.config1(3)
+    m, s = w.models[0], w.scenes[0]
+    p = dataclasses.replace(w.params, k_max=K, window=3)
+    taus = np.arange(0, 71, 3)
+    res = ctx.match(m, s, p)
+    check(m, s, p, res, oracle.match(m, s, p, taus=taus), rows=taus)
+
+
+@pytest.mark.parametrize("T", [0, -5, 1, 2, 3])
+def test_closeness_variants(ctx, T):
+    w = synth.config1(5)
+    m, s = w.models[0], w.scenes[0]
+    p = dataclasses.replace(w.params, T=T)
+    res = ctx.match(m, s, p)
+    st = check(m, s, p, res, oracle.match(m, s, p))
+    if T == 1:  # strict order and gaps < 1 frame cannot both hold
+        assert st["feasible"] == 0
+
+
+def test_empty_windows_are_infeasible(ctx):
+    # a scene with a gap of empty frames: offsets whose windows fall in the gap
+    w = synth.config1(6)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    keep = (s.t < 40) | (s.t >= 60)
+    s2 = synth.Points(np.ascontiguousarray(s.xy[keep]), np.ascontiguousarray(s.t[keep]),
+                      np.ascontiguousarray(s.desc[keep]), s.n_frames)
+    res = ctx.match(m, s2, p)
+    st = check(m, s2, p, res, oracle.match(m, s2, p))
+    assert st["feasible"] < st["n"]
+
+
+def test_density_caps(ctx):
+    w = synth.config3(0, n_models=3, n_scenes=1)
+    s = w.scenes[0]
+    p = w.params
+    for m in w.models:
+        b, e = ctx.offsets(m, s)
+        if e == 0:
+            continue
+        taus = np.unique(np.linspace(0, e - 1, 5).astype(np.int32))
+        res = ctx.match(m, s, p)
+        check(m, s, p, res, oracle.match(m, s, p, taus=taus), rows=taus)
+
+
+def test_zero_energy_planted_copy(ctx):
+    rng = np.random.Generator(np.random.PCG64(12))
+    m = synth.make_model(rng, 30, 160, 120, 10)
+    nf = 80
+    cxy, ct, cd = synth.clutter(rng, np.full(nf, 4), 160, 120)
+    tau0 = 17
+    a = 0.4
+    R = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+    copy = ((m.xy.astype(np.float64) - 80) @ R.T * 1.05 + 80).astype(np.float32)
+    s = synth.assemble_scene([cxy, copy], [ct, (tau0 + m.t - m.t[0]).astype(np.int32)],
+                             [cd, m.desc.copy()], nf)
+    p = synth.Params(window=2, k_max=16)
+    res = ctx.match(m, s, p, tau0, tau0 + 1)
+    assert abs(float(res["energy32"][0])) < ATOL
+    ora = oracle.match(m, s, p, taus=[tau0])
+    assert ora["energy"][0] < 1e-5
+    check(m, s, p, res, ora)
+
+
+def test_long_model_max_k(ctx):
+    # M = 150 (the largest model size of the batched workload) at K = 64
+    rng = np.random.Generator(np.random.PCG64(21))
+    m = synth.make_model(rng, 150, 320, 240, 10)
+    span = int(m.t[-1])
+    nf = span + 40
+    s, _ = synth.make_scene(rng, [m], nf, np.full(nf, 20), 320, 240, 1)
+    p = synth.Params(window=3, k_max=64)
+    res = ctx.match(m, s, p)
+    taus = np.array([0, 13, 27, 39])
+    st = check(m, s, p, res, oracle.match(m, s, p, taus=taus), rows=taus)
+    say(f"  M=150: {st}")
+
+
+# ---------------------------------------------------------------------------
+# The realistic single-scene workload at full size: 10 models with M in
+# 50..100 against a 1500-frame scene (20 points per frame), K=64, every offset.
+# Sampled offsets are compared with the oracle one by one; properties that
+# hold at any size are checked at every offset.
+# ---------------------------------------------------------------------------
+
+def test_config2_full_size(ctx):
+    import torch
+    w = synth.config2(0)
+    s = w.scenes[0]
+    p = w.params
+    ds = stm.DevicePoints.from_host(s)
+    total = 0
+    for mi, m in enumerate(w.models):
+        dm = stm.DevicePoints.from_host(m)
+        res = ctx.match(dm, ds, p)
+        torch.cuda.synchronize()
+        e32 = _np(res["energy32"]).astype(np.float64)
+        e64 = _np(res["energy64"])
+        A = _np(res["assign"])
+        fin = np.isfinite(e32)
+        total += e32.size
+        # every offset: the FP64 re-score of the returned assignment equals the
+        # FP32 optimum, and every assignment is admissible
+        tol = np.maximum(RTOL * np.abs(e64[fin]), ATOL)
+        assert (np.abs(e32[fin] - e64[fin]) <= tol).all()
+        tz = s.t[A[fin]]
+        assert (np.diff(tz, axis=1) > 0).all() and (np.diff(tz, axis=1) < p.T).all()
+        # sampled offsets against the oracle
+        taus = np.unique(np.concatenate([[0, e32.size - 1],
+                                         np.linspace(1, e32.size - 2, 4).astype(int)]))
+        planted = [t for (mm, _, t) in w.planted if mm == mi][:2]
+        taus = np.unique(np.concatenate([taus, planted])).astype(np.int32)
+        ora = oracle.match(m, s, p, taus=taus)
+        st = check(m, s, p, res, ora, rows=taus)
+        say(f"  model {mi} M={m.n}: n_tau={e32.size} {st}")
+    assert total > 13000
