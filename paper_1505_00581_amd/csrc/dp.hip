@@ -23,14 +23,16 @@
 // adds, |wrap| via pi - |pi - |x|| (valid for |x| <= 2 pi), a square root,
 // fused multiply-adds and a compare.
 //
-// Layout.  Lanes of a 64-wide wavefront are the candidates a_i of the current
-// point; the waves of the workgroup take the rows a_{i-1} round-robin.  The
-// admissible predecessors a_{i-2} of a row form one contiguous index range
-// (candidates are sorted by frame), found with two ballots, so the inner loop
-// has wave-uniform bounds (the paper's loop bounds of Section 3.4).  Per step
-// the LDS holds the previous V column pairs with their directions and the
-// (a_{i-2}, a_i) direction table; the new cells stay in registers until every
-// wave has finished reading, then replace the old ones.
+// Layout.  Candidates are sorted by frame, so the rows a_{i-1} of one frame
+// share one contiguous range of admissible columns a_i and one contiguous
+// range of admissible predecessors a_{i-2} (the paper's loop bounds of
+// Section 3.4).  Each step builds a schedule of 64-cell chunks over the
+// admissible cells only, frame group by frame group; a lane takes one cell of
+// a chunk, the waves take chunks round-robin, and every lane of a chunk shares
+// the predecessor loop bounds.  Per step the LDS holds the previous V cells
+// with their directions and the (a_{i-2}, a_i) direction table; the new cells
+// stay in registers until every wave has finished reading, then replace the
+// old ones.  Only admissible cells are ever read back.
 //
 // Degenerate triangles.  A zero-length side gives a scene angle of 0 in the
 // definition, which the direction form does not reproduce.  The fast variant
@@ -54,6 +56,91 @@ __device__ __forceinline__ float wrap_pi(float x) { return fmaf(-kTwoPi, rintf(x
 // |wrap(x)| for |x| <= 2 pi.
 __device__ __forceinline__ float abs_wrap(float x) { return kPi - fabsf(kPi - fabsf(x)); }
 
+// A chunk of the cells of one step: the admissible cells (a_{i-1}, a_i) of the
+// rows r0.. r0+nr-1 of one frame group, flattened row-major over their common
+// column range [clo, clo + nc); the chunk covers flat cells [e0, e0 + 64).  All
+// rows of the group share the predecessor range [lo, hi).
+struct Chunk {
+  int r0, clo, nc, e0, lo, hi, ncell;
+};
+
+__device__ __forceinline__ uint2 pack_chunk(int r0, int clo, int nc, int e0, int lo, int hi, int ncell) {
+  return make_uint2(static_cast<uint32_t>(r0) | (static_cast<uint32_t>(clo) << 6) |
+                        (static_cast<uint32_t>(nc) << 12) | (static_cast<uint32_t>(e0) << 19),
+                    static_cast<uint32_t>(lo) | (static_cast<uint32_t>(hi) << 7) |
+                        (static_cast<uint32_t>(ncell) << 14));
+}
+
+__device__ __forceinline__ Chunk unpack_chunk(uint2 d) {
+  Chunk c;
+  c.r0 = d.x & 63;
+  c.clo = (d.x >> 6) & 63;
+  c.nc = (d.x >> 12) & 127;
+  c.e0 = d.x >> 19;
+  c.lo = d.y & 127;
+  c.hi = (d.y >> 7) & 127;
+  c.ncell = d.y >> 14;
+  return c;
+}
+
+// Number of entries < x in the ascending list a[0..n).
+__device__ __forceinline__ int count_lt(const int32_t* a, int n, int x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Cell of lane `lane` in chunk c: row r and column a; false past the last cell.
+__device__ __forceinline__ bool chunk_cell(const Chunk& c, int lane, int& r, int& a) {
+  const int e = c.e0 + lane;
+  // e < 4096 and nc <= 64: (e + 1/2) / nc stays >= 1/128 away from an integer,
+  // far above the float rounding, so the truncation is the exact quotient.
+  const int q = static_cast<int>((static_cast<float>(e) + 0.5f) * __builtin_amdgcn_rcpf(static_cast<float>(c.nc)));
+  r = c.r0 + q;
+  a = c.clo + (e - q * c.nc);
+  return e < c.ncell;
+}
+
+// Builds the chunk schedule of one step, run by one wave (lane = row).  Rows
+// are the candidates of point i-1 (frames trow, ascending), columns those of
+// point i (tcol), predecessors those of point i-2 (tprev, or none for the
+// first pair).  The rows of one frame f share the admissible columns (frames in
+// (f, f + T)) and predecessors (frames in (f - T, f)).  Each group gives
+// ceil(rows * columns / 64) <= rows chunks, so a step has at most K chunks.
+__device__ void build_schedule(const int32_t* trow, int nrow, const int32_t* tcol, int ncol,
+                               const int32_t* tprev, int nprev, int T, uint2* out, int32_t* nout,
+                               int lane) {
+  const int f = lane < nrow ? trow[lane] : 0;
+  const bool start = lane < nrow && (lane == 0 || trow[lane - 1] != f);
+  const unsigned long long starts = __ballot(start);
+  int nchunk = 0, nr = 0, nc = 0, clo = 0, lo = 0, hi = 0;
+  if (start) {
+    const unsigned long long later = starts & ~((2ull << lane) - 1ull);
+    const int next = later ? __ffsll(static_cast<long long>(later)) - 1 : nrow;
+    nr = next - lane;
+    clo = count_lt(tcol, ncol, f + 1);
+    const int chi = T > 0 ? count_lt(tcol, ncol, f > 0x7fffffff - T ? 0x7fffffff : f + T) : ncol;
+    nc = chi > clo ? chi - clo : 0;
+    if (tprev) {
+      hi = count_lt(tprev, nprev, f);
+      lo = T > 0 ? count_lt(tprev, nprev, f - T + 1) : 0;
+    }
+    nchunk = (nr * nc + 63) >> 6;
+  }
+  int incl = nchunk;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  if (start)
+    for (int c = 0; c < nchunk; ++c) out[incl - nchunk + c] = pack_chunk(lane, clo, nc, c * 64, lo, hi, nr * nc);
+  const int total = __shfl(incl, 63);
+  if (lane == 0) *nout = total;
+}
+
 template <int NW>
 struct DPShared {
   float2 va[KL * KL];   // [a_{i-2}][a_{i-1}]: (V_{i-1}, -phi(z_{i-2} -> z_{i-1}))
@@ -61,6 +148,8 @@ struct DPShared {
   float2 cxy[4][KL];    // candidate ring: coordinates,
   int32_t ctt[4][KL];   //   frames,
   float cu[4][KL];      //   l1 * U
+  uint2 sched[2][KL];   // chunk schedules of the current and the previous step
+  int32_t nch[2];
   int32_t ck[4];        //   list lengths
   int32_t flag;         // coincident points seen (fast variant)
   float red_v[NW];
@@ -70,7 +159,7 @@ struct DPShared {
 template <int NW, bool DEGEN>
 __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   __shared__ DPShared<NW> sh;
-  constexpr int RPW = KL / NW;  // rows per wave
+  constexpr int RPW = KL / NW;  // chunk slots per wave (a step has <= 64 chunks)
   const int tl = blockIdx.x;
   if (DEGEN && a.degen[tl] == 0) return;
   const int tau = a.tau0 + tl;
@@ -83,6 +172,7 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   const int tm0 = a.m.t[0];
   const float INF = __builtin_inff();
   const float QNAN = __builtin_nanf("");
+  constexpr int kBuilder = NW - 1;  // wave that builds the schedules
 
   auto load_slot = [&](int j) {
     if (wv == 0) {
@@ -104,6 +194,9 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   load_slot(1);
   load_slot(2);
   __syncthreads();
+  if (wv == kBuilder)
+    build_schedule(sh.ctt[0], sh.ck[0], sh.ctt[1], sh.ck[1], nullptr, 0, T, sh.sched[1], &sh.nch[1], lane);
+  __syncthreads();
 
   float vr[RPW], ar[RPW];
 #pragma unroll
@@ -111,24 +204,23 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
 
   // ---- the first pair (points 0, 1) ------------------------------------------
   {
-    const int K0 = sh.ck[0], K1 = sh.ck[1];
-    const bool valid_a = lane < K1;
-    const int tp = valid_a ? sh.ctt[1][lane] : 0;
-    const float2 xa = valid_a ? sh.cxy[1][lane] : make_float2(0.f, 0.f);
-    const float ua = valid_a ? sh.cu[1][lane] : 0.f;
     const int dtm = a.m.t[1] - a.m.t[0];
+    const int nch = sh.nch[1];
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
-      const int r = wv + NW * s;
-      if (r < K0) {
-        const int tr = sh.ctt[0][r];
-        const float2 xr = sh.cxy[0][r];
-        const bool adm = valid_a && admissible(tr, tp, T);
+      const int ch = wv + NW * s;
+      if (ch < nch) {
+        const Chunk c = unpack_chunk(sh.sched[1][ch]);
+        int r, col;
+        const bool valid = chunk_cell(c, lane, r, col);
+        if (!valid) { r = c.r0; col = c.clo; }
+        const int tr = sh.ctt[0][r], tp = sh.ctt[1][col];
+        const float2 xr = sh.cxy[0][r], xa = sh.cxy[1][col];
         const bool same = xa.x == xr.x && xa.y == xr.y;
         const float phi = same ? 0.f : atan2f(xa.y - xr.y, xa.x - xr.x);
-        if (!DEGEN && same && adm) sh.flag = 1;
+        if (!DEGEN && same && valid) sh.flag = 1;
         const float q = a.lambda2 * fabsf(static_cast<float>(dtm - (tp - tr)));
-        vr[s] = adm ? (sh.cu[0][r] + ua) + q : INF;
+        vr[s] = (sh.cu[0][r] + sh.cu[1][col]) + q;
         ar[s] = (DEGEN && same) ? QNAN : -phi;
       }
     }
@@ -138,14 +230,24 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   for (int i = 2; i < M; ++i) {
     const int s2 = (i - 2) & 3, s1 = (i - 1) & 3, s0 = i & 3;
     const int Kq = sh.ck[s2], Kp = sh.ck[s1], Kn = sh.ck[s0];
+    const int cur = i & 1, prv = cur ^ 1;
 
-    // Phase 1: publish the previous cells, build the (a_{i-2}, a_i) direction
-    // table, prefetch the next candidate list.
+    // Phase 1: publish the previous step's cells, build this step's schedule and
+    // (a_{i-2}, a_i) direction table, prefetch the next candidate list.
+    {
+      const int nprev = sh.nch[prv];
 #pragma unroll
-    for (int s = 0; s < RPW; ++s) {
-      const int k = wv + NW * s;
-      if (k < Kq && lane < Kp) sh.va[k * KL + lane] = make_float2(vr[s], ar[s]);
+      for (int s = 0; s < RPW; ++s) {
+        const int ch = wv + NW * s;
+        if (ch < nprev) {
+          const Chunk c = unpack_chunk(sh.sched[prv][ch]);
+          int r, col;
+          if (chunk_cell(c, lane, r, col)) sh.va[r * KL + col] = make_float2(vr[s], ar[s]);
+        }
+      }
     }
+    if (wv == kBuilder)
+      build_schedule(sh.ctt[s1], Kp, sh.ctt[s0], Kn, sh.ctt[s2], Kq, T, sh.sched[cur], &sh.nch[cur], lane);
     for (int e = threadIdx.x; e < Kq * KL; e += NW * 64) {
       const int k = e >> 6, c = e & 63;
       if (c < Kn) {
@@ -160,76 +262,80 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
     if (i + 1 < M) load_slot(i + 1);
     __syncthreads();
 
-    // Phase 2: the relaxations of every cell (a_{i-1} = row, a_i = lane).
+    // Phase 2: the relaxations of every admissible cell, chunk by chunk.
     const float2 th = a.theta[i];
     const int dtm = a.m.t[i] - a.m.t[i - 1];
     const float qw = a.lambda2 * (i <= M - 2 ? 2.f : 1.f);
-    const bool valid_a = lane < Kn;
-    const int tp = valid_a ? sh.ctt[s0][lane] : 0;
-    const float2 xa = valid_a ? sh.cxy[s0][lane] : make_float2(0.f, 0.f);
-    const float ua = valid_a ? sh.cu[s0][lane] : 0.f;
-    const int tk_lane = lane < Kq ? sh.ctt[s2][lane] : 0x7fffffff;
-    uint8_t* bprow = a.bp + ((long long)tl * (M - 2) + (i - 2)) * Kc * Kc;
+    uint8_t* bpstep = a.bp + ((long long)tl * (M - 2) + (i - 2)) * Kc * Kc;
     const float w = a.w;
+    const int nch = sh.nch[cur];
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
-      const int r = wv + NW * s;
+      const int ch = wv + NW * s;
       float vnew = INF, anew = 0.f;
-      if (r < Kp) {
-        const int tr = sh.ctt[s1][r];
-        const float2 xr = sh.cxy[s1][r];
-        const bool adm = valid_a && admissible(tr, tp, T);
+      if (ch < nch) {
+        const Chunk c = unpack_chunk(sh.sched[cur][ch]);
+        int r, col;
+        const bool valid = chunk_cell(c, lane, r, col);
+        if (!valid) { r = c.r0; col = c.clo; }
+        const int tr = sh.ctt[s1][r], tp = sh.ctt[s0][col];
+        const float2 xr = sh.cxy[s1][r], xa = sh.cxy[s0][col];
         const bool same = xa.x == xr.x && xa.y == xr.y;
         const float phi = same ? 0.f : atan2f(xa.y - xr.y, xa.x - xr.x);
-        if (!DEGEN && same && adm) sh.flag = 1;
-        const int hi = __popcll(__ballot(tk_lane < tr));
-        const int lo = T > 0 ? __popcll(__ballot(tk_lane <= tr - T)) : 0;
+        if (!DEGEN && same && valid) sh.flag = 1;
         float best = INF;
         int arg = 0;
-        if (adm) {
+        if (valid) {
           const float bm = wrap_pi(th.x - kPi + phi), be = wrap_pi(th.y + phi);
           const float2* vcol = sh.va + r;
-          const float* ccol = sh.ct + lane;
+          const float* ccol = sh.ct + col;
 #pragma unroll 4
-          for (int k = lo; k < hi; ++k) {
+          for (int k = c.lo; k < c.hi; ++k) {
             const float2 v = vcol[k * KL];
-            const float c = ccol[k * KL];
+            const float cc = ccol[k * KL];
             float x1, x2;
             if (DEGEN) {
               x1 = (same || isnan(v.y)) ? th.x : v.y + bm;
-              x2 = (same || isnan(c)) ? th.y : c + be;
+              x2 = (same || isnan(cc)) ? th.y : cc + be;
             } else {
               x1 = v.y + bm;
-              x2 = c + be;
+              x2 = cc + be;
             }
             const float z1 = abs_wrap(x1), z2 = abs_wrap(x2);
             const float d = __builtin_amdgcn_sqrtf(fmaf(z2, z2, z1 * z1));
             const float tot = fmaf(w, d, v.x);
             if (tot < best) { best = tot; arg = k; }
           }
-          const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
-          vnew = (ua + q) + best;
+          bpstep[r * Kc + col] = static_cast<uint8_t>(arg);
         }
+        const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
+        vnew = (sh.cu[s0][col] + q) + best;
         anew = (DEGEN && same) ? QNAN : -phi;
-        if (valid_a) bprow[r * Kc + lane] = static_cast<uint8_t>(arg);
       }
       vr[s] = vnew;
       ar[s] = anew;
     }
     __syncthreads();
+    (void)Kp;
+    (void)Kn;
   }
 
   // ---- optimum: first row-major minimum of V_{M-1}(a_{M-2}, a_{M-1}) ------------
   {
-    const int Kq = sh.ck[(M - 2) & 3], Kn = sh.ck[(M - 1) & 3];
+    const int last = (M - 1) & 1;
+    const int nch = sh.nch[last];
     float bv = INF;
     int bi = 0x7fffffff;
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
-      const int r = wv + NW * s;
-      if (r < Kq && lane < Kn) {
-        const int idx = r * KL + lane;
-        if (vr[s] < bv || (vr[s] == bv && idx < bi)) { bv = vr[s]; bi = idx; }
+      const int ch = wv + NW * s;
+      if (ch < nch) {
+        const Chunk c = unpack_chunk(sh.sched[last][ch]);
+        int r, col;
+        if (chunk_cell(c, lane, r, col)) {
+          const int idx = r * KL + col;
+          if (vr[s] < bv || (vr[s] == bv && idx < bi)) { bv = vr[s]; bi = idx; }
+        }
       }
     }
     for (int off = 32; off > 0; off >>= 1) {
