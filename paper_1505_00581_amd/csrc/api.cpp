@@ -37,11 +37,11 @@ struct DevBuf {
 struct stm_ctx {
   int device = 0;
   // scratch
-  DevBuf fstart, theta, U, bp, last2, degen, val, counts;
+  DevBuf fstart, theta, U, vt, last2, degen, val, counts;
   // staging for host-pointer calls
   DevBuf mxy, mt, mdesc, sxy, st, sdesc;
   DevBuf o_e32, o_e64, o_eu, o_assign, o_cand, o_cnt;
-  size_t bp_chunk_bytes = size_t(1) << 30;  // back-pointer scratch per chunk of offsets
+  size_t vt_chunk_bytes = size_t(4) << 30;  // value-table scratch per chunk of offsets
   // kernel timing
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
@@ -218,7 +218,7 @@ void stm_destroy(stm_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&ctx->fstart, &ctx->theta, &ctx->U,     &ctx->bp,    &ctx->last2, &ctx->degen,
+  DevBuf* bufs[] = {&ctx->fstart, &ctx->theta, &ctx->U,     &ctx->vt,    &ctx->last2, &ctx->degen,
                     &ctx->val,    &ctx->counts, &ctx->mxy,  &ctx->mt,    &ctx->mdesc, &ctx->sxy,
                     &ctx->st,     &ctx->sdesc,  &ctx->o_e32, &ctx->o_e64, &ctx->o_eu, &ctx->o_assign,
                     &ctx->o_cand, &ctx->o_cnt};
@@ -290,10 +290,10 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
   if ((rc = grow(ctx, ctx->U, (size_t)M * S * sizeof(float), st))) return rc;
   STM_HIP(stm::launch_unary_f32(pr.m, pr.s, static_cast<float*>(ctx->U.p), st));
 
-  // the recursion, in chunks of offsets bounded by the back-pointer scratch
-  const size_t per_tau = (size_t)(M - 2) * K * K;
-  int chunk = static_cast<int>(std::min<size_t>(n_tau, std::max<size_t>(1, ctx->bp_chunk_bytes / per_tau)));
-  if ((rc = grow(ctx, ctx->bp, per_tau * chunk, st))) return rc;
+  // the recursion, in chunks of offsets bounded by the value-table scratch
+  const size_t per_tau = (size_t)(M - 2) * K * K * sizeof(float);
+  int chunk = static_cast<int>(std::min<size_t>(n_tau, std::max<size_t>(1, ctx->vt_chunk_bytes / per_tau)));
+  if ((rc = grow(ctx, ctx->vt, per_tau * chunk, st))) return rc;
   if ((rc = grow(ctx, ctx->last2, (size_t)chunk * sizeof(int2), st))) return rc;
   if ((rc = grow(ctx, ctx->degen, (size_t)chunk * sizeof(int32_t), st))) return rc;
   for (int c0 = 0; c0 < n_tau; c0 += chunk) {
@@ -309,7 +309,7 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
     a.w = static_cast<float>(params->lambda2 * params->lambda3);
     a.tau0 = tau_begin + c0;
     a.n_tau = nc;
-    a.bp = static_cast<uint8_t*>(ctx->bp.p);
+    a.vt = static_cast<float*>(ctx->vt.p);
     a.e32 = d_e32 + c0;
     a.last2 = static_cast<int2*>(ctx->last2.p);
     a.degen = static_cast<int32_t*>(ctx->degen.p);

@@ -2,6 +2,11 @@
 // (model, scene, offset) matching, with the triplet cost fused into the
 // minimisation; backtracking and the FP64 re-score of the result.
 //
+// The forward pass keeps only running minima: each step's cell values are
+// written to device memory, and backtracking (Eq. 12) recomputes, along the
+// optimal path only, the minimising predecessor of each step with the same
+// arithmetic as the forward pass, so ties resolve to the lowest index.
+//
 // Forward form of Eq. 10-13.  With a_i the candidate index of model point i:
 //   V_1(a_0, a_1) = l1 U_0 + l1 U_1 + Q_1(a_0, a_1)
 //   V_i(a_{i-1}, a_i) = l1 U_i(a_i) + Q_i(a_{i-1}, a_i)
@@ -9,7 +14,8 @@
 // where Q_i = l2 c_i Delta(i, i-1), +inf unless the pair is admissible (Eq. 7,
 // 8), and c_i counts the triangles holding the pair (i, i-1) (2 inside the
 // chain, 1 at its ends), so every D^t term of Eq. 4 is charged exactly once.
-// The optimum is min V_{M-1}; B_i = argmin a_{i-2} is kept for backtracking.
+// The optimum is min V_{M-1}; the argmin a_{i-2} of each step on the optimal
+// path is found again during backtracking.
 //
 // D^g from pairwise directions.  With phi(p -> q) the direction of q - p, the
 // oriented angle at b of (a, b, c) is phi(b -> c) - phi(b -> a) mod 2 pi, and
@@ -56,6 +62,41 @@ __device__ __forceinline__ float wrap_pi(float x) { return fmaf(-kTwoPi, rintf(x
 // |wrap(x)| for |x| <= 2 pi.
 __device__ __forceinline__ float abs_wrap(float x) { return kPi - fabsf(kPi - fabsf(x)); }
 
+// -phi(p -> q), the stored (negated) direction of q - p; 0 for coincident
+// points in the fast variant, NaN in the degenerate variant.
+template <bool DEGEN>
+__device__ __forceinline__ float neg_dir(float2 p, float2 q) {
+  const bool same = p.x == q.x && p.y == q.y;
+  if (DEGEN && same) return __builtin_nanf("");
+  return -(same ? 0.f : atan2f(q.y - p.y, q.x - p.x));
+}
+
+// The per-cell brackets of delta_mid and delta_end, pre-wrapped; phi is the
+// direction z_{i-1} -> z_i of the cell.
+__device__ __forceinline__ void cell_brackets(float2 th, float phi, float& bm, float& be) {
+  bm = wrap_pi(th.x - kPi + phi);
+  be = wrap_pi(th.y + phi);
+}
+
+// One relaxation term V_{i-1}(a_{i-2}, a_{i-1}) + l2 l3 D^g_i.  A = -phi(z_{i-2}
+// -> z_{i-1}), C = -phi(z_{i-2} -> z_i); same_rc: z_{i-1} and z_i coincide.
+// The forward pass and backtracking both evaluate terms through this function,
+// so they agree bit for bit.
+template <bool DEGEN>
+__device__ __forceinline__ float relax(float v, float A, float C, float bm, float be, float2 th,
+                                       bool same_rc, float w) {
+  float x1, x2;
+  if (DEGEN) {
+    x1 = (same_rc || isnan(A)) ? th.x : A + bm;
+    x2 = (same_rc || isnan(C)) ? th.y : C + be;
+  } else {
+    x1 = A + bm;
+    x2 = C + be;
+  }
+  const float z1 = abs_wrap(x1), z2 = abs_wrap(x2);
+  return fmaf(w, __builtin_amdgcn_sqrtf(fmaf(z2, z2, z1 * z1)), v);
+}
+
 // A chunk of the cells of one step: the admissible cells (a_{i-1}, a_i) of the
 // rows r0.. r0+nr-1 of one frame group, flattened row-major over their common
 // column range [clo, clo + nc); the chunk covers flat cells [e0, e0 + 64).  All
@@ -71,15 +112,18 @@ __device__ __forceinline__ uint2 pack_chunk(int r0, int clo, int nc, int e0, int
                         (static_cast<uint32_t>(ncell) << 14));
 }
 
+// Decodes a descriptor read from LDS; the fields are wave-uniform, so they are
+// moved to scalar registers and the loops over them stay scalar.
 __device__ __forceinline__ Chunk unpack_chunk(uint2 d) {
+  const uint32_t x = __builtin_amdgcn_readfirstlane(d.x), y = __builtin_amdgcn_readfirstlane(d.y);
   Chunk c;
-  c.r0 = d.x & 63;
-  c.clo = (d.x >> 6) & 63;
-  c.nc = (d.x >> 12) & 127;
-  c.e0 = d.x >> 19;
-  c.lo = d.y & 127;
-  c.hi = (d.y >> 7) & 127;
-  c.ncell = d.y >> 14;
+  c.r0 = x & 63;
+  c.clo = (x >> 6) & 63;
+  c.nc = (x >> 12) & 127;
+  c.e0 = x >> 19;
+  c.lo = y & 127;
+  c.hi = (y >> 7) & 127;
+  c.ncell = y >> 14;
   return c;
 }
 
@@ -156,6 +200,11 @@ struct DPShared {
   int32_t red_i[NW];
 };
 
+// Value table of step i (cells V_i(a_{i-1}, a_i), i = 1..M-2) of matching tl.
+__device__ __forceinline__ float* vtable(const DPLaunch& a, int tl, int i) {
+  return a.vt + ((long long)tl * (a.m.M - 2) + (i - 1)) * a.sp.K * a.sp.K;
+}
+
 template <int NW, bool DEGEN>
 __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   __shared__ DPShared<NW> sh;
@@ -171,7 +220,6 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   const int Kc = a.sp.K;
   const int tm0 = a.m.t[0];
   const float INF = __builtin_inff();
-  const float QNAN = __builtin_nanf("");
   constexpr int kBuilder = NW - 1;  // wave that builds the schedules
 
   auto load_slot = [&](int j) {
@@ -206,6 +254,7 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   {
     const int dtm = a.m.t[1] - a.m.t[0];
     const int nch = sh.nch[1];
+    float* vt = M > 2 ? vtable(a, tl, 1) : nullptr;
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
       const int ch = wv + NW * s;
@@ -217,11 +266,11 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
         const int tr = sh.ctt[0][r], tp = sh.ctt[1][col];
         const float2 xr = sh.cxy[0][r], xa = sh.cxy[1][col];
         const bool same = xa.x == xr.x && xa.y == xr.y;
-        const float phi = same ? 0.f : atan2f(xa.y - xr.y, xa.x - xr.x);
         if (!DEGEN && same && valid) sh.flag = 1;
         const float q = a.lambda2 * fabsf(static_cast<float>(dtm - (tp - tr)));
         vr[s] = (sh.cu[0][r] + sh.cu[1][col]) + q;
-        ar[s] = (DEGEN && same) ? QNAN : -phi;
+        ar[s] = neg_dir<DEGEN>(xr, xa);
+        if (valid && vt) vt[r * Kc + col] = vr[s];
       }
     }
   }
@@ -252,21 +301,18 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
       const int k = e >> 6, c = e & 63;
       if (c < Kn) {
         const float2 pk = sh.cxy[s2][k], pc = sh.cxy[s0][c];
-        const bool same = pk.x == pc.x && pk.y == pc.y;
-        float v = same ? 0.f : -atan2f(pc.y - pk.y, pc.x - pk.x);
-        if (DEGEN && same) v = QNAN;
-        if (!DEGEN && same && sh.ctt[s2][k] < sh.ctt[s0][c]) sh.flag = 1;
-        sh.ct[e] = v;
+        if (!DEGEN && pk.x == pc.x && pk.y == pc.y && sh.ctt[s2][k] < sh.ctt[s0][c]) sh.flag = 1;
+        sh.ct[e] = neg_dir<DEGEN>(pk, pc);
       }
     }
     if (i + 1 < M) load_slot(i + 1);
     __syncthreads();
 
-    // Phase 2: the relaxations of every admissible cell, chunk by chunk.
+    // Phase 2: the minima over a_{i-2} of every admissible cell, chunk by chunk.
     const float2 th = a.theta[i];
     const int dtm = a.m.t[i] - a.m.t[i - 1];
     const float qw = a.lambda2 * (i <= M - 2 ? 2.f : 1.f);
-    uint8_t* bpstep = a.bp + ((long long)tl * (M - 2) + (i - 2)) * Kc * Kc;
+    float* vt = i <= M - 2 ? vtable(a, tl, i) : nullptr;
     const float w = a.w;
     const int nch = sh.nch[cur];
 #pragma unroll
@@ -277,47 +323,39 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
         const Chunk c = unpack_chunk(sh.sched[cur][ch]);
         int r, col;
         const bool valid = chunk_cell(c, lane, r, col);
-        if (!valid) { r = c.r0; col = c.clo; }
+        if (!valid) { r = c.r0; col = c.clo; }  // in-range reads; results unused
         const int tr = sh.ctt[s1][r], tp = sh.ctt[s0][col];
         const float2 xr = sh.cxy[s1][r], xa = sh.cxy[s0][col];
         const bool same = xa.x == xr.x && xa.y == xr.y;
-        const float phi = same ? 0.f : atan2f(xa.y - xr.y, xa.x - xr.x);
         if (!DEGEN && same && valid) sh.flag = 1;
+        anew = neg_dir<DEGEN>(xr, xa);
+        float bm, be;
+        cell_brackets(th, -anew, bm, be);
+        const float2* vcol = sh.va + r;
+        const float* ccol = sh.ct + col;
         float best = INF;
-        int arg = 0;
-        if (valid) {
-          const float bm = wrap_pi(th.x - kPi + phi), be = wrap_pi(th.y + phi);
-          const float2* vcol = sh.va + r;
-          const float* ccol = sh.ct + col;
-#pragma unroll 4
-          for (int k = c.lo; k < c.hi; ++k) {
-            const float2 v = vcol[k * KL];
-            const float cc = ccol[k * KL];
-            float x1, x2;
-            if (DEGEN) {
-              x1 = (same || isnan(v.y)) ? th.x : v.y + bm;
-              x2 = (same || isnan(cc)) ? th.y : cc + be;
-            } else {
-              x1 = v.y + bm;
-              x2 = cc + be;
-            }
-            const float z1 = abs_wrap(x1), z2 = abs_wrap(x2);
-            const float d = __builtin_amdgcn_sqrtf(fmaf(z2, z2, z1 * z1));
-            const float tot = fmaf(w, d, v.x);
-            if (tot < best) { best = tot; arg = k; }
-          }
-          bpstep[r * Kc + col] = static_cast<uint8_t>(arg);
+        int k = c.lo;
+        for (; k + 3 < c.hi; k += 4) {
+          const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
+          const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
+          const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
+          const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
+          const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
+          const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
+          best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
+        }
+        for (; k < c.hi; ++k) {
+          const float2 v0 = vcol[k * KL];
+          best = fminf(best, relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w));
         }
         const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
         vnew = (sh.cu[s0][col] + q) + best;
-        anew = (DEGEN && same) ? QNAN : -phi;
+        if (valid && vt) vt[r * Kc + col] = vnew;
       }
       vr[s] = vnew;
       ar[s] = anew;
     }
     __syncthreads();
-    (void)Kp;
-    (void)Kn;
   }
 
   // ---- optimum: first row-major minimum of V_{M-1}(a_{M-2}, a_{M-1}) ------------
@@ -358,27 +396,64 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   }
 }
 
-// ---- backtracking (Eq. 12), one thread per matching -----------------------------
-__global__ void k_backtrack(DPLaunch a, int32_t* __restrict__ assign) {
-  const int tl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tl >= a.n_tau) return;
-  const int M = a.m.M, K = a.sp.K;
+// ---- backtracking (Eq. 12), one wave per matching ---------------------------------
+// From the optimal final pair, each step recomputes the terms of the optimal
+// cell over its admissible predecessors (lanes) with the forward pass's
+// arithmetic and keeps the lowest index of the minimum.
+template <bool DEGEN>
+__device__ void backtrack_one(const DPLaunch& a, int tl, int lane, int32_t* out) {
+  const int M = a.m.M, Kc = a.sp.K, tau = a.tau0 + tl, tm0 = a.m.t[0];
+  const float INF = __builtin_inff();
+  int r = a.last2[tl].x, c = a.last2[tl].y;  // a_{M-2}, a_{M-1}
+  CandRange cc = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[M - 1] - tm0, a.sp);
+  CandRange cr = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[M - 2] - tm0, a.sp);
+  if (lane == 0) {
+    out[M - 1] = cand_node(cc, c);
+    out[M - 2] = cand_node(cr, r);
+  }
+  for (int i = M - 1; i >= 2; --i) {
+    const CandRange ck = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[i - 2] - tm0, a.sp);
+    const int nk = ck.k1 + ck.k2;
+    const int nr = cand_node(cr, r), nc = cand_node(cc, c);
+    const float2 xr = a.s.xy[nr], xa = a.s.xy[nc];
+    const int tr = a.s.t[nr];
+    const float2 th = a.theta[i];
+    const bool same = xa.x == xr.x && xa.y == xr.y;
+    float bm, be;
+    cell_brackets(th, -neg_dir<DEGEN>(xr, xa), bm, be);
+    float tot = INF;
+    if (lane < nk) {
+      const int nkn = cand_node(ck, lane);
+      if (admissible(a.s.t[nkn], tr, a.sp.T)) {
+        const float2 pk = a.s.xy[nkn];
+        const float v = vtable(a, tl, i - 1)[lane * Kc + r];
+        tot = relax<DEGEN>(v, neg_dir<DEGEN>(pk, xr), neg_dir<DEGEN>(pk, xa), bm, be, th, same, a.w);
+      }
+    }
+    int bk = lane;
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ot = __shfl_xor(tot, off);
+      const int ok = __shfl_xor(bk, off);
+      if (ot < tot || (ot == tot && ok < bk)) { tot = ot; bk = ok; }
+    }
+    if (lane == 0) out[i - 2] = cand_node(ck, bk);
+    c = r;
+    r = bk;
+    cc = cr;
+    cr = ck;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_backtrack(DPLaunch a, int32_t* __restrict__ assign) {
+  const int tl = blockIdx.x, lane = threadIdx.x;
+  const int M = a.m.M;
   int32_t* out = assign + (long long)tl * M;
   if (!(a.e32[tl] < __builtin_inff())) {
-    for (int i = 0; i < M; ++i) out[i] = -1;
+    for (int i = lane; i < M; i += 64) out[i] = -1;
     return;
   }
-  const int tau = a.tau0 + tl, tm0 = a.m.t[0];
-  int r = a.last2[tl].x, c = a.last2[tl].y;  // a_{M-2}, a_{M-1}
-  out[M - 1] = cand_node(point_candidates(a.s.fstart, a.s.F, tau + a.m.t[M - 1] - tm0, a.sp), c);
-  out[M - 2] = cand_node(point_candidates(a.s.fstart, a.s.F, tau + a.m.t[M - 2] - tm0, a.sp), r);
-  for (int i = M - 1; i >= 2; --i) {
-    const uint8_t* bprow = a.bp + ((long long)tl * (M - 2) + (i - 2)) * K * K;
-    const int k = bprow[r * K + c];
-    out[i - 2] = cand_node(point_candidates(a.s.fstart, a.s.F, tau + a.m.t[i - 2] - tm0, a.sp), k);
-    c = r;
-    r = k;
-  }
+  if (a.degen[tl]) backtrack_one<true>(a, tl, lane, out);
+  else backtrack_one<false>(a, tl, lane, out);
 }
 
 // ---- FP64 re-score of an assignment from the definition (Eq. 1-8) ---------------
@@ -458,7 +533,7 @@ hipError_t launch_dp_degenerate(const DPLaunch& a, hipStream_t st) {
 
 hipError_t launch_backtrack(const DPLaunch& a, int32_t* assign, hipStream_t st) {
   if (a.n_tau <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_backtrack, dim3((a.n_tau + 63) / 64), dim3(64), 0, st, a, assign);
+  hipLaunchKernelGGL(k_backtrack, dim3(a.n_tau), dim3(64), 0, st, a, assign);
   return hipGetLastError();
 }
 

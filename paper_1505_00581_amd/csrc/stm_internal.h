@@ -133,7 +133,7 @@ struct DPLaunch {
   const float2* theta;  // [M] model angles (mid, end) of the triangle ending at i
   float lambda1, lambda2, w;  // w = lambda2 * lambda3
   int32_t tau0, n_tau;
-  uint8_t* bp;          // [n_tau][M-2][K][K]
+  float* vt;            // [n_tau][M-2][K][K] cell values V_i, i = 1..M-2
   float* e32;           // [n_tau]
   int2* last2;          // [n_tau]
   int32_t* degen;       // [n_tau], zeroed before the launch
