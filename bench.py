@@ -31,9 +31,9 @@ METRIC = ("exact matchings/sec + DP cells/s (roofline %); pruned vs exact at "
 # forming the two angle sums, four subtractions for the two wrapped absolute
 # differences, a multiply and a fused multiply-add for the squared norm, one
 # square root, one fused multiply-add adding the weighted angle term to the
-# predecessor value, and a compare plus two selects for the running minimum and
-# its argument.
-OPS_PER_RELAX = 13
+# predecessor value, and one minimum.  (The minimising index is needed only
+# along the optimal path and is recovered there.)
+OPS_PER_RELAX = 11
 # VALU issue rate of MI355X with packed FP32 disabled: 256 CUs x 64 lanes x 2.4 GHz.
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 
@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--dp-waves", type=int, default=0, help="waves per recursion workgroup (4, 8, 16)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -108,6 +109,8 @@ def main():
     w = synth.config2(args.seed)
     s, p = w.scenes[0], w.params
     ctx = stm.Context(0)
+    if args.dp_waves:
+        ctx.set_dp_waves(args.dp_waves)
     ds = stm.DevicePoints.from_host(s)
     dms = [stm.DevicePoints.from_host(m) for m in w.models]
 
@@ -184,7 +187,8 @@ def main():
         "config": {"workload": "realistic_single_scene: 10 models M~U{50..100} vs 1 scene of "
                                "1500 frames x 20 pts (320x240, 5 planted copies/model), D=162, "
                                "K=64, W=3, T=10, all offsets",
-                   "matchings": n_match, "scene_points": int(s.n), "seed": args.seed},
+                   "matchings": n_match, "scene_points": int(s.n), "seed": args.seed,
+                   "dp_waves": args.dp_waves or 8},
         "dp_cells_per_s": {"dense": round(counts["dense_cells"] / sec, 1),
                            "feasible": round(counts["feasible_cells"] / sec, 1)},
         "relax_per_s": {"dense": round(counts["dense_relax"] / sec, 1),

@@ -170,6 +170,12 @@ int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_points* scen
                    const stm_params* params, int32_t tau_begin, int32_t tau_end,
                    int64_t* counts, void* hip_stream);
 
+/* ---- tuning ----------------------------------------------------------------- */
+
+/* Waves per workgroup of the recursion kernel (one workgroup per matching):
+ * 4, 8 or 16; 0 restores the default (8).  Results do not depend on it. */
+int stm_set_dp_waves(stm_ctx* ctx, int waves);
+
 /* ---- kernel timing for benchmarks -------------------------------------------- */
 
 /* Enables (1) or disables (0) timing and resets the totals.  While enabled,

@@ -23,8 +23,8 @@ STM_DEVICE_PTRS = 0x1
 STM_K_DENSITY = 0x4
 
 EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_match",
-           "stm_candidates", "stm_unary", "stm_count_work", "stm_profile_enable",
-           "stm_profile_read")
+           "stm_candidates", "stm_unary", "stm_count_work", "stm_set_dp_waves",
+           "stm_profile_enable", "stm_profile_read")
 
 
 class StmError(RuntimeError):
@@ -71,10 +71,12 @@ def load() -> ctypes.CDLL:
                                   ctypes.POINTER(_Params), P, P]
         lib.stm_count_work.argtypes = [P, ctypes.POINTER(_Points), ctypes.POINTER(_Points),
                                        ctypes.POINTER(_Params), i32, i32, P, P]
+        lib.stm_set_dp_waves.argtypes = [P, ctypes.c_int]
         lib.stm_profile_enable.argtypes = [P, ctypes.c_int]
         lib.stm_profile_read.argtypes = [P, P, P, P]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
-                     "stm_count_work", "stm_profile_enable", "stm_profile_read"):
+                     "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
+                     "stm_profile_read"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -260,6 +262,10 @@ class Context:
                                         _stream() if dev else None))
         return dict(dense_cells=int(c[0]), feasible_cells=int(c[1]), dense_relax=int(c[2]),
                     feasible_relax=int(c[3]))
+
+    # -- tuning -------------------------------------------------------------------
+    def set_dp_waves(self, waves: int):
+        _check(self._lib.stm_set_dp_waves(self.handle, int(waves)))
 
     # -- kernel timing ------------------------------------------------------------
     def profile_enable(self, enable: bool = True):

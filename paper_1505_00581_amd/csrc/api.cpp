@@ -47,6 +47,7 @@ struct stm_ctx {
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
   size_t prof_used = 0;             // events in use
   int64_t prof_matchings = 0;
+  int dp_waves = 8;
 };
 
 namespace {
@@ -313,6 +314,7 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
     a.e32 = d_e32 + c0;
     a.last2 = static_cast<int2*>(ctx->last2.p);
     a.degen = static_cast<int32_t*>(ctx->degen.p);
+    a.waves = ctx->dp_waves;
     if (ctx->prof) {
       if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
         for (int q = 0; q < 2; ++q) {
@@ -415,6 +417,15 @@ int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_points* scen
   STM_HIP(hipMemcpyAsync(h, ctx->counts.p, sizeof(h), hipMemcpyDeviceToHost, pr.st));
   STM_HIP(hipStreamSynchronize(pr.st));
   for (int i = 0; i < 4; ++i) counts[i] = static_cast<int64_t>(h[i]);
+  return STM_OK;
+}
+
+int stm_set_dp_waves(stm_ctx* ctx, int waves) {
+  g_err.clear();
+  if (!ctx) return fail(STM_EINVAL, "null context");
+  if (waves == 0) waves = 8;
+  if (waves != 4 && waves != 8 && waves != 16) return fail(STM_EINVAL, "waves must be 4, 8 or 16");
+  ctx->dp_waves = waves;
   return STM_OK;
 }
 

@@ -300,9 +300,14 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
     for (int e = threadIdx.x; e < Kq * KL; e += NW * 64) {
       const int k = e >> 6, c = e & 63;
       if (c < Kn) {
-        const float2 pk = sh.cxy[s2][k], pc = sh.cxy[s0][c];
-        if (!DEGEN && pk.x == pc.x && pk.y == pc.y && sh.ctt[s2][k] < sh.ctt[s0][c]) sh.flag = 1;
-        sh.ct[e] = neg_dir<DEGEN>(pk, pc);
+        // a pair is used only if some z_{i-1} fits strictly between its frames
+        // and within T of both: 2 <= t_i - t_{i-2} <= 2T - 2
+        const int gap = sh.ctt[s0][c] - sh.ctt[s2][k];
+        if (gap >= 2 && (T <= 0 || gap <= 2 * T - 2)) {
+          const float2 pk = sh.cxy[s2][k], pc = sh.cxy[s0][c];
+          if (!DEGEN && pk.x == pc.x && pk.y == pc.y) sh.flag = 1;
+          sh.ct[e] = neg_dir<DEGEN>(pk, pc);
+        }
       }
     }
     if (i + 1 < M) load_slot(i + 1);
@@ -515,21 +520,27 @@ __global__ void k_rescore(ModelView m, SceneView s, int32_t T, double l1, double
   }
 }
 
-constexpr int kDPWaves = 4;
+template <bool DEGEN>
+hipError_t launch_dp_waves(const DPLaunch& a, hipStream_t st) {
+  if (a.n_tau <= 0) return hipSuccess;
+  switch (a.waves) {
+    case 4:
+      hipLaunchKernelGGL((k_dp<4, DEGEN>), dim3(a.n_tau), dim3(4 * 64), 0, st, a);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_dp<16, DEGEN>), dim3(a.n_tau), dim3(16 * 64), 0, st, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_dp<8, DEGEN>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
+  }
+  return hipGetLastError();
+}
 
 }  // namespace
 
-hipError_t launch_dp_fast(const DPLaunch& a, hipStream_t st) {
-  if (a.n_tau <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_dp<kDPWaves, false>), dim3(a.n_tau), dim3(kDPWaves * 64), 0, st, a);
-  return hipGetLastError();
-}
+hipError_t launch_dp_fast(const DPLaunch& a, hipStream_t st) { return launch_dp_waves<false>(a, st); }
 
-hipError_t launch_dp_degenerate(const DPLaunch& a, hipStream_t st) {
-  if (a.n_tau <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_dp<kDPWaves, true>), dim3(a.n_tau), dim3(kDPWaves * 64), 0, st, a);
-  return hipGetLastError();
-}
+hipError_t launch_dp_degenerate(const DPLaunch& a, hipStream_t st) { return launch_dp_waves<true>(a, st); }
 
 hipError_t launch_backtrack(const DPLaunch& a, int32_t* assign, hipStream_t st) {
   if (a.n_tau <= 0) return hipSuccess;

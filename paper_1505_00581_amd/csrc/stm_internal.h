@@ -136,7 +136,8 @@ struct DPLaunch {
   float* vt;            // [n_tau][M-2][K][K] cell values V_i, i = 1..M-2
   float* e32;           // [n_tau]
   int2* last2;          // [n_tau]
-  int32_t* degen;       // [n_tau], zeroed before the launch
+  int32_t* degen;       // [n_tau], written by the fast variant
+  int32_t waves;        // waves per workgroup of the recursion: 4, 8 or 16
 };
 // The fast variant over every matching of the launch, then the variant for
 // degenerate triangles, which only recomputes the matchings flagged by the first.
