@@ -62,13 +62,47 @@ __device__ __forceinline__ float wrap_pi(float x) { return fmaf(-kTwoPi, rintf(x
 // |wrap(x)| for |x| <= 2 pi.
 __device__ __forceinline__ float abs_wrap(float x) { return kPi - fabsf(kPi - fabsf(x)); }
 
-// -phi(p -> q), the stored (negated) direction of q - p; 0 for coincident
+// Coefficients of atan(t) ~ t * P(t^2) on [0, 1]: degree-7 minimax fit by the
+// Remez exchange algorithm (gen_atan_poly.py prints them).
+constexpr float kAtanC0 = 0.9999993443489075f;
+constexpr float kAtanC1 = -0.33329859375953674f;
+constexpr float kAtanC2 = 0.19946566224098206f;
+constexpr float kAtanC3 = -0.1390862911939621f;
+constexpr float kAtanC4 = 0.0964219719171524f;
+constexpr float kAtanC5 = -0.0559123270213604f;
+constexpr float kAtanC6 = 0.021862957626581192f;
+constexpr float kAtanC7 = -0.004054567310959101f;
+constexpr float kHalfPi = 1.57079632679489661923f;
+
+// -atan2(y, x) for (x, y) != (0, 0): reduction to t = min(|x|,|y|) / max(|x|,|y|)
+// in [0, 1], the polynomial, then the octant and quadrant corrections.  The
+// largest error over the plane is below 3.5e-7 rad (mostly the final rounding
+// of values near pi).
+__device__ __forceinline__ float neg_atan2(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
+  const float s = t * t;
+  float p = kAtanC7;
+  p = fmaf(p, s, kAtanC6);
+  p = fmaf(p, s, kAtanC5);
+  p = fmaf(p, s, kAtanC4);
+  p = fmaf(p, s, kAtanC3);
+  p = fmaf(p, s, kAtanC2);
+  p = fmaf(p, s, kAtanC1);
+  p = fmaf(p, s, kAtanC0);
+  float a = t * p;
+  a = ay > ax ? kHalfPi - a : a;
+  a = x < 0.f ? kPi - a : a;
+  return y < 0.f ? a : -a;
+}
+
+// -phi(p -> q), the stored (negated) direction of q - p; -0 for coincident
 // points in the fast variant, NaN in the degenerate variant.
 template <bool DEGEN>
 __device__ __forceinline__ float neg_dir(float2 p, float2 q) {
   const bool same = p.x == q.x && p.y == q.y;
   if (DEGEN && same) return __builtin_nanf("");
-  return -(same ? 0.f : atan2f(q.y - p.y, q.x - p.x));
+  return same ? -0.f : neg_atan2(q.y - p.y, q.x - p.x);
 }
 
 // The per-cell brackets of delta_mid and delta_end, pre-wrapped; phi is the
