@@ -67,6 +67,12 @@ extern "C" {
 
 /* ---- flags (stm_params.flags) ------------------------------------------- */
 #define STM_DEVICE_PTRS 0x1u  /* all pointers of the call are device pointers           */
+#define STM_UNARY_BF16  0x2u  /* unary table as sqrt(|f|^2 + |g|^2 - 2 f.g) with the
+                                 descriptors rounded to BF16, dot products on MFMA with
+                                 FP32 accumulation, squared norms of the rounded vectors
+                                 in FP32, the descriptor zero-padded to a multiple of 32;
+                                 the recursion stays FP32 and the re-score FP64 from the
+                                 FP32 descriptors                                          */
 #define STM_K_DENSITY   0x4u  /* per-point cap from the local density of scene points:
                                  rho = points in frames f-1..f+1 around the shifted
                                  model frame f, K = clamp(floor((56 rho - 1170) / 60),
@@ -99,7 +105,7 @@ typedef struct {
   int32_t T;            /* temporal closeness in frames (Eq. 8); <= 0: no limit    */
   int32_t window;       /* candidate window half-width in frames, >= 0             */
   int32_t k_max;        /* candidate cap K, 1..STM_K_LIMIT                         */
-  uint32_t flags;       /* STM_DEVICE_PTRS | STM_K_DENSITY                          */
+  uint32_t flags;       /* STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY         */
 } stm_params;
 
 /* ---- context ------------------------------------------------------------ */
@@ -157,8 +163,9 @@ int stm_candidates(stm_ctx* ctx, const stm_points* model, const stm_points* scen
                    const stm_params* params, int32_t tau_begin, int32_t tau_end,
                    int32_t* cand, int32_t* count, void* hip_stream);
 
-/* FP32 unary table U [M][S]: U[i][n] = ||f_i - g_n||_2 (Eq. 2, without
- * lambda1), the look-up table of Section 3.3. */
+/* Unary table U [M][S]: U[i][n] = ||f_i - g_n||_2 (Eq. 2, without lambda1),
+ * the look-up table of Section 3.3; FP32, or split-precision BF16 with
+ * STM_UNARY_BF16. */
 int stm_unary(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
               const stm_params* params, float* U, void* hip_stream);
 

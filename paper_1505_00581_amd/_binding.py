@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libstm.so")
 STM_OK, STM_EINVAL, STM_ENOMEM, STM_EHIP, STM_EUNSUPPORTED = 0, -1, -2, -3, -4
 STM_K_LIMIT = 64
 STM_DEVICE_PTRS = 0x1
+STM_UNARY_BF16 = 0x2
 STM_K_DENSITY = 0x4
 
 EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_match",
@@ -129,7 +130,8 @@ def _points(p, keep: list) -> _Points:
 
 
 def _params(params, device: bool) -> _Params:
-    flags = (STM_DEVICE_PTRS if device else 0) | (STM_K_DENSITY if params.k_density else 0)
+    flags = ((STM_DEVICE_PTRS if device else 0) | (STM_K_DENSITY if params.k_density else 0)
+             | (STM_UNARY_BF16 if getattr(params, "unary_bf16", False) else 0))
     return _Params(params.lambda1, params.lambda2, params.lambda3, params.T, params.window,
                    params.k_max, flags)
 

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libstm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "prep.hip", "dp.hip"]
+SOURCES = ["api.cpp", "prep.hip", "dp.hip", "unary_bf16.hip"]
 HEADERS = [os.path.join(CSRC, "stm_internal.h"), os.path.join(ROOT, "include", "stm.h")]
 
 FLAGS = [

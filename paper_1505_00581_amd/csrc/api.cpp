@@ -41,6 +41,7 @@ struct stm_ctx {
   // staging for host-pointer calls
   DevBuf mxy, mt, mdesc, sxy, st, sdesc;
   DevBuf o_e32, o_e64, o_eu, o_assign, o_cand, o_cnt;
+  DevBuf fb, fn, gb, gn;  // BF16 descriptors and squared norms
   size_t vt_chunk_bytes = size_t(4) << 30;  // value-table scratch per chunk of offsets
   // kernel timing
   bool prof = false;
@@ -94,7 +95,8 @@ int check_shapes(const stm_points* m, const stm_points* s, const stm_params* p) 
   if (p->window < 0) return fail(STM_EINVAL, "window < 0");
   if (!finite_lambda(p->lambda1) || !finite_lambda(p->lambda2) || !finite_lambda(p->lambda3))
     return fail(STM_EINVAL, "lambdas must be finite and >= 0");
-  if (p->flags & ~(STM_DEVICE_PTRS | STM_K_DENSITY)) return fail(STM_EUNSUPPORTED, "unknown flag");
+  if (p->flags & ~(STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY))
+    return fail(STM_EUNSUPPORTED, "unknown flag");
   return STM_OK;
 }
 
@@ -133,6 +135,7 @@ struct Prepared {
   int32_t span = 0;
   hipStream_t st = nullptr;
   bool device = false;
+  bool bf16 = false;
 };
 
 template <class T>
@@ -155,6 +158,7 @@ int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_pa
   STM_HIP(hipSetDevice(ctx->device));
   out.st = static_cast<hipStream_t>(hip_stream);
   out.device = (p->flags & STM_DEVICE_PTRS) != 0;
+  out.bf16 = (p->flags & STM_UNARY_BF16) != 0;
   const int M = m->n, S = s->n, D = m->dim, F = s->n_frames;
   if (out.device) {
     out.m = {reinterpret_cast<const float2*>(m->xy), m->t, m->desc, M};
@@ -185,6 +189,29 @@ int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_pa
   out.s.fstart = static_cast<const int32_t*>(ctx->fstart.p);
   // a window wider than the scene adds only empty frames
   out.sp = {p->T, std::min(p->window, F), p->k_max, (p->flags & STM_K_DENSITY) ? 1 : 0};
+  return STM_OK;
+}
+
+// The unary table U [M][S] (Section 3.3), FP32 direct or BF16 on MFMA.
+int unary_table(stm_ctx* ctx, const Prepared& pr, float* U) {
+  if (!pr.bf16) {
+    STM_HIP(stm::launch_unary_f32(pr.m, pr.s, U, pr.st));
+    return STM_OK;
+  }
+  const int M = pr.m.M, S = pr.s.S, dim = pr.s.dim;
+  const int Mp = (M + 15) / 16 * 16, Sp = (S + 255) / 256 * 256, dp = stm::bf16_padded_dim(dim);
+  int rc;
+  if ((rc = grow(ctx, ctx->fb, (size_t)Mp * dp * 2, pr.st))) return rc;
+  if ((rc = grow(ctx, ctx->fn, (size_t)Mp * sizeof(float), pr.st))) return rc;
+  if ((rc = grow(ctx, ctx->gb, (size_t)Sp * dp * 2, pr.st))) return rc;
+  if ((rc = grow(ctx, ctx->gn, (size_t)Sp * sizeof(float), pr.st))) return rc;
+  uint16_t* fb = static_cast<uint16_t*>(ctx->fb.p);
+  uint16_t* gb = static_cast<uint16_t*>(ctx->gb.p);
+  float* fn = static_cast<float*>(ctx->fn.p);
+  float* gn = static_cast<float*>(ctx->gn.p);
+  STM_HIP(stm::launch_to_bf16(pr.m.desc, M, dim, Mp, fb, fn, pr.st));
+  STM_HIP(stm::launch_to_bf16(pr.s.desc, S, dim, Sp, gb, gn, pr.st));
+  STM_HIP(stm::launch_unary_bf16(fb, fn, M, gb, gn, S, dim, U, pr.st));
   return STM_OK;
 }
 
@@ -222,7 +249,7 @@ void stm_destroy(stm_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->fstart, &ctx->theta, &ctx->U,     &ctx->vt,    &ctx->last2, &ctx->degen,
                     &ctx->val,    &ctx->counts, &ctx->mxy,  &ctx->mt,    &ctx->mdesc, &ctx->sxy,
                     &ctx->st,     &ctx->sdesc,  &ctx->o_e32, &ctx->o_e64, &ctx->o_eu, &ctx->o_assign,
-                    &ctx->o_cand, &ctx->o_cnt};
+                    &ctx->o_cand, &ctx->o_cnt, &ctx->fb,   &ctx->fn,    &ctx->gb,    &ctx->gn};
   for (DevBuf* b : bufs) release(*b);
   for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
   delete ctx;
@@ -289,7 +316,7 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
   if ((rc = grow(ctx, ctx->theta, (size_t)M * sizeof(float2), st))) return rc;
   STM_HIP(stm::launch_model_angles(pr.m, static_cast<float2*>(ctx->theta.p), st));
   if ((rc = grow(ctx, ctx->U, (size_t)M * S * sizeof(float), st))) return rc;
-  STM_HIP(stm::launch_unary_f32(pr.m, pr.s, static_cast<float*>(ctx->U.p), st));
+  if ((rc = unary_table(ctx, pr, static_cast<float*>(ctx->U.p)))) return rc;
 
   // the recursion, in chunks of offsets bounded by the value-table scratch
   const size_t per_tau = (size_t)(M - 2) * K * K * sizeof(float);
@@ -392,7 +419,7 @@ int stm_unary(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
     if ((rc = grow(ctx, ctx->U, n * sizeof(float), pr.st))) return rc;
     d_u = static_cast<float*>(ctx->U.p);
   }
-  STM_HIP(stm::launch_unary_f32(pr.m, pr.s, d_u, pr.st));
+  if ((rc = unary_table(ctx, pr, d_u))) return rc;
   if (!pr.device) {
     STM_HIP(hipMemcpyAsync(U, d_u, n * sizeof(float), hipMemcpyDeviceToHost, pr.st));
     STM_HIP(hipStreamSynchronize(pr.st));

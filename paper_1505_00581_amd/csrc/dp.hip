@@ -232,24 +232,46 @@ struct DPShared {
   int32_t flag;         // coincident points seen (fast variant)
   float red_v[NW];
   int32_t red_i[NW];
+  float res_v;
+  int32_t res_i;
 };
 
-// Value table of step i (cells V_i(a_{i-1}, a_i), i = 1..M-2) of matching tl.
-__device__ __forceinline__ float* vtable(const DPLaunch& a, int tl, int i) {
-  return a.vt + ((long long)tl * (a.m.M - 2) + (i - 1)) * a.sp.K * a.sp.K;
+// One matching: a model against a scene at offset tau.
+struct MatchView {
+  ModelView m;
+  SceneView s;
+  SearchParams sp;
+  const float* U;       // unary table: row j = model point j, row stride us
+  long long us;
+  const float2* theta;  // model angles of the triangle ending at each point
+  float lambda1, lambda2, w;
+  int tau;
+};
+
+// Value table of step i (cells V_i(a_{i-1}, a_i), i = 1..M-2) inside the
+// matching's scratch vt [M-2][K][K].
+__device__ __forceinline__ float* vtable(float* vt, const MatchView& a, int i) {
+  return vt + (long long)(i - 1) * a.sp.K * a.sp.K;
+}
+__device__ __forceinline__ const float* vtable(const float* vt, const MatchView& a, int i) {
+  return vt + (long long)(i - 1) * a.sp.K * a.sp.K;
 }
 
+struct DPResult {
+  float v;   // optimum (+inf if infeasible)
+  int idx;   // r * 64 + c of the first minimising final pair (a_{M-2}, a_{M-1})
+  int flag;  // coincident points seen (fast variant)
+};
+
+// Forward pass of one matching by the whole workgroup (NW waves): writes the
+// value tables of steps 1..M-2 to vtm and returns the optimum to every thread.
 template <int NW, bool DEGEN>
-__global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
-  __shared__ DPShared<NW> sh;
+__device__ DPResult dp_forward(DPShared<NW>& sh, const MatchView& a, float* vtm) {
   constexpr int RPW = KL / NW;  // chunk slots per wave (a step has <= 64 chunks)
-  const int tl = blockIdx.x;
-  if (DEGEN && a.degen[tl] == 0) return;
-  const int tau = a.tau0 + tl;
+  const int tau = a.tau;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int M = a.m.M;
-  const int S = a.s.S;
   const int T = a.sp.T;
   const int Kc = a.sp.K;
   const int tm0 = a.m.t[0];
@@ -265,7 +287,7 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
         const int n = cand_node(c, lane);
         sh.cxy[sl][lane] = a.s.xy[n];
         sh.ctt[sl][lane] = a.s.t[n];
-        sh.cu[sl][lane] = a.lambda1 * a.U[(long long)j * S + n];
+        sh.cu[sl][lane] = a.lambda1 * a.U[(long long)j * a.us + n];
       }
       if (lane == 0) sh.ck[sl] = k;
     }
@@ -288,7 +310,7 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
   {
     const int dtm = a.m.t[1] - a.m.t[0];
     const int nch = sh.nch[1];
-    float* vt = M > 2 ? vtable(a, tl, 1) : nullptr;
+    float* vt = vtable(vtm, a, 1);
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
       const int ch = wv + NW * s;
@@ -304,7 +326,7 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
         const float q = a.lambda2 * fabsf(static_cast<float>(dtm - (tp - tr)));
         vr[s] = (sh.cu[0][r] + sh.cu[1][col]) + q;
         ar[s] = neg_dir<DEGEN>(xr, xa);
-        if (valid && vt) vt[r * Kc + col] = vr[s];
+        if (valid) vt[r * Kc + col] = vr[s];
       }
     }
   }
@@ -351,7 +373,7 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
     const float2 th = a.theta[i];
     const int dtm = a.m.t[i] - a.m.t[i - 1];
     const float qw = a.lambda2 * (i <= M - 2 ? 2.f : 1.f);
-    float* vt = i <= M - 2 ? vtable(a, tl, i) : nullptr;
+    float* vt = i <= M - 2 ? vtable(vtm, a, i) : nullptr;
     const float w = a.w;
     const int nch = sh.nch[cur];
 #pragma unroll
@@ -428,22 +450,27 @@ __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
         const int oi = sh.red_i[q];
         if (ov < bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
       }
-      a.e32[tl] = bv;
-      a.last2[tl] = bi == 0x7fffffff ? make_int2(0, 0) : make_int2(bi / KL, bi % KL);
-      if (!DEGEN) a.degen[tl] = sh.flag;
+      sh.res_v = bv;
+      sh.res_i = bi == 0x7fffffff ? 0 : bi;
     }
+    __syncthreads();
   }
+  DPResult res;
+  res.v = sh.res_v;
+  res.idx = sh.res_i;
+  res.flag = DEGEN ? 0 : sh.flag;
+  return res;
 }
 
 // ---- backtracking (Eq. 12), one wave per matching ---------------------------------
-// From the optimal final pair, each step recomputes the terms of the optimal
-// cell over its admissible predecessors (lanes) with the forward pass's
-// arithmetic and keeps the lowest index of the minimum.
+// From the optimal final pair (r, c) = (a_{M-2}, a_{M-1}), each step recomputes
+// the terms of the optimal cell over its admissible predecessors (lanes) with
+// the forward pass's arithmetic and keeps the lowest index of the minimum.
 template <bool DEGEN>
-__device__ void backtrack_one(const DPLaunch& a, int tl, int lane, int32_t* out) {
-  const int M = a.m.M, Kc = a.sp.K, tau = a.tau0 + tl, tm0 = a.m.t[0];
+__device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int c, int lane,
+                               int32_t* out) {
+  const int M = a.m.M, Kc = a.sp.K, tau = a.tau, tm0 = a.m.t[0];
   const float INF = __builtin_inff();
-  int r = a.last2[tl].x, c = a.last2[tl].y;  // a_{M-2}, a_{M-1}
   CandRange cc = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[M - 1] - tm0, a.sp);
   CandRange cr = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[M - 2] - tm0, a.sp);
   if (lane == 0) {
@@ -465,7 +492,7 @@ __device__ void backtrack_one(const DPLaunch& a, int tl, int lane, int32_t* out)
       const int nkn = cand_node(ck, lane);
       if (admissible(a.s.t[nkn], tr, a.sp.T)) {
         const float2 pk = a.s.xy[nkn];
-        const float v = vtable(a, tl, i - 1)[lane * Kc + r];
+        const float v = vtable(vtm, a, i - 1)[lane * Kc + r];
         tot = relax<DEGEN>(v, neg_dir<DEGEN>(pk, xr), neg_dir<DEGEN>(pk, xa), bm, be, th, same, a.w);
       }
     }
@@ -483,6 +510,39 @@ __device__ void backtrack_one(const DPLaunch& a, int tl, int lane, int32_t* out)
   }
 }
 
+// ---- per-offset kernels: one workgroup per offset of one (model, scene) pair ------
+__device__ __forceinline__ MatchView view_of(const DPLaunch& a, int tl) {
+  MatchView v;
+  v.m = a.m;
+  v.s = a.s;
+  v.sp = a.sp;
+  v.U = a.U;
+  v.us = a.s.S;
+  v.theta = a.theta;
+  v.lambda1 = a.lambda1;
+  v.lambda2 = a.lambda2;
+  v.w = a.w;
+  v.tau = a.tau0 + tl;
+  return v;
+}
+
+__device__ __forceinline__ float* scratch_of(const DPLaunch& a, int tl) {
+  return a.vt + (long long)tl * (a.m.M - 2) * a.sp.K * a.sp.K;
+}
+
+template <int NW, bool DEGEN>
+__global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
+  __shared__ DPShared<NW> sh;
+  const int tl = blockIdx.x;
+  if (DEGEN && a.degen[tl] == 0) return;
+  const DPResult r = dp_forward<NW, DEGEN>(sh, view_of(a, tl), scratch_of(a, tl));
+  if (threadIdx.x == 0) {
+    a.e32[tl] = r.v;
+    a.last2[tl] = make_int2(r.idx / KL, r.idx % KL);
+    if (!DEGEN) a.degen[tl] = r.flag;
+  }
+}
+
 __global__ __launch_bounds__(64) void k_backtrack(DPLaunch a, int32_t* __restrict__ assign) {
   const int tl = blockIdx.x, lane = threadIdx.x;
   const int M = a.m.M;
@@ -491,8 +551,10 @@ __global__ __launch_bounds__(64) void k_backtrack(DPLaunch a, int32_t* __restric
     for (int i = lane; i < M; i += 64) out[i] = -1;
     return;
   }
-  if (a.degen[tl]) backtrack_one<true>(a, tl, lane, out);
-  else backtrack_one<false>(a, tl, lane, out);
+  const MatchView v = view_of(a, tl);
+  const int2 l2 = a.last2[tl];
+  if (a.degen[tl]) backtrack_wave<true>(v, scratch_of(a, tl), l2.x, l2.y, lane, out);
+  else backtrack_wave<false>(v, scratch_of(a, tl), l2.x, l2.y, lane, out);
 }
 
 // ---- FP64 re-score of an assignment from the definition (Eq. 1-8) ---------------

@@ -125,6 +125,16 @@ hipError_t launch_count(const ModelView& m, const SceneView& s, const SearchPara
                         int32_t tau0, int32_t n_tau, unsigned long long* counts, hipStream_t st);
 hipError_t launch_model_angles(const ModelView& m, float2* theta, hipStream_t st);
 
+// BF16 split-precision unary table.  launch_to_bf16 writes x [n_valid][dim]
+// rounded to BF16 into out [np][bf16_padded_dim(dim)] (zero padding) and the
+// squared norms of the rounded rows into norm2 [np].  launch_unary_bf16 reads
+// fb/fn padded to a multiple of 16 rows and gb/gn padded to a multiple of 256.
+int32_t bf16_padded_dim(int32_t dim);
+hipError_t launch_to_bf16(const float* x, int32_t n_valid, int32_t dim, int32_t np, uint16_t* out,
+                          float* norm2, hipStream_t st);
+hipError_t launch_unary_bf16(const uint16_t* fb, const float* fn, int32_t M, const uint16_t* gb,
+                             const float* gn, int32_t S, int32_t dim, float* U, hipStream_t st);
+
 struct DPLaunch {
   ModelView m;
   SceneView s;

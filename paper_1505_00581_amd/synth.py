@@ -53,6 +53,7 @@ class Params:
     window: int = 2      # candidate window half-width W in frames
     k_max: int = 16      # candidate cap K
     k_density: bool = False  # per-point K from local density (batched workload)
+    unary_bf16: bool = False  # unary table from BF16 descriptors on MFMA
 
 
 @dataclasses.dataclass
