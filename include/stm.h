@@ -154,6 +154,73 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
               float* energy32, double* energy64, double* energy_u64, int32_t* assign,
               void* hip_stream);
 
+/* ---- many matchings in one launch ------------------------------------------
+ *
+ * A plan matches every offset of every (model, scene) pair of a batch.  At
+ * creation it validates all point sets once, builds the scenes' frame indices,
+ * a pair table and a work list of (pair, offset) items sorted by decreasing
+ * cost (the dense relaxation count sum_i K_{i-2} K_{i-1} K_i of the item), and
+ * allocates its scratch.  A run queues, as one HIP graph captured at the first
+ * run and replayed afterwards: the frame indices, the model angles, the unary
+ * tables (every model against every scene of the plan), one persistent
+ * recursion kernel whose workgroups pull items from the cost-sorted list with
+ * an atomic counter (a second launch redoes the items with coincident points),
+ * and the FP64 re-score.  This is the paper's suggestion of matching several
+ * models and spreading several trellises over the GPU at once (Section 5),
+ * for the under-used GPU it measures on small scene blocks (Section 3.9).
+ *
+ * Output rows: pair p owns the energy rows [row_offsets[p], row_offsets[p+1])
+ * (one per offset, in offset order) and the assignment elements
+ * [assign_offsets[p], assign_offsets[p+1]) (n_tau x M of its model).
+ * With STM_DEVICE_PTRS the point sets are referenced, not copied: they must stay
+ * allocated and unchanged while the plan lives; outputs of a run are device
+ * pointers and the run is queued on `hip_stream` (NULL: the HIP default
+ * stream).  Without it the plan keeps device copies and runs synchronously. */
+typedef struct stm_plan stm_plan;
+
+/* pairs: [n_pairs][2] (model index, scene index), host memory.  All models
+ * and scenes share one descriptor dim.  Errors as for stm_match, plus
+ * STM_EINVAL for a pair index out of range. */
+int stm_plan_create(stm_ctx* ctx, const stm_points* models, int32_t n_models,
+                    const stm_points* scenes, int32_t n_scenes, const int32_t* pairs,
+                    int32_t n_pairs, const stm_params* params, stm_plan** out);
+
+/* Frees the plan, its graph and its scratch (waits for the device).  NULL is a no-op. */
+void stm_plan_destroy(stm_plan* plan);
+
+/* Prefix offsets of the outputs, host memory, [n_pairs + 1] each (nullable),
+ * and the totals (nullable). */
+int stm_plan_rows(const stm_plan* plan, int64_t* row_offsets, int64_t* assign_offsets,
+                  int64_t* n_rows, int64_t* n_assign);
+
+/* One run over the whole batch.  energy32 [n_rows] and assign [n_assign] are
+ * required; energy64 and energy_u64 [n_rows] are nullable.  Same meaning and
+ * tie rules as stm_match. */
+int stm_plan_run(stm_plan* plan, float* energy32, double* energy64, double* energy_u64,
+                 int32_t* assign, void* hip_stream);
+
+/* Launch shape of the persistent recursion kernel: waves per workgroup (4, 8
+ * or 16) and workgroups per compute unit (1..3; 16-wave workgroups at most 2).
+ * Results do not depend on it. */
+int stm_plan_set_tuning(stm_plan* plan, int32_t waves, int32_t wgs_per_cu);
+
+/* Picks the launch shape: looks up the key (GPU architecture, K bucket = k_max
+ * rounded up to a power of two, M bucket = the largest model rounded up to a
+ * multiple of 32, density flag) in the cache file `cache_path` (nullable;
+ * one JSON object, one entry per line); if absent, times every candidate
+ * shape on an evenly spaced sample of at most `n_sample` items (<= 0: a
+ * default) of the work list, keeps the fastest and writes it to the cache.
+ * chosen [3] (nullable) receives waves, workgroups per CU, and 1 if the
+ * shape came from the cache. */
+int stm_plan_autotune(stm_plan* plan, const char* cache_path, int32_t n_sample, int32_t* chosen);
+
+/* One-shot batch: plan, run once, destroy.  row_offsets [n_pairs + 1]
+ * (nullable, host) receives the energy row prefix. */
+int stm_match_batch(stm_ctx* ctx, const stm_points* models, int32_t n_models,
+                    const stm_points* scenes, int32_t n_scenes, const int32_t* pairs,
+                    int32_t n_pairs, const stm_params* params, int64_t* row_offsets,
+                    float* energy32, double* energy64, int32_t* assign, void* hip_stream);
+
 /* ---- the steps of the path, exposed for checking ------------------------- */
 
 /* Candidate lists of every model point at every offset in [tau_begin,

@@ -25,7 +25,9 @@ STM_K_DENSITY = 0x4
 
 EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_match",
            "stm_candidates", "stm_unary", "stm_count_work", "stm_set_dp_waves",
-           "stm_profile_enable", "stm_profile_read")
+           "stm_profile_enable", "stm_profile_read", "stm_plan_create", "stm_plan_destroy",
+           "stm_plan_rows", "stm_plan_run", "stm_plan_set_tuning", "stm_plan_autotune",
+           "stm_match_batch")
 
 
 class StmError(RuntimeError):
@@ -73,11 +75,22 @@ def load() -> ctypes.CDLL:
         lib.stm_count_work.argtypes = [P, ctypes.POINTER(_Points), ctypes.POINTER(_Points),
                                        ctypes.POINTER(_Params), i32, i32, P, P]
         lib.stm_set_dp_waves.argtypes = [P, ctypes.c_int]
+        lib.stm_plan_create.argtypes = [P, P, i32, P, i32, P, i32, ctypes.POINTER(_Params),
+                                        ctypes.POINTER(P)]
+        lib.stm_plan_destroy.argtypes = [P]
+        lib.stm_plan_destroy.restype = None
+        lib.stm_plan_rows.argtypes = [P, P, P, P, P]
+        lib.stm_plan_run.argtypes = [P, P, P, P, P, P]
+        lib.stm_plan_set_tuning.argtypes = [P, i32, i32]
+        lib.stm_plan_autotune.argtypes = [P, ctypes.c_char_p, i32, P]
+        lib.stm_match_batch.argtypes = [P, P, i32, P, i32, P, i32, ctypes.POINTER(_Params), P, P, P,
+                                        P, P]
         lib.stm_profile_enable.argtypes = [P, ctypes.c_int]
         lib.stm_profile_read.argtypes = [P, P, P, P]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
-                     "stm_profile_read"):
+                     "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
+                     "stm_plan_set_tuning", "stm_plan_autotune", "stm_match_batch"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -279,3 +292,80 @@ class Context:
         _check(self._lib.stm_profile_read(self.handle, ctypes.addressof(ms), ctypes.addressof(nl),
                                           ctypes.addressof(nm)))
         return dict(dp_ms=ms.value, dp_launches=nl.value, dp_matchings=nm.value)
+
+
+class Plan:
+    """Every offset of every (model, scene) pair in one persistent, graph-replayed
+    launch (stm_plan_*).  `pairs` is [n_pairs, 2] (model index, scene index).
+    Device point sets (DevicePoints) are referenced and must outlive the plan."""
+
+    def __init__(self, ctx: Context, models, scenes, pairs, params):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        self.device = _is_device(models[0])
+        self._keep = []
+        self._models = (_Points * len(models))(*[_points(m, self._keep) for m in models])
+        self._scenes = (_Points * len(scenes))(*[_points(s_, self._keep) for s_ in scenes])
+        self.pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        self.msizes = [int(m.t.shape[0]) for m in models]
+        pp = _params(params, self.device)
+        h = ctypes.c_void_p()
+        _check(self._lib.stm_plan_create(ctx.handle, ctypes.addressof(self._models), len(models),
+                                         ctypes.addressof(self._scenes), len(scenes),
+                                         self.pairs.ctypes.data, self.pairs.shape[0], ctypes.byref(pp),
+                                         ctypes.byref(h)))
+        self.handle = h
+        n = self.pairs.shape[0]
+        self.row_offsets = np.zeros(n + 1, np.int64)
+        self.assign_offsets = np.zeros(n + 1, np.int64)
+        nr, na = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.stm_plan_rows(self.handle, self.row_offsets.ctypes.data,
+                                       self.assign_offsets.ctypes.data, ctypes.addressof(nr),
+                                       ctypes.addressof(na)))
+        self.n_rows, self.n_assign = nr.value, na.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.stm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def outputs(self):
+        if self.device:
+            import torch
+            return dict(energy32=torch.empty(self.n_rows, dtype=torch.float32, device="cuda"),
+                        energy64=torch.empty(self.n_rows, dtype=torch.float64, device="cuda"),
+                        energy_u64=torch.empty(self.n_rows, dtype=torch.float64, device="cuda"),
+                        assign=torch.empty(max(self.n_assign, 1), dtype=torch.int32, device="cuda"))
+        return dict(energy32=np.empty(self.n_rows, np.float32), energy64=np.empty(self.n_rows, np.float64),
+                    energy_u64=np.empty(self.n_rows, np.float64),
+                    assign=np.empty(max(self.n_assign, 1), np.int32))
+
+    def run(self, out=None):
+        out = out if out is not None else self.outputs()
+        _check(self._lib.stm_plan_run(self.handle, _ptr(out["energy32"]), _ptr(out["energy64"]),
+                                      _ptr(out["energy_u64"]), _ptr(out["assign"]),
+                                      _stream() if self.device else None))
+        return out
+
+    def pair_rows(self, out, q):
+        """(energy32, energy64, assign [n_tau, M]) slices of pair q."""
+        r0, r1 = self.row_offsets[q], self.row_offsets[q + 1]
+        a0, a1 = self.assign_offsets[q], self.assign_offsets[q + 1]
+        M = self.msizes[self.pairs[q, 0]]
+        return (out["energy32"][r0:r1], out["energy64"][r0:r1], out["energy_u64"][r0:r1],
+                out["assign"][a0:a1].reshape(-1, M))
+
+    def set_tuning(self, waves: int, wgs_per_cu: int):
+        _check(self._lib.stm_plan_set_tuning(self.handle, waves, wgs_per_cu))
+
+    def autotune(self, cache_path=None, n_sample: int = 0):
+        ch = (ctypes.c_int32 * 3)()
+        _check(self._lib.stm_plan_autotune(self.handle, cache_path.encode() if cache_path else None,
+                                           n_sample, ctypes.addressof(ch)))
+        return dict(waves=ch[0], wgs_per_cu=ch[1], cached=bool(ch[2]))

@@ -557,18 +557,103 @@ __global__ __launch_bounds__(64) void k_backtrack(DPLaunch a, int32_t* __restric
   else backtrack_wave<false>(v, scratch_of(a, tl), l2.x, l2.y, lane, out);
 }
 
+// ---- batched persistent launch ------------------------------------------------------
+// Workgroups pull (pair, offset) items from a cost-sorted list with an atomic
+// counter until it runs out; each solves its item with the forward pass, re-runs
+// the degenerate variant when coincident points were flagged, and backtracks in
+// wave 0 from its own value-table scratch before taking the next item.
+__device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev& pd, int tau) {
+  MatchView v;
+  v.m = pd.m;
+  v.s = pd.s;
+  v.sp = b.sp;
+  v.U = pd.U;
+  v.us = pd.us;
+  v.theta = pd.theta;
+  v.lambda1 = b.lambda1;
+  v.lambda2 = b.lambda2;
+  v.w = b.w;
+  v.tau = tau;
+  return v;
+}
+
+// The fast variant takes every item; an item whose matching has coincident
+// points is appended to the degenerate list instead of being backtracked, and
+// the degenerate variant (a second launch) takes the items of that list.
+template <int NW, bool DEGEN>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW >= 8 ? 6 : 3)))
+void k_dp_persistent(BatchLaunch b) {
+  __shared__ DPShared<NW> sh;
+  __shared__ int item_sh;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float* vtm = b.vt + (long long)blockIdx.x * b.vt_stride;
+  const int n_items = DEGEN ? *b.degen_count : b.n_items;
+  int32_t* counter = DEGEN ? b.counter + 1 : b.counter;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = DEGEN ? (item_sh < n_items ? b.degen_items[item_sh] : -1) : item_sh;
+    if (item_sh >= n_items) break;
+    const int2 it = b.items[item];
+    const PairDev pd = b.pairs[it.x];
+    const MatchView mv = view_of(b, pd, it.y);
+    const DPResult r = dp_forward<NW, DEGEN>(sh, mv, vtm);
+    if (!DEGEN && r.flag) {
+      if (threadIdx.x == 0) b.degen_items[atomicAdd(b.degen_count, 1)] = item;
+    } else if (wv == 0) {
+      const long long row = pd.row0 + it.y;
+      int32_t* out = b.assign + pd.assign0 + (long long)it.y * pd.m.M;
+      if (lane == 0) b.e32[row] = r.v;
+      if (r.v < __builtin_inff()) {
+        backtrack_wave<DEGEN>(mv, vtm, r.idx / KL, r.idx % KL, lane, out);
+      } else {
+        for (int i = lane; i < pd.m.M; i += 64) out[i] = -1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Dense relaxations sum_i K_{i-2} K_{i-1} K_i of each item (one wave per item),
+// the cost the work list is sorted by.
+__global__ __launch_bounds__(64) void k_item_cost(const PairDev* __restrict__ pairs,
+                                                 const int2* __restrict__ items, int n_items,
+                                                 SearchParams sp, long long* __restrict__ cost) {
+  const int item = blockIdx.x, lane = threadIdx.x;
+  if (item >= n_items) return;
+  const int2 it = items[item];
+  const PairDev pd = pairs[it.x];
+  const int M = pd.m.M, t0 = pd.m.t[0];
+  long long acc = 0;
+  for (int i = 2 + lane; i < M; i += 64) {
+    long long prod = 1;
+    for (int q = i - 2; q <= i; ++q) {
+      const CandRange c = point_candidates(pd.s.fstart, pd.s.F, it.y + pd.m.t[q] - t0, sp);
+      prod *= c.k1 + c.k2;
+    }
+    acc += prod;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) cost[item] = acc;
+}
+
+__global__ void k_fill_i32(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // ---- FP64 re-score of an assignment from the definition (Eq. 1-8) ---------------
 __device__ __forceinline__ double wrap64(double x) {
   const double two_pi = 6.283185307179586476925286766559;
   return x - two_pi * rint(x / two_pi);
 }
 
-__global__ void k_rescore(ModelView m, SceneView s, int32_t T, double l1, double l2, double l3,
-                          const int32_t* __restrict__ assign, double* __restrict__ e64,
-                          double* __restrict__ eu64) {
-  const int tl = blockIdx.x, lane = threadIdx.x;
+// One wave re-scores the assignment z of one matching into e64[row], eu64[row].
+__device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, double l1, double l2,
+                             double l3, const int32_t* __restrict__ z, long long tl,
+                             double* __restrict__ e64, double* __restrict__ eu64) {
+  const int lane = threadIdx.x & 63;
   const int M = m.M, dim = s.dim;
-  const int32_t* z = assign + (long long)tl * M;
   const double inf = __builtin_inf();
   if (z[0] < 0) {
     if (lane == 0) {
@@ -616,6 +701,26 @@ __global__ void k_rescore(ModelView m, SceneView s, int32_t T, double l1, double
   }
 }
 
+__global__ __launch_bounds__(64) void k_rescore(ModelView m, SceneView s, int32_t T, double l1, double l2,
+                                               double l3, const int32_t* __restrict__ assign,
+                                               double* __restrict__ e64, double* __restrict__ eu64) {
+  const int tl = blockIdx.x;
+  rescore_wave(m, s, T, l1, l2, l3, assign + (long long)tl * m.M, tl, e64, eu64);
+}
+
+__global__ __launch_bounds__(64) void k_rescore_batch(const PairDev* __restrict__ pairs,
+                                                     const int2* __restrict__ items, int n_items,
+                                                     int32_t T, double l1, double l2, double l3,
+                                                     const int32_t* __restrict__ assign,
+                                                     double* __restrict__ e64, double* __restrict__ eu64) {
+  const int item = blockIdx.x;
+  if (item >= n_items) return;
+  const int2 it = items[item];
+  const PairDev pd = pairs[it.x];
+  rescore_wave(pd.m, pd.s, T, l1, l2, l3, assign + pd.assign0 + (long long)it.y * pd.m.M,
+               pd.row0 + it.y, e64, eu64);
+}
+
 template <bool DEGEN>
 hipError_t launch_dp_waves(const DPLaunch& a, hipStream_t st) {
   if (a.n_tau <= 0) return hipSuccess;
@@ -637,6 +742,49 @@ hipError_t launch_dp_waves(const DPLaunch& a, hipStream_t st) {
 hipError_t launch_dp_fast(const DPLaunch& a, hipStream_t st) { return launch_dp_waves<false>(a, st); }
 
 hipError_t launch_dp_degenerate(const DPLaunch& a, hipStream_t st) { return launch_dp_waves<true>(a, st); }
+
+template <bool DEGEN>
+hipError_t launch_persistent_variant(const BatchLaunch& b, int n_wg, hipStream_t st) {
+  switch (b.waves) {
+    case 4:
+      hipLaunchKernelGGL((k_dp_persistent<4, DEGEN>), dim3(n_wg), dim3(4 * 64), 0, st, b);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_dp_persistent<16, DEGEN>), dim3(n_wg), dim3(16 * 64), 0, st, b);
+      break;
+    default:
+      hipLaunchKernelGGL((k_dp_persistent<8, DEGEN>), dim3(n_wg), dim3(8 * 64), 0, st, b);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dp_persistent(const BatchLaunch& b, int n_wg, hipStream_t st) {
+  hipError_t e = launch_persistent_variant<false>(b, n_wg, st);
+  if (e != hipSuccess) return e;
+  return launch_persistent_variant<true>(b, n_wg, st);
+}
+
+hipError_t launch_item_cost(const PairDev* pairs, const int2* items, int n_items, const SearchParams& sp,
+                            long long* cost, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_cost, dim3(n_items), dim3(64), 0, st, pairs, items, n_items, sp, cost);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, int32_t T,
+                                double lambda1, double lambda2, double lambda3, const int32_t* assign,
+                                double* e64, double* eu64, hipStream_t st) {
+  if (n_items <= 0 || (!e64 && !eu64)) return hipSuccess;
+  hipLaunchKernelGGL(k_rescore_batch, dim3(n_items), dim3(64), 0, st, pairs, items, n_items, T,
+                     lambda1, lambda2, lambda3, assign, e64, eu64);
+  return hipGetLastError();
+}
 
 hipError_t launch_backtrack(const DPLaunch& a, int32_t* assign, hipStream_t st) {
   if (a.n_tau <= 0) return hipSuccess;

@@ -160,4 +160,44 @@ hipError_t launch_rescore(const ModelView& m, const SceneView& s, int32_t T, dou
                           double lambda2, double lambda3, const int32_t* assign, int32_t n_tau,
                           double* e64, double* eu64, hipStream_t st);
 
+// ---- batched persistent launch ---------------------------------------------------
+
+// One (model, scene) pair of a batch.
+struct PairDev {
+  ModelView m;
+  SceneView s;
+  const float* U;       // this model's rows of the scene's unary table
+  long long us;         // row stride of U (the scene's point count)
+  const float2* theta;  // this model's angles
+  long long row0;       // first output row (offset 0) of the pair
+  long long assign0;    // first assignment element of the pair
+  int32_t n_tau;
+};
+
+struct BatchLaunch {
+  const PairDev* pairs;
+  const int2* items;    // (pair, offset), in the order workgroups take them
+  int32_t n_items;
+  int32_t* counter;     // two work counters (fast, degenerate), 0 at launch
+  int32_t* degen_count; // items whose matching has coincident points, 0 at launch
+  int32_t* degen_items; // [n_items] their indices into items
+  SearchParams sp;
+  float lambda1, lambda2, w;
+  float* vt;            // value-table scratch, vt_stride floats per workgroup
+  long long vt_stride;
+  float* e32;           // [rows]
+  int32_t* assign;      // [sum over pairs of n_tau * M]
+  int32_t waves;        // 4, 8 or 16 waves per workgroup
+};
+
+// The fast variant over all items, then the degenerate variant over the items
+// the first one flagged; n_wg workgroups each.
+hipError_t launch_dp_persistent(const BatchLaunch& b, int n_wg, hipStream_t st);
+hipError_t launch_item_cost(const PairDev* pairs, const int2* items, int n_items, const SearchParams& sp,
+                            long long* cost, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st);
+hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, int32_t T,
+                                double lambda1, double lambda2, double lambda3, const int32_t* assign,
+                                double* e64, double* eu64, hipStream_t st);
+
 }  // namespace stm
