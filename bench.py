@@ -79,6 +79,74 @@ def cpu_baseline(workload, target_s: float, seed: int):
                         f"OpenMP over offsets, {elapsed:.1f}s"))
 
 
+def bench_batched(ctx, seed: int, runs: int, cache_path: str):
+    """The batched uneven workload: 64 models (M in 30..150) against 8 scenes
+    (500..3000 frames, 10..30 points per frame), density caps K in [8, 64],
+    every offset of every pair (~8.0e5 matchings) in one autotuned persistent
+    plan replayed as a HIP graph, against a loop of one stm_match call per
+    (model, scene) pair on the same device-resident inputs."""
+    import torch
+
+    import paper_1505_00581_amd as stm
+    from paper_1505_00581_amd import synth
+    log("batched workload: generating ...")
+    w = synth.config3(seed)
+    p = w.params
+    dms = [stm.DevicePoints.from_host(m) for m in w.models]
+    dss = [stm.DevicePoints.from_host(s) for s in w.scenes]
+    pairs = np.array([(i, j) for i in range(len(dms)) for j in range(len(dss))], np.int32)
+    counts = dict(dense_relax=0, feasible_relax=0, dense_cells=0, feasible_cells=0)
+    for i, j in pairs:
+        c = ctx.count_work(dms[i], dss[j], p)
+        for k in counts:
+            counts[k] += c[k]
+    plan = stm.Plan(ctx, dms, dss, pairs, p)
+    tune = plan.autotune(cache_path)
+    out = plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        plan.run(out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / runs
+    n = plan.n_rows
+    log(f"  plan: {n} matchings, {dt * 1e3:.1f} ms per run, tuning {tune}")
+    # baseline: one stm_match call per (model, scene) pair, no graph
+    base_out = []
+    for i, j in pairs:
+        b, e = ctx.offsets(dms[i], dss[j])
+        base_out.append(dict(energy32=torch.empty(e - b, dtype=torch.float32, device="cuda"),
+                             energy64=torch.empty(e - b, dtype=torch.float64, device="cuda"),
+                             energy_u64=torch.empty(e - b, dtype=torch.float64, device="cuda"),
+                             assign=torch.empty((e - b, w.models[i].n), dtype=torch.int32, device="cuda")))
+
+    def loop():
+        for (i, j), o in zip(pairs, base_out):
+            ctx.match(dms[i], dss[j], p, out=o)
+
+    loop()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop()
+    torch.cuda.synchronize()
+    dt_base = time.perf_counter() - t0
+    same = all(bool(torch.equal(plan.pair_rows(out, q)[0], base_out[q]["energy32"]))
+               and bool(torch.equal(plan.pair_rows(out, q)[3], base_out[q]["assign"]))
+               for q in range(len(pairs)))
+    log(f"  per-pair loop: {dt_base * 1e3:.1f} ms; identical results: {same}")
+    plan.close()
+    return dict(workload="batched_uneven: 64 models M~U[30,150] x 8 scenes F~U[500,3000] at "
+                         "U{10..30} pts/frame, density caps K in [8,64], W=3, T=10, all offsets",
+                matchings=int(n), value=round(n / dt, 2), unit="matchings/s",
+                ms_per_run=round(dt * 1e3, 3), per_pair_launch_value=round(n / dt_base, 2),
+                per_pair_launch_ms=round(dt_base * 1e3, 3), speedup=round(dt_base / dt, 3),
+                identical_to_per_pair=same, tuning=tune,
+                relax_per_s={"dense": round(counts["dense_relax"] / dt, 1),
+                             "feasible": round(counts["feasible_relax"] / dt, 1)},
+                dp_cells_per_s={"dense": round(counts["dense_cells"] / dt, 1),
+                                "feasible": round(counts["feasible_cells"] / dt, 1)})
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +156,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--dp-waves", type=int, default=0, help="waves per recursion workgroup (4, 8, 16)")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the batched uneven workload (persistent plan vs per-pair launches)")
+    ap.add_argument("--batched-runs", type=int, default=3)
+    ap.add_argument("--tune-cache", default=os.path.join("/tmp", "stm_tuning_cache.json"))
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -170,6 +242,10 @@ def main():
             log(f"cpu baseline failed: {ex!r}")
             cpu = dict(value=None, unit="matchings/s", cores=None, kind="oracle", sample=f"failed: {ex!r}")
 
+    batched = None
+    if args.batched:
+        batched = bench_batched(ctx, args.seed, args.batched_runs, args.tune_cache)
+
     sec = elapsed / args.steps
     line = {
         "metric": METRIC,
@@ -197,6 +273,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if batched is not None:
+        line["batched"] = batched
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -49,6 +49,12 @@
 
 #include <stdint.h>
 
+#if defined(__GNUC__) || defined(__clang__)
+#define STM_API __attribute__((visibility("default")))
+#else
+#define STM_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -113,22 +119,22 @@ typedef struct {
 /* Creates a context on HIP device `hip_device`.  *out receives the context.
  * Work is queued on the stream each call names (NULL: the HIP default
  * stream). */
-int stm_create(stm_ctx** out, int hip_device);
+STM_API int stm_create(stm_ctx** out, int hip_device);
 
 /* Waits for the device, then frees the context and all its device scratch.
  * NULL is a no-op. */
-void stm_destroy(stm_ctx* ctx);
+STM_API void stm_destroy(stm_ctx* ctx);
 
 /* Message of the last failed call on this thread ("" if none).  The string
  * stays valid until the next call on this thread. */
-const char* stm_last_error(void);
+STM_API const char* stm_last_error(void);
 
 /* ---- offsets ------------------------------------------------------------ */
 
 /* The offsets at which the whole model fits in the scene: [*begin, *end) =
  * [0, max(0, scene->n_frames - (t_{M-1} - t_0))).  `flags` may hold
  * STM_DEVICE_PTRS (then model->t is read from the device of `ctx`). */
-int stm_offsets(stm_ctx* ctx, const stm_points* model, const stm_points* scene, uint32_t flags,
+STM_API int stm_offsets(stm_ctx* ctx, const stm_points* model, const stm_points* scene, uint32_t flags,
                 int32_t* begin, int32_t* end);
 
 /* ---- the exact matching ------------------------------------------------- */
@@ -149,7 +155,7 @@ int stm_offsets(stm_ctx* ctx, const stm_points* model, const stm_points* scene, 
  * [0, n_frames), non-finite coordinates or descriptors, window < 0, k_max
  * outside 1..STM_K_LIMIT, a negative or non-finite lambda, or an offset range
  * outside [0, n_frames - span). */
-int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+STM_API int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
               const stm_params* params, int32_t tau_begin, int32_t tau_end,
               float* energy32, double* energy64, double* energy_u64, int32_t* assign,
               void* hip_stream);
@@ -181,28 +187,28 @@ typedef struct stm_plan stm_plan;
 /* pairs: [n_pairs][2] (model index, scene index), host memory.  All models
  * and scenes share one descriptor dim.  Errors as for stm_match, plus
  * STM_EINVAL for a pair index out of range. */
-int stm_plan_create(stm_ctx* ctx, const stm_points* models, int32_t n_models,
+STM_API int stm_plan_create(stm_ctx* ctx, const stm_points* models, int32_t n_models,
                     const stm_points* scenes, int32_t n_scenes, const int32_t* pairs,
                     int32_t n_pairs, const stm_params* params, stm_plan** out);
 
 /* Frees the plan, its graph and its scratch (waits for the device).  NULL is a no-op. */
-void stm_plan_destroy(stm_plan* plan);
+STM_API void stm_plan_destroy(stm_plan* plan);
 
 /* Prefix offsets of the outputs, host memory, [n_pairs + 1] each (nullable),
  * and the totals (nullable). */
-int stm_plan_rows(const stm_plan* plan, int64_t* row_offsets, int64_t* assign_offsets,
+STM_API int stm_plan_rows(const stm_plan* plan, int64_t* row_offsets, int64_t* assign_offsets,
                   int64_t* n_rows, int64_t* n_assign);
 
 /* One run over the whole batch.  energy32 [n_rows] and assign [n_assign] are
  * required; energy64 and energy_u64 [n_rows] are nullable.  Same meaning and
  * tie rules as stm_match. */
-int stm_plan_run(stm_plan* plan, float* energy32, double* energy64, double* energy_u64,
+STM_API int stm_plan_run(stm_plan* plan, float* energy32, double* energy64, double* energy_u64,
                  int32_t* assign, void* hip_stream);
 
 /* Launch shape of the persistent recursion kernel: waves per workgroup (4, 8
  * or 16) and workgroups per compute unit (1..3; 16-wave workgroups at most 2).
  * Results do not depend on it. */
-int stm_plan_set_tuning(stm_plan* plan, int32_t waves, int32_t wgs_per_cu);
+STM_API int stm_plan_set_tuning(stm_plan* plan, int32_t waves, int32_t wgs_per_cu);
 
 /* Picks the launch shape: looks up the key (GPU architecture, K bucket = k_max
  * rounded up to a power of two, M bucket = the largest model rounded up to a
@@ -212,11 +218,11 @@ int stm_plan_set_tuning(stm_plan* plan, int32_t waves, int32_t wgs_per_cu);
  * default) of the work list, keeps the fastest and writes it to the cache.
  * chosen [3] (nullable) receives waves, workgroups per CU, and 1 if the
  * shape came from the cache. */
-int stm_plan_autotune(stm_plan* plan, const char* cache_path, int32_t n_sample, int32_t* chosen);
+STM_API int stm_plan_autotune(stm_plan* plan, const char* cache_path, int32_t n_sample, int32_t* chosen);
 
 /* One-shot batch: plan, run once, destroy.  row_offsets [n_pairs + 1]
  * (nullable, host) receives the energy row prefix. */
-int stm_match_batch(stm_ctx* ctx, const stm_points* models, int32_t n_models,
+STM_API int stm_match_batch(stm_ctx* ctx, const stm_points* models, int32_t n_models,
                     const stm_points* scenes, int32_t n_scenes, const int32_t* pairs,
                     int32_t n_pairs, const stm_params* params, int64_t* row_offsets,
                     float* energy32, double* energy64, int32_t* assign, void* hip_stream);
@@ -226,21 +232,21 @@ int stm_match_batch(stm_ctx* ctx, const stm_points* models, int32_t n_models,
 /* Candidate lists of every model point at every offset in [tau_begin,
  * tau_end): cand [n_tau][M][k_max] scene node ids in ascending order (unused
  * slots -1) and count [n_tau][M].  Same rule and validation as stm_match. */
-int stm_candidates(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+STM_API int stm_candidates(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
                    const stm_params* params, int32_t tau_begin, int32_t tau_end,
                    int32_t* cand, int32_t* count, void* hip_stream);
 
 /* Unary table U [M][S]: U[i][n] = ||f_i - g_n||_2 (Eq. 2, without lambda1),
  * the look-up table of Section 3.3; FP32, or split-precision BF16 with
  * STM_UNARY_BF16. */
-int stm_unary(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+STM_API int stm_unary(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
               const stm_params* params, float* U, void* hip_stream);
 
 /* Work of the recursion over [tau_begin, tau_end), written to counts[4]
  * (host memory, always): dense cells sum_i K_{i-1} K_i, feasible cells (the
  * pair is admissible), dense relaxations sum_i K_{i-2} K_{i-1} K_i and
  * feasible relaxations (both consecutive pairs admissible).  Synchronous. */
-int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+STM_API int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
                    const stm_params* params, int32_t tau_begin, int32_t tau_end,
                    int64_t* counts, void* hip_stream);
 
@@ -248,19 +254,19 @@ int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_points* scen
 
 /* Waves per workgroup of the recursion kernel (one workgroup per matching):
  * 4, 8 or 16; 0 restores the default (8).  Results do not depend on it. */
-int stm_set_dp_waves(stm_ctx* ctx, int waves);
+STM_API int stm_set_dp_waves(stm_ctx* ctx, int waves);
 
 /* ---- kernel timing for benchmarks -------------------------------------------- */
 
 /* Enables (1) or disables (0) timing and resets the totals.  While enabled,
  * every launch of the recursion kernel (the fast variant) is bracketed by two
  * HIP events recorded on the stream it is launched on. */
-int stm_profile_enable(stm_ctx* ctx, int enable);
+STM_API int stm_profile_enable(stm_ctx* ctx, int enable);
 
 /* Waits for the recorded events and writes the summed kernel time in
  * milliseconds, the number of launches and the number of matchings they
  * processed.  Any output pointer may be NULL. */
-int stm_profile_read(stm_ctx* ctx, double* dp_ms, int64_t* dp_launches, int64_t* dp_matchings);
+STM_API int stm_profile_read(stm_ctx* ctx, double* dp_ms, int64_t* dp_launches, int64_t* dp_matchings);
 
 #ifdef __cplusplus
 }

@@ -21,11 +21,12 @@ LIB = os.path.join(PKG, "libstm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "prep.hip", "dp.hip", "unary_bf16.hip"]
-HEADERS = [os.path.join(CSRC, "stm_internal.h"), os.path.join(ROOT, "include", "stm.h")]
+SOURCES = ["api.cpp", "plan.cpp", "prep.hip", "dp.hip", "unary_bf16.hip"]
+HEADERS = [os.path.join(CSRC, "stm_internal.h"), os.path.join(CSRC, "host_common.h"),
+           os.path.join(ROOT, "include", "stm.h")]
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-fvisibility=hidden",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,

@@ -1,0 +1,88 @@
+// Host-side helpers shared by the C-ABI sources of libstm.so: error state,
+// the context, device scratch buffers, argument and data validation, and the
+// preparation of one (model, scene) pair on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "stm.h"
+#include "stm_internal.h"
+
+namespace stmh {
+
+// Message of the last failure on this thread.
+std::string& err();
+
+inline int fail(int code, const std::string& msg) {
+  err() = msg;
+  return code;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace stmh
+
+#define STM_HIP(expr)                                                                               \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return stmh::fail(STM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct stm_ctx {
+  int device = 0;
+  // scratch
+  stmh::DevBuf fstart, theta, U, vt, last2, degen, val, counts;
+  // staging for host-pointer calls
+  stmh::DevBuf mxy, mt, mdesc, sxy, st, sdesc;
+  stmh::DevBuf o_e32, o_e64, o_eu, o_assign, o_cand, o_cnt;
+  stmh::DevBuf fb, fn, gb, gn;  // BF16 descriptors and squared norms
+  size_t vt_chunk_bytes = size_t(4) << 30;  // value-table scratch per chunk of offsets
+  // kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
+  size_t prof_used = 0;             // events in use
+  int64_t prof_matchings = 0;
+  int dp_waves = 8;
+};
+
+namespace stmh {
+
+// Grows `b` to at least `bytes` (waiting for `st` before freeing); the old
+// contents are not kept.
+int grow(stm_ctx* ctx, DevBuf& b, size_t bytes, hipStream_t st);
+void release(DevBuf& b);
+
+// Checks that do not need the data.
+int check_shapes(const stm_points* m, const stm_points* s, const stm_params* p);
+// Bits of invalid host data (see bit_message).
+int host_validate(const stm_points* m, const stm_points* s);
+const char* bit_message(int bits);
+
+// Inputs on the device, validated, with the frame index built.
+struct Prepared {
+  stm::ModelView m;
+  stm::SceneView s;
+  stm::SearchParams sp;
+  int32_t span = 0;
+  hipStream_t st = nullptr;
+  bool device = false;
+  bool bf16 = false;
+};
+
+int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_params* p,
+            void* hip_stream, Prepared& out);
+// The unary table U [M][S] (Section 3.3), FP32 direct or BF16 on MFMA.
+int unary_table(stm_ctx* ctx, const Prepared& pr, float* U);
+int check_range(const Prepared& pr, int32_t tau_begin, int32_t tau_end);
+
+}  // namespace stmh
