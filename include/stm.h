@@ -250,6 +250,115 @@ STM_API int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_poin
                    const stm_params* params, int32_t tau_begin, int32_t tau_end,
                    int64_t* counts, void* hip_stream);
 
+/* ---- learned candidate pruner ------------------------------------------------
+ *
+ * Not part of the paper.  A small network scores each candidate scene node n
+ * of model point i at offset tau and keeps the best `topk`, so that the exact
+ * recursion (Section 2.2) runs on candidate lists of at most topk nodes (a
+ * subset of the windowed lists, kept in ascending node order).  Since every
+ * pruned list is a subset of the exact one, a pruned optimum is an admissible
+ * assignment of the exact problem and its energy is never below the exact
+ * optimum.  Offsets left with no admissible assignment are solved again
+ * exactly (the fallback).
+ *
+ * A group is the candidate list of one (tau, i); it has 64 slots (slot a holds
+ * the a-th node of the windowed list, slots past the list are empty).  Row
+ * input x = [f_i (dim), g_n (dim), phi (8)]:
+ *   phi0  (t'_n - (tau + t_i - t_0)) / 4                frame offset
+ *   phi1,2 ((p'_n - p'_{q_a}) - (p_i - p_a)) / 64        x, y against neighbour a
+ *   phi3,4 the same against neighbour b
+ *   phi5  log((|p'_n - p'_{q_a}| + 1) / (|p_i - p_a| + 1)) scale ratio
+ *   phi6  U(i, n) (Eq. 2)                                phi7  i / (M - 1)
+ * with a = i - 1, b = i + 1 (the one neighbour twice at the chain ends) and q_j
+ * the candidate of neighbour j with the smallest U (lowest slot on ties; no
+ * candidate: its terms are 0).  Network: h1 = relu(W1 x + b1), h2 =
+ * relu(W2 h1 + b2), score = w3 . h2 + b3, 128 hidden units.  Parameters are
+ * packed FP32 as [W1 (128 x (2 dim + 8), row-major), b1 (128), W2 (128 x 128),
+ * b2 (128), w3 (128), b3 (1)].
+ *
+ * Training: FP32 forward and backward on the device; the loss of a group is
+ * the softmax cross-entropy of its scores against the slot of the label node
+ * (the exact optimum's a*_i), the batch loss the mean over groups; Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  Inference: BF16 inputs and weights on
+ * MFMA with FP32 accumulation (the first layer split into a model part, a
+ * scene part and the feature part, which stays FP32).
+ *
+ * Group lists `groups` are host arrays of G (tau, i) int32 pairs and `labels`
+ * host arrays of G node ids, whatever params->flags says; model and scene
+ * follow params->flags as in stm_match.  All pruner calls are synchronous.
+ */
+typedef struct stm_pruner stm_pruner;
+
+/* Number of packed parameters for descriptor dimension dim (no GPU needed). */
+STM_API int64_t stm_pruner_num_params(int32_t dim);
+
+/* A pruner for descriptors of dimension dim on ctx's device, parameters zero;
+ * set them with stm_pruner_set_params.  The pruner keeps ctx; destroy it
+ * before ctx. */
+STM_API int stm_pruner_create(stm_ctx* ctx, int32_t dim, stm_pruner** out);
+STM_API void stm_pruner_destroy(stm_pruner* pruner);
+
+/* Copies n = stm_pruner_num_params(dim) FP32 parameters from / to host
+ * memory.  Setting them also resets the Adam moments and step count. */
+STM_API int stm_pruner_set_params(stm_pruner* pruner, const float* theta, int64_t n);
+STM_API int stm_pruner_get_params(stm_pruner* pruner, float* theta, int64_t n);
+
+/* Parameters to / from a file: 8-byte tag "STMPRUN1", int32 dim, int32 0,
+ * int64 n, then n little-endian FP32 values. */
+STM_API int stm_pruner_save(stm_pruner* pruner, const char* path);
+STM_API int stm_pruner_load(stm_pruner* pruner, const char* path);
+
+/* The rows of G groups (host outputs): node [G][64] (-1 for empty slots), phi
+ * [G][64][8] (zeros for empty slots), q [G][2] (q_a, q_b node ids or -1).
+ * Every (tau, i) must be a valid offset and model point. */
+STM_API int stm_pruner_features(stm_pruner* pruner, const stm_points* model, const stm_points* scene,
+                                const stm_params* params, const int32_t* groups, int32_t G,
+                                int32_t* node, float* phi, int32_t* q, void* hip_stream);
+
+/* FP32 forward and backward over G groups: loss (mean over groups) into
+ * *loss, and optionally the gradient [n_params] and the scores [G][64]
+ * (-inf for empty slots), host memory.  STM_EINVAL if a label is not among
+ * its group's candidates.  No parameter changes. */
+STM_API int stm_pruner_gradient(stm_pruner* pruner, const stm_points* model, const stm_points* scene,
+                                const stm_params* params, const int32_t* groups, const int32_t* labels,
+                                int32_t G, float* loss, float* grad, float* scores, void* hip_stream);
+
+/* stm_pruner_gradient followed by one Adam step with learning rate lr. */
+STM_API int stm_pruner_train_step(stm_pruner* pruner, const stm_points* model, const stm_points* scene,
+                                  const stm_params* params, const int32_t* groups, const int32_t* labels,
+                                  int32_t G, float lr, float* loss, void* hip_stream);
+
+/* BF16 inference over G groups: scores [G][64] (-inf for empty slots), and the
+ * kept nodes cand [G][topk] (ascending; entries past count are unspecified)
+ * with count [G] (min(topk, list length)).  Kept: the topk highest scores,
+ * the lower slot first on equal scores.  1 <= topk <= 64.  Host outputs;
+ * any may be NULL. */
+STM_API int stm_pruner_infer(stm_pruner* pruner, const stm_points* model, const stm_points* scene,
+                             const stm_params* params, const int32_t* groups, int32_t G, int32_t topk,
+                             float* scores, int32_t* cand, int32_t* count, void* hip_stream);
+
+/* stm_match on the pruned candidate lists: outputs as in stm_match (host or
+ * device per params->flags), plus fell_back [tau_end - tau_begin] (same
+ * memory kind, may be NULL): 1 where the pruned lists admitted no assignment
+ * and the offset was solved exactly instead.  Synchronous (the fallback reads
+ * the pruned energies back). */
+STM_API int stm_match_pruned(stm_ctx* ctx, stm_pruner* pruner, const stm_points* model,
+                             const stm_points* scene, const stm_params* params, int32_t topk,
+                             int32_t tau_begin, int32_t tau_end, float* energy32, double* energy64,
+                             double* energy_u64, int32_t* assign, int32_t* fell_back, void* hip_stream);
+
+/* stm_match on caller-given candidate lists: cand [n_tau][M][kc] and count
+ * [n_tau][M] (offset-major, then model point), each list ascending scene node
+ * ids, count <= kc <= 64; the same memory kind as the other pointers (checked
+ * on the device with STM_DEVICE_PTRS).  The recursion, tie rules and re-score
+ * are those of stm_match; an offset whose lists admit no assignment gets +inf
+ * and a -1 row (no fallback).  With the windowed lists this reproduces
+ * stm_match. */
+STM_API int stm_match_lists(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+                            const stm_params* params, int32_t tau_begin, int32_t tau_end,
+                            const int32_t* cand, const int32_t* count, int32_t kc, float* energy32,
+                            double* energy64, double* energy_u64, int32_t* assign, void* hip_stream);
+
 /* ---- tuning ----------------------------------------------------------------- */
 
 /* Waves per workgroup of the recursion kernel (one workgroup per matching):

@@ -49,6 +49,9 @@ def _load():
             lib.oracle_match.restype = ctypes.c_int
             lib.oracle_match.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
                                          i32, i32, i32, i32, P, i32, P, P, P, P, i32]
+            lib.oracle_match_lists.restype = ctypes.c_int
+            lib.oracle_match_lists.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
+                                               i32, i32, P, P, i32, P, P, P, i32]
             lib.oracle_energies.restype = None
             lib.oracle_energies.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
                                             i32, P, i32, P, P]
@@ -101,6 +104,30 @@ def match(model, scene, params, taus=None, n_threads: int = 0):
     return dict(energy=e, energy_u=eu, assign=z, taus=taus,
                 counts=dict(dense_cells=int(c[0]), feasible_cells=int(c[1]),
                             dense_relax=int(c[2]), feasible_relax=int(c[3])))
+
+
+def match_lists(model, scene, params, lists, counts, n_threads: int = 0):
+    """The exact recursion on given candidate lists: lists [n, M, K] int32
+    (ascending node ids), counts [n, M].  Returns dict(energy, energy_u,
+    assign) like match."""
+    lib = _load()
+    lists = _i32(lists)
+    counts = _i32(counts)
+    n, M, K = lists.shape
+    assert counts.shape == (n, M) and M == model.n and (counts <= K).all() and (counts >= 0).all()
+    e = np.empty(n, np.float64)
+    eu = np.empty(n, np.float64)
+    z = np.empty((n, M), np.int32)
+    keep = [_f32(model.xy), _i32(model.t), _f32(model.desc), _f32(scene.xy), _i32(scene.t),
+            _f32(scene.desc)]
+    rc = lib.oracle_match_lists(M, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n,
+                                scene.n_frames, _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]),
+                                model.dim, params.lambda1, params.lambda2, params.lambda3, params.T,
+                                K, _ptr(lists), _ptr(counts), n, _ptr(e), _ptr(eu), _ptr(z),
+                                n_threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle_match_lists failed ({rc}): recursion and literal energy disagree")
+    return dict(energy=e, energy_u=eu, assign=z)
 
 
 def energies(model, scene, params, assign):

@@ -144,13 +144,14 @@ def candidate_lists(model, scene, params, tau: int):
             for i in range(model.n)]
 
 
-def brute_force(model, scene, params, tau: int):
+def brute_force(model, scene, params, tau: int, lists=None):
     """Minimum of E over every assignment drawn from the candidate lists, by
-    enumeration: the definition of the exact matching (Section 2.2).
+    enumeration: the definition of the exact matching (Section 2.2).  `lists`
+    replaces the windowed lists of offset tau when given.
 
     Returns (E*, list of all optimal assignments); E* = +inf and [] when no
     assignment is admissible.  Only for tiny inputs."""
-    cands = candidate_lists(model, scene, params, tau)
+    cands = candidate_lists(model, scene, params, tau) if lists is None else lists
     if any(len(c) == 0 for c in cands):
         return INF, []
     best, arg = INF, []

@@ -163,8 +163,8 @@ int32_t oracle_candidates(const problem* p, int32_t tau, int32_t i, int32_t* out
  * relaxations.  A cell is a state pair of consecutive points (a_{i-1}, a_i);
  * a relaxation is a triple (a_{i-2}, a_{i-1}, a_i); "feasible" means every
  * consecutive pair in it is admissible. */
-static int match_one(const problem* p, int32_t tau, double* energy, double* energy_u,
-                     int32_t* assign, long long* counts) {
+static int match_one(const problem* p, int32_t tau, const int32_t* given, const int32_t* given_cnt,
+                     double* energy, double* energy_u, int32_t* assign, long long* counts) {
   const int M = p->M, K = p->K;
   int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (size_t)M * K);
   int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
@@ -178,7 +178,12 @@ static int match_one(const problem* p, int32_t tau, double* energy, double* ener
 
   int empty = 0;
   for (int i = 0; i < M; ++i) {
-    cnt[i] = build_candidates(p, tau, i, cand + (size_t)i * K, tmp);
+    if (given) { /* caller's lists, [M][K] with counts [M] */
+      cnt[i] = given_cnt[i];
+      memcpy(cand + (size_t)i * K, given + (size_t)i * K, sizeof(int32_t) * (size_t)cnt[i]);
+    } else {
+      cnt[i] = build_candidates(p, tau, i, cand + (size_t)i * K, tmp);
+    }
     if (cnt[i] == 0) empty = 1;
   }
   /* Unary look-up table (Section 3.3): U of every (point, candidate), lambda1 absorbed. */
@@ -291,11 +296,34 @@ int oracle_match(int32_t M, const float* mxy, const int32_t* mt, const float* md
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : c0, c1, c2, c3) reduction(min : rc)
   for (int32_t j = 0; j < n_tau; ++j) {
     long long c[4] = {0, 0, 0, 0};
-    int r = match_one(&p, taus[j], energy + j, energy_u ? energy_u + j : NULL, assign + (size_t)j * M, c);
+    int r = match_one(&p, taus[j], NULL, NULL, energy + j, energy_u ? energy_u + j : NULL, assign + (size_t)j * M, c);
     c0 += c[0]; c1 += c[1]; c2 += c[2]; c3 += c[3];
     if (r < rc) rc = r;
   }
   if (counts) { counts[0] = c0; counts[1] = c1; counts[2] = c2; counts[3] = c3; }
+  return rc;
+}
+
+/* The same recursion on caller-given candidate lists: lists [n_tau][M][K]
+ * (ascending node ids, any subset of the scene), counts [n_tau][M] <= K.  The
+ * offsets matter only through the lists.  Returns as oracle_match. */
+int oracle_match_lists(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
+                       int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
+                       int32_t dim, double l1, double l2, double l3, int32_t T, int32_t K,
+                       const int32_t* lists, const int32_t* counts_in, int32_t n_tau, double* energy,
+                       double* energy_u, int32_t* assign, int32_t n_threads) {
+  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, K, 0);
+  int rc = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : rc)
+  for (int32_t j = 0; j < n_tau; ++j) {
+    long long c[4] = {0, 0, 0, 0};
+    int r = match_one(&p, 0, lists + (size_t)j * M * K, counts_in + (size_t)j * M, energy + j,
+                      energy_u ? energy_u + j : NULL, assign + (size_t)j * M, c);
+    if (r < rc) rc = r;
+  }
   return rc;
 }
 

@@ -27,7 +27,10 @@ EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_ma
            "stm_candidates", "stm_unary", "stm_count_work", "stm_set_dp_waves",
            "stm_profile_enable", "stm_profile_read", "stm_plan_create", "stm_plan_destroy",
            "stm_plan_rows", "stm_plan_run", "stm_plan_set_tuning", "stm_plan_autotune",
-           "stm_match_batch")
+           "stm_match_batch", "stm_pruner_num_params", "stm_pruner_create", "stm_pruner_destroy",
+           "stm_pruner_set_params", "stm_pruner_get_params", "stm_pruner_save", "stm_pruner_load",
+           "stm_pruner_features", "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
+           "stm_match_pruned", "stm_match_lists")
 
 
 class StmError(RuntimeError):
@@ -87,10 +90,30 @@ def load() -> ctypes.CDLL:
                                         P, P]
         lib.stm_profile_enable.argtypes = [P, ctypes.c_int]
         lib.stm_profile_read.argtypes = [P, P, P, P]
+        PP, PS = ctypes.POINTER(_Points), ctypes.POINTER(_Params)
+        lib.stm_pruner_num_params.argtypes = [i32]
+        lib.stm_pruner_num_params.restype = ctypes.c_int64
+        lib.stm_pruner_create.argtypes = [P, i32, ctypes.POINTER(P)]
+        lib.stm_pruner_destroy.argtypes = [P]
+        lib.stm_pruner_destroy.restype = None
+        lib.stm_pruner_set_params.argtypes = [P, P, ctypes.c_int64]
+        lib.stm_pruner_get_params.argtypes = [P, P, ctypes.c_int64]
+        lib.stm_pruner_save.argtypes = [P, ctypes.c_char_p]
+        lib.stm_pruner_load.argtypes = [P, ctypes.c_char_p]
+        lib.stm_pruner_features.argtypes = [P, PP, PP, PS, P, i32, P, P, P, P]
+        lib.stm_pruner_gradient.argtypes = [P, PP, PP, PS, P, P, i32, P, P, P, P]
+        lib.stm_pruner_train_step.argtypes = [P, PP, PP, PS, P, P, i32, ctypes.c_float, P, P]
+        lib.stm_pruner_infer.argtypes = [P, PP, PP, PS, P, i32, i32, P, P, P, P]
+        lib.stm_match_pruned.argtypes = [P, P, PP, PP, PS, i32, i32, i32, P, P, P, P, P, P]
+        lib.stm_match_lists.argtypes = [P, PP, PP, PS, i32, i32, P, P, i32, P, P, P, P, P]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
                      "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
-                     "stm_plan_set_tuning", "stm_plan_autotune", "stm_match_batch"):
+                     "stm_plan_set_tuning", "stm_plan_autotune", "stm_match_batch",
+                     "stm_pruner_create", "stm_pruner_set_params", "stm_pruner_get_params",
+                     "stm_pruner_save", "stm_pruner_load", "stm_pruner_features",
+                     "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
+                     "stm_match_pruned", "stm_match_lists"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -224,6 +247,40 @@ class Context:
                                    ctypes.byref(pp), b, e, _ptr(out["energy32"]),
                                    _ptr(out["energy64"]), _ptr(out["energy_u64"]),
                                    _ptr(out["assign"]), stream))
+        out["tau_begin"], out["tau_end"] = b, e
+        return out
+
+    def match_lists(self, model, scene, params, cand, count, tau_begin=None, tau_end=None):
+        """The exact recursion on given lists cand [n, M, kc] / count [n, M]
+        (numpy for host Points, torch tensors for DevicePoints)."""
+        b, e = self._range(model, scene, tau_begin, tau_end)
+        n, M = e - b, int(model.t.shape[0])
+        keep = []
+        pm, ps = _points(model, keep), _points(scene, keep)
+        dev = _is_device(model)
+        if dev:
+            import torch
+            d = model.xy.device
+            cand = cand.to(torch.int32).contiguous()
+            count = count.to(torch.int32).contiguous()
+            out = dict(energy32=torch.empty(n, dtype=torch.float32, device=d),
+                       energy64=torch.empty(n, dtype=torch.float64, device=d),
+                       energy_u64=torch.empty(n, dtype=torch.float64, device=d),
+                       assign=torch.empty((n, M), dtype=torch.int32, device=d))
+            stream = _stream()
+        else:
+            cand = np.ascontiguousarray(cand, np.int32)
+            count = np.ascontiguousarray(count, np.int32)
+            out = dict(energy32=np.empty(n, np.float32), energy64=np.empty(n, np.float64),
+                       energy_u64=np.empty(n, np.float64), assign=np.empty((n, M), np.int32))
+            stream = None
+        assert tuple(cand.shape[:2]) == (n, M) and tuple(count.shape) == (n, M)
+        pp = _params(params, dev)
+        _check(self._lib.stm_match_lists(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                         ctypes.byref(pp), b, e, _ptr(cand), _ptr(count),
+                                         int(cand.shape[2]), _ptr(out["energy32"]),
+                                         _ptr(out["energy64"]), _ptr(out["energy_u64"]),
+                                         _ptr(out["assign"]), stream))
         out["tau_begin"], out["tau_end"] = b, e
         return out
 
@@ -369,3 +426,138 @@ class Plan:
         _check(self._lib.stm_plan_autotune(self.handle, cache_path.encode() if cache_path else None,
                                            n_sample, ctypes.addressof(ch)))
         return dict(waves=ch[0], wgs_per_cu=ch[1], cached=bool(ch[2]))
+
+
+def pruner_num_params(dim: int) -> int:
+    """Packed parameter count of the candidate pruner for descriptor dim."""
+    return int(load().stm_pruner_num_params(int(dim)))
+
+
+class Pruner:
+    """The learned candidate pruner of a context (device parameters).
+
+    groups: int32 [G, 2] of (tau, i); labels: int32 [G] node ids.  Model and
+    scene are host Points or DevicePoints as for Context.match."""
+
+    def __init__(self, ctx: Context, dim: int):
+        self._lib = load()
+        self.ctx = ctx
+        self.dim = int(dim)
+        self.n_params = pruner_num_params(dim)
+        h = ctypes.c_void_p()
+        _check(self._lib.stm_pruner_create(ctx.handle, self.dim, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.stm_pruner_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, np.float32).reshape(-1)
+        _check(self._lib.stm_pruner_set_params(self.handle, _ptr(th), th.size))
+
+    def get_params(self) -> np.ndarray:
+        th = np.empty(self.n_params, np.float32)
+        _check(self._lib.stm_pruner_get_params(self.handle, _ptr(th), th.size))
+        return th
+
+    def save(self, path: str):
+        _check(self._lib.stm_pruner_save(self.handle, str(path).encode()))
+
+    def load(self, path: str):
+        _check(self._lib.stm_pruner_load(self.handle, str(path).encode()))
+
+    def _pair(self, model, scene, params, keep):
+        pm, ps = _points(model, keep), _points(scene, keep)
+        dev = _is_device(model)
+        return pm, ps, _params(params, dev), (_stream() if dev else None)
+
+    @staticmethod
+    def _groups(groups):
+        g = np.ascontiguousarray(groups, np.int32).reshape(-1, 2)
+        return g, int(g.shape[0])
+
+    def features(self, model, scene, params, groups):
+        """node [G, 64], phi [G, 64, 8], q [G, 2] (host arrays)."""
+        keep = []
+        pm, ps, pp, st = self._pair(model, scene, params, keep)
+        g, G = self._groups(groups)
+        node = np.empty((G, 64), np.int32)
+        phi = np.empty((G, 64, 8), np.float32)
+        q = np.empty((G, 2), np.int32)
+        _check(self._lib.stm_pruner_features(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                             ctypes.byref(pp), _ptr(g), G, _ptr(node), _ptr(phi),
+                                             _ptr(q), st))
+        return node, phi, q
+
+    def gradient(self, model, scene, params, groups, labels):
+        """(mean loss, gradient [n_params], scores [G, 64]); no update."""
+        keep = []
+        pm, ps, pp, st = self._pair(model, scene, params, keep)
+        g, G = self._groups(groups)
+        lab = np.ascontiguousarray(labels, np.int32)
+        loss = np.zeros(1, np.float32)
+        grad = np.empty(self.n_params, np.float32)
+        scores = np.empty((G, 64), np.float32)
+        _check(self._lib.stm_pruner_gradient(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                             ctypes.byref(pp), _ptr(g), _ptr(lab), G, _ptr(loss),
+                                             _ptr(grad), _ptr(scores), st))
+        return float(loss[0]), grad, scores
+
+    def train_step(self, model, scene, params, groups, labels, lr: float) -> float:
+        keep = []
+        pm, ps, pp, st = self._pair(model, scene, params, keep)
+        g, G = self._groups(groups)
+        lab = np.ascontiguousarray(labels, np.int32)
+        loss = np.zeros(1, np.float32)
+        _check(self._lib.stm_pruner_train_step(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                               ctypes.byref(pp), _ptr(g), _ptr(lab), G,
+                                               float(lr), _ptr(loss), st))
+        return float(loss[0])
+
+    def infer(self, model, scene, params, groups, topk: int):
+        """BF16 scores [G, 64], kept nodes cand [G, topk] and count [G]."""
+        keep = []
+        pm, ps, pp, st = self._pair(model, scene, params, keep)
+        g, G = self._groups(groups)
+        scores = np.empty((G, 64), np.float32)
+        cand = np.empty((G, topk), np.int32)
+        count = np.empty(G, np.int32)
+        _check(self._lib.stm_pruner_infer(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                          ctypes.byref(pp), _ptr(g), G, int(topk), _ptr(scores),
+                                          _ptr(cand), _ptr(count), st))
+        return scores, cand, count
+
+    def match(self, model, scene, params, topk: int = 16, tau_begin=None, tau_end=None, out=None):
+        """stm_match on the pruned lists; adds fell_back [n] to the outputs."""
+        b, e = self.ctx._range(model, scene, tau_begin, tau_end)
+        n, M = e - b, int(model.t.shape[0])
+        keep = []
+        pm, ps, pp, st = self._pair(model, scene, params, keep)
+        if _is_device(model):
+            import torch
+            d = model.xy.device
+            if out is None:
+                out = dict(energy32=torch.empty(n, dtype=torch.float32, device=d),
+                           energy64=torch.empty(n, dtype=torch.float64, device=d),
+                           energy_u64=torch.empty(n, dtype=torch.float64, device=d),
+                           assign=torch.empty((n, M), dtype=torch.int32, device=d),
+                           fell_back=torch.empty(n, dtype=torch.int32, device=d))
+        else:
+            out = dict(energy32=np.empty(n, np.float32), energy64=np.empty(n, np.float64),
+                       energy_u64=np.empty(n, np.float64), assign=np.empty((n, M), np.int32),
+                       fell_back=np.empty(n, np.int32))
+        _check(self._lib.stm_match_pruned(self.ctx.handle, self.handle, ctypes.byref(pm),
+                                          ctypes.byref(ps), ctypes.byref(pp), int(topk), b, e,
+                                          _ptr(out["energy32"]), _ptr(out["energy64"]),
+                                          _ptr(out["energy_u64"]), _ptr(out["assign"]),
+                                          _ptr(out["fell_back"]), st))
+        out["tau_begin"], out["tau_end"] = b, e
+        return out

@@ -246,7 +246,35 @@ struct MatchView {
   const float2* theta;  // model angles of the triangle ending at each point
   float lambda1, lambda2, w;
   int tau;
+  // explicit candidate lists of this matching (null: the windowed rule):
+  // point j's nodes are cand[j * cstride + a], a < ccount[j], ascending
+  const int32_t* cand;
+  const int32_t* ccount;
+  int cstride;
 };
+
+// Candidate list of point j of a matching: explicit, or the windowed rule.
+struct Cands {
+  CandRange r;
+  const int32_t* list;
+  int n;
+  __device__ __forceinline__ int count() const { return list ? n : r.k1 + r.k2; }
+  __device__ __forceinline__ int node(int a) const { return list ? list[a] : cand_node(r, a); }
+};
+
+__device__ __forceinline__ Cands cands_of(const MatchView& a, int j) {
+  Cands c;
+  if (a.cand) {
+    c.list = a.cand + (long long)j * a.cstride;
+    c.n = a.ccount[j];
+    c.r = CandRange{0, 0, 0, 0};
+  } else {
+    c.list = nullptr;
+    c.n = 0;
+    c.r = point_candidates(a.s.fstart, a.s.F, a.tau + a.m.t[j] - a.m.t[0], a.sp);
+  }
+  return c;
+}
 
 // Value table of step i (cells V_i(a_{i-1}, a_i), i = 1..M-2) inside the
 // matching's scratch vt [M-2][K][K].
@@ -280,11 +308,11 @@ __device__ DPResult dp_forward(DPShared<NW>& sh, const MatchView& a, float* vtm)
 
   auto load_slot = [&](int j) {
     if (wv == 0) {
-      const CandRange c = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[j] - tm0, a.sp);
-      const int k = c.k1 + c.k2;
+      const Cands c = cands_of(a, j);
+      const int k = c.count();
       const int sl = j & 3;
       if (lane < k) {
-        const int n = cand_node(c, lane);
+        const int n = c.node(lane);
         sh.cxy[sl][lane] = a.s.xy[n];
         sh.ctt[sl][lane] = a.s.t[n];
         sh.cu[sl][lane] = a.lambda1 * a.U[(long long)j * a.us + n];
@@ -471,16 +499,16 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
                                int32_t* out) {
   const int M = a.m.M, Kc = a.sp.K, tau = a.tau, tm0 = a.m.t[0];
   const float INF = __builtin_inff();
-  CandRange cc = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[M - 1] - tm0, a.sp);
-  CandRange cr = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[M - 2] - tm0, a.sp);
+  Cands cc = cands_of(a, M - 1);
+  Cands cr = cands_of(a, M - 2);
   if (lane == 0) {
-    out[M - 1] = cand_node(cc, c);
-    out[M - 2] = cand_node(cr, r);
+    out[M - 1] = cc.node(c);
+    out[M - 2] = cr.node(r);
   }
   for (int i = M - 1; i >= 2; --i) {
-    const CandRange ck = point_candidates(a.s.fstart, a.s.F, tau + a.m.t[i - 2] - tm0, a.sp);
-    const int nk = ck.k1 + ck.k2;
-    const int nr = cand_node(cr, r), nc = cand_node(cc, c);
+    const Cands ck = cands_of(a, i - 2);
+    const int nk = ck.count();
+    const int nr = cr.node(r), nc = cc.node(c);
     const float2 xr = a.s.xy[nr], xa = a.s.xy[nc];
     const int tr = a.s.t[nr];
     const float2 th = a.theta[i];
@@ -489,7 +517,7 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
     cell_brackets(th, -neg_dir<DEGEN>(xr, xa), bm, be);
     float tot = INF;
     if (lane < nk) {
-      const int nkn = cand_node(ck, lane);
+      const int nkn = ck.node(lane);
       if (admissible(a.s.t[nkn], tr, a.sp.T)) {
         const float2 pk = a.s.xy[nkn];
         const float v = vtable(vtm, a, i - 1)[lane * Kc + r];
@@ -502,7 +530,7 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
       const int ok = __shfl_xor(bk, off);
       if (ot < tot || (ot == tot && ok < bk)) { tot = ot; bk = ok; }
     }
-    if (lane == 0) out[i - 2] = cand_node(ck, bk);
+    if (lane == 0) out[i - 2] = ck.node(bk);
     c = r;
     r = bk;
     cc = cr;
@@ -522,7 +550,10 @@ __device__ __forceinline__ MatchView view_of(const DPLaunch& a, int tl) {
   v.lambda1 = a.lambda1;
   v.lambda2 = a.lambda2;
   v.w = a.w;
-  v.tau = a.tau0 + tl;
+  v.tau = a.taus ? a.taus[tl] : a.tau0 + tl;
+  v.cand = a.cand ? a.cand + (long long)tl * a.m.M * a.cstride : nullptr;
+  v.ccount = a.cand ? a.ccount + (long long)tl * a.m.M : nullptr;
+  v.cstride = a.cstride;
   return v;
 }
 
@@ -574,6 +605,9 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
   v.lambda2 = b.lambda2;
   v.w = b.w;
   v.tau = tau;
+  v.cand = nullptr;
+  v.ccount = nullptr;
+  v.cstride = 0;
   return v;
 }
 

@@ -148,6 +148,13 @@ struct DPLaunch {
   int2* last2;          // [n_tau]
   int32_t* degen;       // [n_tau], written by the fast variant
   int32_t waves;        // waves per workgroup of the recursion: 4, 8 or 16
+  // explicit candidate lists (null: the windowed rule): offset tl, point j has
+  // the nodes cand[(tl * M + j) * cstride + a], a < ccount[tl * M + j], ascending
+  const int32_t* cand = nullptr;
+  const int32_t* ccount = nullptr;
+  int32_t cstride = 0;
+  // explicit offsets (null: tau0 + tl): matching tl of the launch is offset taus[tl]
+  const int32_t* taus = nullptr;
 };
 // The fast variant over every matching of the launch, then the variant for
 // degenerate triangles, which only recomputes the matchings flagged by the first.
@@ -199,5 +206,68 @@ hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st);
 hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, int32_t T,
                                 double lambda1, double lambda2, double lambda3, const int32_t* assign,
                                 double* e64, double* eu64, hipStream_t st);
+
+// ---- learned candidate pruner -------------------------------------------------------
+
+constexpr int kPrunerHidden = 128;
+
+// Candidate nodes, features and the neighbours' chosen candidates of groups
+// (tau, i): node [G * 64] (-1 past the list), phi [G * 64][8], q [G][2].
+hipError_t launch_group_rows(const ModelView& m, const SceneView& s, const float* U, long long us,
+                             const SearchParams& sp, const int2* groups, int G, int32_t* node, float* phi,
+                             int32_t* q, hipStream_t st);
+
+// One FP32 training pass over G groups (rows = 64 G): forward, scores and
+// per-group losses; with labels also the gradient of the mean loss into grad
+// (packed like theta).  Buffers: h1, h2, dz1, dz2 [rows][128], ds [rows],
+// part [pruner_part_floats(G, D)].
+struct PrunerTrain {
+  const float* mdesc;
+  const float* sdesc;
+  const int2* groups;
+  const int32_t* node;
+  const float* phi;
+  const int32_t* labels;  // null: forward only
+  int D, G;
+  const float* theta;
+  float* grad;
+  float *h1, *h2, *dz1, *dz2, *ds, *loss, *scores, *part;
+};
+hipError_t launch_pruner_train(const PrunerTrain& t, hipStream_t st);
+long long pruner_part_floats(int G, int D);
+hipError_t launch_adam(float* theta, const float* g, float* m, float* v, long long n, float lr, float beta1,
+                       float beta2, float eps, float c1, float c2, hipStream_t st);
+
+// BF16 inference.
+hipError_t launch_cast_rows_bf16(const float* W, int rows, int ld, int off, int D, int dp, uint16_t* out,
+                                 hipStream_t st);
+hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float* P, hipStream_t st);
+struct PrunerInfer {
+  ModelView m;
+  SceneView s;
+  const float* U;
+  long long us;
+  SearchParams sp;
+  const int2* groups;  // null: groups (tau0 + g / M, g % M)
+  long long n_groups;
+  int tau0;
+  const float* theta;  // FP32 parameters (biases, W1 phi columns, w3)
+  int D;
+  const uint16_t* w2b;  // W2 in BF16 [128][128]
+  const float* A;       // [M][128] model projection W1[:, 0:D] f
+  const float* B;       // [S][128] scene projection W1[:, D:2D] g
+  int topk;
+  int32_t* cand;        // [n_groups][topk]
+  int32_t* count;       // [n_groups]
+  float* scores;        // [n_groups][64], nullable
+};
+hipError_t launch_pruner_infer(const PrunerInfer& q, hipStream_t st);
+// Checks caller-given lists [rows][kc] with counts [rows]; ORs error bits into *bad.
+hipError_t launch_check_lists(const int32_t* cand, const int32_t* count, long long rows, int kc, int S, int32_t* bad,
+                              hipStream_t st);
+// Exact re-solves of n offsets taus[] (rows r) back into outputs indexed by tau - tau0.
+hipError_t launch_scatter_fallback(const int32_t* taus, int n, int tau0, int M, const float* e32, const double* e64,
+                                  const double* eu, const int32_t* as, float* o32, double* o64, double* ou,
+                                  int32_t* oas, int32_t* fell, hipStream_t st);
 
 }  // namespace stm

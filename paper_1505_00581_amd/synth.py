@@ -219,3 +219,15 @@ def tiny(seed: int, m: int | None = None, max_per_frame: int = 3, n_frames: int 
     scene = assemble_scene([sxy], [st], [sd], nf)
     p = Params(window=window, k_max=k_max, T=T)
     return Workload([model], [scene], p, [], f"tiny_{seed}")
+
+
+def pruner_init(dim: int = DIM, seed: int = 0, hidden: int = 128) -> np.ndarray:
+    """Initial weights of the learned candidate pruner, packed float32
+    [W1 (hidden x (2 dim + 8)), b1, W2 (hidden x hidden), b2, w3, b3]:
+    He-uniform weights (bound sqrt(6 / fan_in)), zero biases."""
+    rng = _rng(seed)
+    n_in = 2 * dim + 8
+    parts = [rng.uniform(-1, 1, (hidden, n_in)) * math.sqrt(6.0 / n_in), np.zeros(hidden),
+             rng.uniform(-1, 1, (hidden, hidden)) * math.sqrt(6.0 / hidden), np.zeros(hidden),
+             rng.uniform(-1, 1, hidden) * math.sqrt(6.0 / hidden), np.zeros(1)]
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)

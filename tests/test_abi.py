@@ -116,3 +116,31 @@ def test_create_without_gpu_fails_cleanly():
     assert rc in (stm.STM_EHIP, stm.STM_EINVAL)
     assert not h.value
     lib.stm_destroy(None)  # no-op
+
+
+def test_pruner_parameter_count_and_null_arguments():
+    lib = stm.load()
+    assert lib.stm_pruner_num_params(162) == 128 * 332 + 128 + 128 * 128 + 128 + 128 + 1
+    assert stm.pruner_num_params(4) == 128 * 16 + 128 + 128 * 128 + 257
+    assert lib.stm_pruner_num_params(0) == -1
+    h = ctypes.c_void_p()
+    assert lib.stm_pruner_create(None, 162, ctypes.byref(h)) == stm.STM_EINVAL
+    assert "context" in lib.stm_last_error().decode()
+    assert lib.stm_pruner_set_params(None, None, 0) == stm.STM_EINVAL
+    lib.stm_pruner_destroy(None)   # a no-op
+
+
+def test_match_lists_checks_arguments_before_the_device():
+    m, s, p = _good()
+    lib = stm.load()
+    keep = []
+    pm, ps = B._points(m, keep), B._points(s, keep)
+    pp = B._params(p, False)
+    e = np.zeros(1, np.float32)
+    a = np.zeros((1, m.n), np.int32)
+    cand = np.zeros((1, m.n, 4), np.int32)
+    cnt = np.zeros((1, m.n), np.int32)
+    rc = lib.stm_match_lists(None, ctypes.byref(pm), ctypes.byref(ps), ctypes.byref(pp), 0, 1,
+                             cand.ctypes.data, cnt.ctypes.data, 4, e.ctypes.data, None, None,
+                             a.ctypes.data, None)
+    assert rc == stm.STM_EINVAL and "context" in lib.stm_last_error().decode()

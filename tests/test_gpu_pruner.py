@@ -1,0 +1,386 @@
+"""The learned candidate pruner on MI355X, against the FP64 pruner oracle
+(oracle/pruner.py) and the FP64 recursion oracle (oracle.match_lists).
+
+* features: candidate lists bit-exact, neighbour choices valid (the smallest
+  FP64 unary within FP32 rounding), phi within FP32 rounding of the oracle's;
+* FP32 training pass: scores, loss and every gradient block against the FP64
+  oracle (relative norm error <= 1e-3), Adam steps, label checks, a loss that
+  falls under training;
+* BF16 inference: scores close to the FP32 forward, the top-k rule exact on
+  the returned scores, the zero network keeps the first slots;
+* matching on given lists and on pruned lists: identical to stm_match when
+  nothing is pruned, equal to the oracle's recursion on the same lists
+  otherwise, exact fallback rows identical to stm_match.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1505_00581_amd as stm
+from oracle import energy as E
+from oracle import pruner as PR
+from paper_1505_00581_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-5, 1e-4
+H = 128
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def unpack(theta, dim):
+    ni = 2 * dim + 8
+    sizes = [("W1", (H, ni)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("w3", (H,)), ("b3", (1,))]
+    out, o = {}, 0
+    for k, shp in sizes:
+        n = int(np.prod(shp))
+        out[k] = np.asarray(theta[o:o + n], np.float64).reshape(shp)
+        o += n
+    assert o == theta.size
+    return out
+
+
+def cut(scene, n_frames):
+    keep = scene.t < n_frames
+    return synth.Points(np.ascontiguousarray(scene.xy[keep]), np.ascontiguousarray(scene.t[keep]),
+                        np.ascontiguousarray(scene.desc[keep]), n_frames)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = stm.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.config1(5)
+    return w.models[0], w.scenes[0], w.params
+
+
+@pytest.fixture(scope="module")
+def mid():
+    w = synth.config2(21, n_models=1)
+    return w.models[0], cut(w.scenes[0], 320), w.params
+
+
+def random_groups(model, scene, n, seed):
+    rng = np.random.default_rng(seed)
+    n_off = len(E.offsets(model.t, scene.n_frames))
+    taus = rng.integers(0, n_off, n)
+    i = rng.integers(0, model.n, n)
+    i[:2] = [0, model.n - 1]
+    return np.stack([taus, i], 1).astype(np.int32)
+
+
+def unary_row(model, scene, i, nodes):
+    u = np.zeros(scene.n)
+    for n in nodes:
+        u[n] = E.unary(model.desc[i], scene.desc[n])
+    return u
+
+
+def oracle_rows(model, scene, params, groups, node, q):
+    """Oracle inputs X [G*64, 2D+8] and valid [G, 64] of the groups, with the
+    neighbour choices q checked and then shared."""
+    G, D = len(groups), model.dim
+    X = np.zeros((G * 64, 2 * D + 8))
+    valid = np.zeros((G, 64), bool)
+    for g, (tau, i) in enumerate(groups):
+        tau, i = int(tau), int(i)
+        cand = oracle.candidate_list(model, scene, params, tau, i)
+        k = len(cand)
+        np.testing.assert_array_equal(node[g, :k], cand)
+        assert (node[g, k:] == -1).all()
+        valid[g, :k] = True
+        a = i - 1 if i >= 1 else i + 1
+        b = i + 1 if i <= model.n - 2 else i - 1
+        for j, qj in ((a, q[g, 0]), (b, q[g, 1])):
+            cj = oracle.candidate_list(model, scene, params, tau, j)
+            if len(cj) == 0:
+                assert qj == -1
+                continue
+            uj = unary_row(model, scene, j, cj)
+            assert qj in cj
+            # FP32 unary on the device decides; it must be the FP64 minimum up to rounding
+            assert uj[qj] <= uj[cj].min() * (1 + 1e-5) + 1e-6
+        phi = PR.features(model, scene, tau, i, cand, int(q[g, 0]), int(q[g, 1]),
+                          unary_row(model, scene, i, cand))
+        X[g * 64:g * 64 + k] = PR.inputs(model, scene, i, cand, phi)
+    return X, valid
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_features_against_oracle(ctx, request, which):
+    model, scene, p = request.getfixturevalue(which)
+    pr = stm.Pruner(ctx, model.dim)
+    groups = random_groups(model, scene, 24, seed=3)
+    node, phi, q = pr.features(model, scene, p, groups)
+    X, valid = oracle_rows(model, scene, p, groups, node, q)
+    D = model.dim
+    got = phi.reshape(-1, 8)[valid.reshape(-1)]
+    want = X[valid.reshape(-1), 2 * D:]
+    err = np.abs(got - want)
+    assert (err <= 2e-5 + 2e-5 * np.abs(want)).all(), err.max(0)
+    assert (phi.reshape(-1, 8)[~valid.reshape(-1)] == 0).all()
+    say(f"  {which}: {int(valid.sum())} feature rows, max err {err.max():.2e}")
+    pr.close()
+
+
+def _labelled(model, scene, node, seed):
+    rng = np.random.default_rng(seed)
+    labels, slots = [], []
+    for g in range(node.shape[0]):
+        k = int((node[g] >= 0).sum())
+        a = int(rng.integers(0, k))
+        labels.append(node[g, a])
+        slots.append(a)
+    return np.array(labels, np.int32), np.array(slots)
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_gradient_against_oracle(ctx, request, which):
+    model, scene, p = request.getfixturevalue(which)
+    D = model.dim
+    pr = stm.Pruner(ctx, D)
+    theta = synth.pruner_init(D, 11)
+    rng = np.random.default_rng(5)
+    n1 = H * (2 * D + 8)
+    theta[n1:n1 + H] = rng.normal(0, 0.05, H)                       # b1
+    theta[-1 - 2 * H:-1 - H] = rng.normal(0, 0.05, H)               # b2
+    pr.set_params(theta)
+    groups = random_groups(model, scene, 16, seed=9)
+    node, _, q = pr.features(model, scene, p, groups)
+    labels, slots = _labelled(model, scene, node, 2)
+    loss, grad, scores = pr.gradient(model, scene, p, groups, labels)
+    X, valid = oracle_rows(model, scene, p, groups, node, q)
+    P = unpack(theta.astype(np.float64), D)
+    s, cache = PR.forward(P, X)
+    want_loss, ds = PR.group_loss(s.reshape(-1, 64), None, slots, valid)
+    g = PR.backward(P, cache, ds.reshape(-1))
+    assert abs(loss - want_loss) <= 1e-4 * max(1.0, abs(want_loss)), (loss, want_loss)
+    sv = s.reshape(-1, 64)[valid]
+    assert (np.abs(scores[valid] - sv) <= 1e-4 * (1 + np.abs(sv))).all()
+    assert np.isneginf(scores[~valid]).all()
+    G = unpack(grad, D)
+    for k in P:
+        num = np.linalg.norm(G[k] - g[k])
+        den = np.linalg.norm(g[k])
+        say(f"  {which} d{k}: rel err {num / max(den, 1e-30):.2e} (|g| {den:.3e})")
+        assert num <= 1e-3 * den + 1e-9, k
+    pr.close()
+
+
+def test_label_outside_list_rejected(ctx, small):
+    model, scene, p = small
+    pr = stm.Pruner(ctx, model.dim)
+    pr.set_params(synth.pruner_init(model.dim, 0))
+    groups = random_groups(model, scene, 4, seed=1)
+    node, _, _ = pr.features(model, scene, p, groups)
+    labels = node[:, 0].copy()
+    outside = np.setdiff1d(np.arange(scene.n), node[1])
+    labels[1] = outside[0]
+    with pytest.raises(stm.StmError):
+        pr.gradient(model, scene, p, groups, labels)
+    with pytest.raises(stm.StmError):
+        pr.train_step(model, scene, p, groups, labels, 1e-3)
+    # nothing was updated
+    np.testing.assert_array_equal(pr.get_params(), synth.pruner_init(model.dim, 0))
+    pr.close()
+
+
+def test_adam_steps_against_oracle(ctx, small):
+    model, scene, p = small
+    D = model.dim
+    pr = stm.Pruner(ctx, D)
+    theta = synth.pruner_init(D, 4)
+    pr.set_params(theta)
+    groups = random_groups(model, scene, 12, seed=4)
+    node, _, _ = pr.features(model, scene, p, groups)
+    labels, _ = _labelled(model, scene, node, 4)
+    P = {"theta": theta.astype(np.float64)}
+    state = {}
+    for step in (1, 2, 3):
+        _, grad, _ = pr.gradient(model, scene, p, groups, labels)
+        pr.train_step(model, scene, p, groups, labels, 1e-3)
+        PR.adam_step(P, {"theta": grad.astype(np.float64)}, state, lr=1e-3, step=step)
+        got = pr.get_params()
+        assert np.abs(got - P["theta"]).max() <= 1e-6 + 1e-6 * np.abs(P["theta"]).max()
+        P["theta"] = got.astype(np.float64)   # follow the device's FP32 parameters
+    pr.close()
+
+
+def test_training_lowers_the_loss(ctx, mid):
+    model, scene, p = mid
+    r = ctx.match(model, scene, p)
+    feas = np.nonzero(np.isfinite(r["energy32"]))[0]
+    rng = np.random.default_rng(0)
+    taus = rng.choice(feas, 256)
+    i = rng.integers(0, model.n, 256)
+    groups = np.stack([taus, i], 1).astype(np.int32)
+    labels = r["assign"][taus, i].astype(np.int32)
+    pr = stm.Pruner(ctx, model.dim)
+    pr.set_params(synth.pruner_init(model.dim, 1))
+    losses = [pr.train_step(model, scene, p, groups, labels, 2e-3) for _ in range(60)]
+    say(f"  loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert losses[-1] < 0.5 * losses[0]
+    pr.close()
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_infer_bf16_and_topk(ctx, request, which):
+    model, scene, p = request.getfixturevalue(which)
+    pr = stm.Pruner(ctx, model.dim)
+    pr.set_params(synth.pruner_init(model.dim, 6))
+    groups = random_groups(model, scene, 32, seed=6)
+    node, _, _ = pr.features(model, scene, p, groups)
+    labels, _ = _labelled(model, scene, node, 6)
+    _, _, s32 = pr.gradient(model, scene, p, groups, labels)
+    for topk in (1, 5, 16, 64):
+        sb, cand, count = pr.infer(model, scene, p, groups, topk)
+        valid = node >= 0
+        assert np.isneginf(sb[~valid]).all()
+        scale = np.abs(s32[valid]).mean() + 1.0
+        err = np.abs(sb[valid] - s32[valid]).max()
+        assert err <= 0.03 * scale, (err, scale)
+        for g in range(len(groups)):
+            k = int(valid[g].sum())
+            order = sorted(range(k), key=lambda a: (-sb[g, a], a))[:topk]
+            want = np.sort(node[g, order])
+            assert count[g] == min(topk, k)
+            np.testing.assert_array_equal(cand[g, :count[g]], want)
+    say(f"  {which}: bf16 score err {err:.3e} (scale {scale:.3f})")
+    # the zero network scores every candidate 0: the first slots are kept
+    pr.set_params(np.zeros(pr.n_params, np.float32))
+    sb, cand, count = pr.infer(model, scene, p, groups, 4)
+    for g in range(len(groups)):
+        k = int((node[g] >= 0).sum())
+        np.testing.assert_array_equal(cand[g, :count[g]], node[g, :min(4, k)])
+    pr.close()
+
+
+def test_match_lists_reproduces_match(ctx, small):
+    model, scene, p = small
+    cand, cnt = ctx.candidates(model, scene, p)
+    a = ctx.match(model, scene, p)
+    b = ctx.match_lists(model, scene, p, cand, cnt)
+    for k in ("energy32", "energy64", "energy_u64", "assign"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_match_lists_against_oracle(ctx, request, which):
+    model, scene, p = request.getfixturevalue(which)
+    cand, cnt = ctx.candidates(model, scene, p)
+    rng = np.random.default_rng(8)
+    n, M, K = cand.shape
+    sub = np.full((n, M, 16), -1, np.int32)
+    scnt = np.zeros((n, M), np.int32)
+    for t in range(n):
+        for i in range(M):
+            keep = [int(x) for x in cand[t, i, :cnt[t, i]] if rng.random() < 0.6][:16]
+            sub[t, i, :len(keep)] = keep
+            scnt[t, i] = len(keep)
+    got = ctx.match_lists(model, scene, p, sub, scnt)
+    taus = np.unique(np.linspace(0, n - 1, 24).astype(int))
+    ora = oracle.match_lists(model, scene, p, sub[taus], scnt[taus])
+    e = ora["energy"]
+    fin = np.isfinite(e)
+    assert (np.isfinite(got["energy32"][taus]) == fin).all()
+    assert (np.abs(got["energy32"][taus][fin] - e[fin]) <= np.maximum(RTOL * e[fin], ATOL)).all()
+    eg, _ = oracle.energies(model, scene, p, got["assign"][taus][fin])
+    assert (np.abs(eg - e[fin]) <= np.maximum(RTOL * e[fin], ATOL)).all()
+    np.testing.assert_allclose(got["energy64"][taus][fin], eg, rtol=1e-9)
+    assert (got["assign"][taus][~fin] == -1).all()
+    say(f"  {which}: {int(fin.sum())} feasible / {len(taus)} sampled offsets on sub-lists")
+
+
+def test_invalid_lists_rejected(ctx, small):
+    model, scene, p = small
+    cand, cnt = ctx.candidates(model, scene, p)
+    bad = cand.copy()
+    bad[0, 0, :2] = bad[0, 0, 1::-1]       # not ascending
+    with pytest.raises(stm.StmError):
+        ctx.match_lists(model, scene, p, bad, cnt)
+    c2 = cnt.copy()
+    c2[1, 1] = cand.shape[2] + 1
+    with pytest.raises(stm.StmError):
+        ctx.match_lists(model, scene, p, cand, c2)
+
+
+def test_pruned_keeping_everything_equals_exact(ctx, small):
+    model, scene, p = small
+    pr = stm.Pruner(ctx, model.dim)
+    pr.set_params(synth.pruner_init(model.dim, 2))
+    a = ctx.match(model, scene, p)
+    b = pr.match(model, scene, p, topk=64)
+    for k in ("energy32", "energy64", "energy_u64", "assign"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert (b["fell_back"] == np.where(np.isfinite(a["energy32"]), 0, 1)).all()
+    pr.close()
+
+
+@pytest.mark.parametrize("which,topk", [("small", 6), ("mid", 16), ("small", 1)])
+def test_pruned_against_oracle_and_fallback(ctx, request, which, topk):
+    import torch
+    model, scene, p = request.getfixturevalue(which)
+    pr = stm.Pruner(ctx, model.dim)
+    pr.set_params(synth.pruner_init(model.dim, 3))
+    ex = ctx.match(model, scene, p)
+    got = pr.match(model, scene, p, topk=topk)
+    n, M = got["assign"].shape
+    # device-resident inputs and outputs give the same rows
+    dm, ds = stm.DevicePoints.from_host(model), stm.DevicePoints.from_host(scene)
+    dev = pr.match(dm, ds, p, topk=topk)
+    torch.cuda.synchronize()
+    for k in ("energy32", "energy64", "assign", "fell_back"):
+        np.testing.assert_array_equal(got[k], dev[k].cpu().numpy())
+    fell = got["fell_back"].astype(bool)
+    # fallback rows are the exact rows
+    for k in ("energy32", "energy64", "assign"):
+        np.testing.assert_array_equal(got[k][fell], ex[k][fell])
+    # pruned optimum: never below the exact one, and the oracle's on the same lists
+    fin = np.isfinite(ex["energy32"])
+    assert (got["energy32"][fin] >= ex["energy32"][fin] - np.maximum(RTOL * ex["energy32"][fin], ATOL)).all()
+    groups = np.array([(t, i) for t in range(n) for i in range(M)], np.int32)
+    _, cand, count = pr.infer(model, scene, p, groups, topk)
+    cand, count = cand.reshape(n, M, topk), count.reshape(n, M)
+    taus = np.nonzero(~fell)[0]
+    taus = taus[np.unique(np.linspace(0, len(taus) - 1, 20).astype(int))] if len(taus) else taus
+    if len(taus):
+        ora = oracle.match_lists(model, scene, p, cand[taus], count[taus])
+        e = ora["energy"]
+        assert np.isfinite(e).all()
+        assert (np.abs(got["energy32"][taus] - e) <= np.maximum(RTOL * e, ATOL)).all()
+        for t in taus:   # the assignment uses the pruned lists
+            for i in range(M):
+                assert got["assign"][t, i] in cand[t, i, :count[t, i]]
+    gap = (got["energy32"][fin] - ex["energy32"][fin]) / np.maximum(ex["energy32"][fin], 1e-6)
+    say(f"  {which} top-{topk}: fallback {fell.mean():.3f}, mean gap {gap.mean():.4f}, "
+        f"{len(taus)} offsets checked against the oracle")
+    if topk == 1:
+        assert fell.any()
+    pr.close()
+
+
+def test_save_load_roundtrip(ctx, small, tmp_path):
+    model, scene, p = small
+    a = stm.Pruner(ctx, model.dim)
+    th = synth.pruner_init(model.dim, 8)
+    a.set_params(th)
+    path = tmp_path / "pruner.bin"
+    a.save(path)
+    b = stm.Pruner(ctx, model.dim)
+    b.load(path)
+    np.testing.assert_array_equal(b.get_params(), th)
+    c = stm.Pruner(ctx, 16)
+    with pytest.raises(stm.StmError):
+        c.load(path)
+    for x in (a, b, c):
+        x.close()

@@ -376,3 +376,58 @@ def test_c_and_python_energy_agree_on_config1_assignments():
         if math.isfinite(r["energy"][j]):
             e_py = E.energy(m, s, _as_ints(r["assign"][j]), p)
             assert abs(e_py - r["energy"][j]) <= 1e-12 * max(1.0, e_py)
+
+
+def _lists_array(lists, M, K):
+    row = np.full((M, K), -1, np.int32)
+    cnt = np.zeros(M, np.int32)
+    for i, c in enumerate(lists):
+        row[i, :len(c)] = c
+        cnt[i] = len(c)
+    return row, cnt
+
+
+def test_recursion_on_given_lists_equals_brute_force():
+    """The explicit-list entry point (used to judge pruned matchings) against
+    enumeration over random subsets of the windowed lists."""
+    rng = np.random.default_rng(7)
+    feasible = 0
+    for seed in range(40):
+        w = synth.tiny(200 + seed)
+        m, s, p = w.models[0], w.scenes[0], w.params
+        rows, cnts, bf = [], [], []
+        for tau in E.offsets(m.t, s.n_frames):
+            sub = [sorted(int(x) for x in c if rng.random() < 0.75)
+                   for c in E.candidate_lists(m, s, p, tau)]
+            r, c = _lists_array(sub, m.n, p.k_max)
+            rows.append(r)
+            cnts.append(c)
+            bf.append(E.brute_force(m, s, p, tau, lists=sub))
+        if not rows:
+            continue
+        got = oracle.match_lists(m, s, p, np.array(rows), np.array(cnts))
+        for j, (e, zs) in enumerate(bf):
+            if not np.isfinite(e):
+                assert not np.isfinite(got["energy"][j])
+                assert (got["assign"][j] == -1).all()
+                continue
+            feasible += 1
+            assert abs(got["energy"][j] - e) <= 1e-9 * max(1.0, abs(e))
+            assert [int(x) for x in got["assign"][j]] in [list(z) for z in zs]
+    assert feasible >= 40
+
+
+def test_recursion_on_windowed_lists_equals_match():
+    w = synth.config1(3)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    taus = np.arange(0, len(E.offsets(m.t, s.n_frames)), 7, dtype=np.int32)
+    rows, cnts = [], []
+    for tau in taus:
+        r, c = _lists_array([oracle.candidate_list(m, s, p, int(tau), i) for i in range(m.n)], m.n,
+                            p.k_max)
+        rows.append(r)
+        cnts.append(c)
+    a = oracle.match(m, s, p, taus=taus)
+    b = oracle.match_lists(m, s, p, np.array(rows), np.array(cnts))
+    np.testing.assert_array_equal(a["energy"], b["energy"])
+    np.testing.assert_array_equal(a["assign"], b["assign"])
