@@ -263,12 +263,14 @@ STM_API int stm_count_work(stm_ctx* ctx, const stm_points* model, const stm_poin
  *
  * A group is the candidate list of one (tau, i); it has 64 slots (slot a holds
  * the a-th node of the windowed list, slots past the list are empty).  Row
- * input x = [f_i (dim), g_n (dim), phi (8)]:
+ * input x = [dim f_i, dim g_n, phi (8)] (descriptors scaled by their
+ * dimension):
  *   phi0  (t'_n - (tau + t_i - t_0)) / 4                frame offset
  *   phi1,2 ((p'_n - p'_{q_a}) - (p_i - p_a)) / 64        x, y against neighbour a
  *   phi3,4 the same against neighbour b
  *   phi5  log((|p'_n - p'_{q_a}| + 1) / (|p_i - p_a| + 1)) scale ratio
- *   phi6  U(i, n) (Eq. 2)                                phi7  i / (M - 1)
+ *   phi6  U(i, n) - min over the group's candidates n' of U(i, n') (Eq. 2)
+ *   phi7  i / (M - 1)
  * with a = i - 1, b = i + 1 (the one neighbour twice at the chain ends) and q_j
  * the candidate of neighbour j with the smallest U (lowest slot on ties; no
  * candidate: its terms are 0).  Network: h1 = relu(W1 x + b1), h2 =

@@ -8,13 +8,15 @@ of a model point i at an offset tau and keeps the best k, so that the exact
 recursion (Section 2.2) runs on shorter candidate lists; the exact recursion
 stays the fallback and the judge of the energy gap.
 
-Input of one (tau, i, n): x = [f_i (D), g_n (D), phi (8)], D = descriptor dim.
+Input of one (tau, i, n): x = [D f_i (D), D g_n (D), phi (8)], D = descriptor
+dim (the descriptors are L1-normalised, so the factor D brings their entries
+to order 1).
 phi (fixed before any training):
   0  (t'_n - (tau + t_i - t_0)) / 4                       frame offset
   1,2 ((p'_n - p'_{q_a}) - (p_i - p_a)) / 64               x, y consistency with neighbour a
   3,4 ((p'_n - p'_{q_b}) - (p_i - p_b)) / 64               x, y consistency with neighbour b
   5  log((|p'_n - p'_{q_a}| + 1) / (|p_i - p_a| + 1))       scale ratio against neighbour a
-  6  U(i, n) = |f_i - g_n|                                  appearance (Eq. 2)
+  6  U(i, n) - min over the group's candidates n' of U(i, n')  appearance (Eq. 2)
   7  i / (M - 1)                                            position in the chain
 Neighbours: a = i - 1 and b = i + 1; at the chain ends the one neighbour is
 used for both.  q_j is the candidate of neighbour j at tau with the smallest
@@ -71,6 +73,7 @@ def features(model, scene, tau: int, i: int, cand_i, q_a: int, q_b: int, U_i) ->
     p = model.xy.astype(np.float64)
     q = scene.xy.astype(np.float64)
     out = np.zeros((len(cand_i), NPHI))
+    u_min = min(U_i[int(n)] for n in cand_i) if len(cand_i) else 0.0
     for r, n in enumerate(cand_i):
         n = int(n)
         out[r, 0] = (int(scene.t[n]) - f0) / 4.0
@@ -81,15 +84,16 @@ def features(model, scene, tau: int, i: int, cand_i, q_a: int, q_b: int, U_i) ->
         if q_b >= 0:
             d = (q[n] - q[q_b]) - (p[i] - p[b])
             out[r, 3], out[r, 4] = d[0] / 64.0, d[1] / 64.0
-        out[r, 6] = U_i[n]
+        out[r, 6] = U_i[n] - u_min
         out[r, 7] = i / (M - 1)
     return out
 
 
 def inputs(model, scene, i: int, cand_i, phi) -> np.ndarray:
     """x [K, 2D + 8] of one group."""
-    f = np.repeat(model.desc[i:i + 1].astype(np.float64), len(cand_i), 0)
-    g = scene.desc[np.asarray(cand_i, np.int64)].astype(np.float64)
+    D = model.desc.shape[1]
+    f = D * np.repeat(model.desc[i:i + 1].astype(np.float64), len(cand_i), 0)
+    g = D * scene.desc[np.asarray(cand_i, np.int64)].astype(np.float64)
     return np.concatenate([f, g, phi], 1)
 
 

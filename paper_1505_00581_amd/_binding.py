@@ -61,6 +61,10 @@ def load() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1505_00581_amd.build` (no CPU fallback exists)")
+        # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
+        # libstm.so binds to, so the process holds a single runtime whichever
+        # module touches the GPU first
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         P, i32 = ctypes.c_void_p, ctypes.c_int32
         lib.stm_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
@@ -261,8 +265,8 @@ class Context:
         if dev:
             import torch
             d = model.xy.device
-            cand = cand.to(torch.int32).contiguous()
-            count = count.to(torch.int32).contiguous()
+            cand = torch.as_tensor(cand, device=d).to(torch.int32).contiguous()
+            count = torch.as_tensor(count, device=d).to(torch.int32).contiguous()
             out = dict(energy32=torch.empty(n, dtype=torch.float32, device=d),
                        energy64=torch.empty(n, dtype=torch.float64, device=d),
                        energy_u64=torch.empty(n, dtype=torch.float64, device=d),

@@ -6,11 +6,13 @@
 //
 // One group = the candidates of one model point i at one offset tau; a group
 // occupies 64 rows (one per candidate slot; slots past the list are invalid).
-// Row input x = [f_i (D), g_n (D), phi (8)] with phi:
+// Row input x = [D f_i (D), D g_n (D), phi (8)] (descriptors are L1-normalised;
+// the factor D brings their entries to order 1) with phi:
 //   0  (t'_n - (tau + t_i - t_0)) / 4
 //   1,2 ((p'_n - p'_{q_a}) - (p_i - p_a)) / 64,  3,4 the same for neighbour b
 //   5  log((|p'_n - p'_{q_a}| + 1) / (|p_i - p_a| + 1))
-//   6  U(i, n)        7  i / (M - 1)
+//   6  U(i, n) - min over the group's candidates of U(i, .)
+//   7  i / (M - 1)
 // with a = i - 1, b = i + 1 (the one neighbour twice at the chain ends) and q_j
 // the candidate of neighbour j with the smallest U (lowest index on ties).
 // Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), s = w3 . h2 + b3, 128
@@ -58,6 +60,7 @@ __device__ void group_features(const ModelView& m, const SceneView& s, const flo
   qb = wave_argmin_node(cb, U + (long long)b * us, lane);
   const int k = ci.k1 + ci.k2;
   node = lane < k ? cand_node(ci, lane) : -1;
+  const int best = wave_argmin_node(ci, U + (long long)i * us, lane);
 #pragma unroll
   for (int f = 0; f < 8; ++f) phi[f] = 0.f;
   if (node < 0) return;
@@ -75,7 +78,7 @@ __device__ void group_features(const ModelView& m, const SceneView& s, const flo
     phi[3] = ((pn.x - q.x) - (pi.x - pb.x)) * (1.f / 64.f);
     phi[4] = ((pn.y - q.y) - (pi.y - pb.y)) * (1.f / 64.f);
   }
-  phi[6] = U[(long long)i * us + node];
+  phi[6] = U[(long long)i * us + node] - U[(long long)i * us + best];
   phi[7] = static_cast<float>(i) / static_cast<float>(M - 1);
 }
 
@@ -109,11 +112,12 @@ struct GatherX {
   const int32_t* node;  // [rows]
   const float* phi;     // [rows][8]
   int D;
+  float scale;          // D, the descriptor input factor
   __device__ __forceinline__ float operator()(long long r, int c) const {
     const int n = node[r];
     if (n < 0) return 0.f;
-    if (c < D) return mdesc[(long long)groups[r >> 6].y * D + c];
-    if (c < 2 * D) return sdesc[(long long)n * D + (c - D)];
+    if (c < D) return scale * mdesc[(long long)groups[r >> 6].y * D + c];
+    if (c < 2 * D) return scale * sdesc[(long long)n * D + (c - D)];
     if (c < 2 * D + 8) return phi[r * 8 + (c - 2 * D)];
     return 0.f;
   }
@@ -326,11 +330,13 @@ __global__ void k_cast_rows_bf16(const float* __restrict__ W, int rows, int ld, 
   out[e] = d < D ? to_bf16(W[(long long)o * ld + off + d]) : 0;
 }
 
-// P[n][o] = sum_d X[n][d] Wp[o][d] for o < 128: BF16 inputs on MFMA, FP32 out.
+// P[n][o] = scale * sum_d X[n][d] Wp[o][d] for o < 128: BF16 inputs on MFMA,
+// FP32 accumulation and output.
 // Xb [np][dp] zero-padded to a multiple of 16 rows; one 4-wave block per 16
 // rows, each wave 32 output columns (two 16x16 tiles).
 __global__ __launch_bounds__(256) void k_project_bf16(const uint16_t* __restrict__ Xb, int n, int dp,
-                                                     const uint16_t* __restrict__ Wb, float* __restrict__ P) {
+                                                     const uint16_t* __restrict__ Wb, float scale,
+                                                     float* __restrict__ P) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row0 = blockIdx.x * 16, lr = lane & 15, kq = (lane >> 4) * 8;
   f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(256) void k_project_bf16(const uint16_t* __restrict
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = row0 + (lane >> 4) * 4 + j;
-      if (row < n) P[(long long)row * H + wv * 32 + t * 16 + lr] = acc[t][j];
+      if (row < n) P[(long long)row * H + wv * 32 + t * 16 + lr] = scale * acc[t][j];
     }
 }
 
@@ -545,7 +551,7 @@ hipError_t launch_pruner_train(const PrunerTrain& t, hipStream_t st) {
   float* gb2 = gW2 + H * H;
   float* gw3 = gb2 + H;
   float* gb3 = gw3 + H;
-  const GatherX gx{t.mdesc, t.groups, t.sdesc, t.node, t.phi, t.D};
+  const GatherX gx{t.mdesc, t.groups, t.sdesc, t.node, t.phi, t.D, static_cast<float>(t.D)};
   const int nb = blocks(R, 64);
   hipLaunchKernelGGL((k_layer<GatherX, false>), dim3(nb), dim3(256), 0, st, gx, R, NI, W1, NI, b1,
                      (const float*)nullptr, 1, t.h1);
@@ -597,9 +603,10 @@ hipError_t launch_cast_rows_bf16(const float* W, int rows, int ld, int off, int 
   return hipGetLastError();
 }
 
-hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float* P, hipStream_t st) {
+hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float scale, float* P,
+                               hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_project_bf16, dim3(blocks(n, 16)), dim3(256), 0, st, Xb, n, dp, Wb, P);
+  hipLaunchKernelGGL(k_project_bf16, dim3(blocks(n, 16)), dim3(256), 0, st, Xb, n, dp, Wb, scale, P);
   return hipGetLastError();
 }
 

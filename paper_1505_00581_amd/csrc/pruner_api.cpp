@@ -155,8 +155,8 @@ int gradient(stm_pruner* P, const stm_points* m, const stm_points* s, const stm_
   return STM_OK;
 }
 
-// BF16 first-layer projections A = W1[:, :D] f (model) and B = W1[:, D:2D] g
-// (scene), and W2 in BF16.
+// BF16 first-layer projections A = W1[:, :D] (D f) (model) and
+// B = W1[:, D:2D] (D g) (scene), and W2 in BF16.
 int project(stm_pruner* P, const Prepared& pr) {
   stm_ctx* ctx = P->ctx;
   const int D = P->dim, M = pr.m.M, S = pr.s.S, NI = 2 * D + 8;
@@ -176,11 +176,11 @@ int project(stm_pruner* P, const Prepared& pr) {
   STM_HIP(stm::launch_cast_rows_bf16(W1, H, NI, D, D, dp, as<uint16_t>(P->wb), pr.st));
   STM_HIP(stm::launch_cast_rows_bf16(W2, H, H, 0, H, H, as<uint16_t>(P->w2b), pr.st));
   STM_HIP(stm::launch_to_bf16(pr.m.desc, M, D, Mp, as<uint16_t>(P->xm), as<float>(P->norms), pr.st));
-  STM_HIP(stm::launch_project_bf16(as<const uint16_t>(P->xm), M, dp, as<const uint16_t>(P->wa), as<float>(P->A),
-                                   pr.st));
+  STM_HIP(stm::launch_project_bf16(as<const uint16_t>(P->xm), M, dp, as<const uint16_t>(P->wa),
+                                   static_cast<float>(D), as<float>(P->A), pr.st));
   STM_HIP(stm::launch_to_bf16(pr.s.desc, S, D, Sp, as<uint16_t>(P->xs), as<float>(P->norms), pr.st));
-  STM_HIP(stm::launch_project_bf16(as<const uint16_t>(P->xs), S, dp, as<const uint16_t>(P->wb), as<float>(P->B),
-                                   pr.st));
+  STM_HIP(stm::launch_project_bf16(as<const uint16_t>(P->xs), S, dp, as<const uint16_t>(P->wb),
+                                   static_cast<float>(D), as<float>(P->B), pr.st));
   return STM_OK;
 }
 

@@ -241,7 +241,8 @@ hipError_t launch_adam(float* theta, const float* g, float* m, float* v, long lo
 // BF16 inference.
 hipError_t launch_cast_rows_bf16(const float* W, int rows, int ld, int off, int D, int dp, uint16_t* out,
                                  hipStream_t st);
-hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float* P, hipStream_t st);
+hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float scale, float* P,
+                               hipStream_t st);
 struct PrunerInfer {
   ModelView m;
   SceneView s;
@@ -254,8 +255,8 @@ struct PrunerInfer {
   const float* theta;  // FP32 parameters (biases, W1 phi columns, w3)
   int D;
   const uint16_t* w2b;  // W2 in BF16 [128][128]
-  const float* A;       // [M][128] model projection W1[:, 0:D] f
-  const float* B;       // [S][128] scene projection W1[:, D:2D] g
+  const float* A;       // [M][128] model projection W1[:, 0:D] (D f)
+  const float* B;       // [S][128] scene projection W1[:, D:2D] (D g)
   int topk;
   int32_t* cand;        // [n_groups][topk]
   int32_t* count;       // [n_groups]

@@ -124,39 +124,54 @@ def _gap_stats(e, ex, fin):
                 total_gap=float((e[fin] - ex[fin]).sum() / max(ex[fin].sum(), 1e-12)))
 
 
-def evaluate(ctx, pruner, model, scene, params, topk: int = 16, baselines: bool = True) -> dict:
+def evaluate(ctx, pruner, model, scene, params, topks=(16,), baselines: bool = True) -> dict:
     """Energy gap, recall of the exact optimum's choices and fallback rate of
-    the pruned matching (and of the baselines, with the same exact fallback)."""
+    the pruned matching at each k in topks (and of the baselines, with the same
+    exact fallback)."""
     ex = ctx.match(model, scene, params)
     e_ex, a_ex = _host(ex["energy32"]).astype(np.float64), _host(ex["assign"])
     fin = np.isfinite(e_ex)
     n, M = a_ex.shape
-    out = {"offsets": int(n), "feasible": int(fin.sum())}
-
-    pr = pruner.match(model, scene, params, topk=topk)
-    e_pr, fell = _host(pr["energy32"]).astype(np.float64), _host(pr["fell_back"]).astype(bool)
+    out = {"offsets": int(n), "feasible": int(fin.sum()), "k": {}}
     groups = np.array([(t, i) for t in range(n) for i in range(M)], np.int32)
     groups[:, 0] += ex["tau_begin"]
-    _, cand, count = pruner.infer(model, scene, params, groups, topk)
-    cand, count = cand.reshape(n, M, topk), count.reshape(n, M)
-    out["mlp"] = dict(_gap_stats(e_pr, e_ex, fin), fallback=float(fell.mean()),
-                      recall=_recall(cand, count, a_ex, fin))
-    if baselines:
-        uc, ucnt = u_ranked_lists(ctx, model, scene, params, topk)
-        ru = ctx.match_lists(model, scene, params, uc, ucnt)
-        e_u = _host(ru["energy32"]).astype(np.float64)
-        fb_u = ~np.isfinite(e_u)
-        e_u = np.where(fb_u, e_ex, e_u)
-        out["u_ranked"] = dict(_gap_stats(e_u, e_ex, fin), fallback=float(fb_u.mean()),
-                               recall=_recall(uc, ucnt, a_ex, fin))
-        pt = dataclasses.replace(params, k_max=topk)
-        rt = ctx.match(model, scene, pt)
-        e_t = _host(rt["energy32"]).astype(np.float64)
-        fb_t = ~np.isfinite(e_t)
-        e_t = np.where(fb_t, e_ex, e_t)
-        tc, tcnt = ctx.candidates(model, scene, pt)
-        out["time_nearest"] = dict(_gap_stats(e_t, e_ex, fin), fallback=float(fb_t.mean()),
-                                   recall=_recall(_host(tc), _host(tcnt), a_ex, fin))
+    for k in topks:
+        r = {}
+        pr = pruner.match(model, scene, params, topk=k)
+        e_pr, fell = _host(pr["energy32"]).astype(np.float64), _host(pr["fell_back"]).astype(bool)
+        _, cand, count = pruner.infer(model, scene, params, groups, k)
+        cand, count = cand.reshape(n, M, k), count.reshape(n, M)
+        r["mlp"] = dict(_gap_stats(e_pr, e_ex, fin), fallback=float(fell.mean()),
+                        recall=_recall(cand, count, a_ex, fin))
+        if baselines:
+            uc, ucnt = u_ranked_lists(ctx, model, scene, params, k)
+            ru = ctx.match_lists(model, scene, params, uc, ucnt)
+            e_u = _host(ru["energy32"]).astype(np.float64)
+            fb_u = ~np.isfinite(e_u)
+            e_u = np.where(fb_u, e_ex, e_u)
+            r["u_ranked"] = dict(_gap_stats(e_u, e_ex, fin), fallback=float(fb_u.mean()),
+                                 recall=_recall(uc, ucnt, a_ex, fin))
+            pt = dataclasses.replace(params, k_max=k)
+            rt = ctx.match(model, scene, pt)
+            e_t = _host(rt["energy32"]).astype(np.float64)
+            fb_t = ~np.isfinite(e_t)
+            e_t = np.where(fb_t, e_ex, e_t)
+            tc, tcnt = ctx.candidates(model, scene, pt)
+            r["time_nearest"] = dict(_gap_stats(e_t, e_ex, fin), fallback=float(fb_t.mean()),
+                                     recall=_recall(_host(tc), _host(tcnt), a_ex, fin))
+        out["k"][int(k)] = r
+    return out
+
+
+def summarise(results: list) -> dict:
+    """Means over evaluated (model, scene) pairs, per k and method."""
+    out = {}
+    for k in results[0]["k"]:
+        out[k] = {}
+        for meth in results[0]["k"][k]:
+            rows = [r["k"][k][meth] for r in results]
+            out[k][meth] = {f: round(float(np.mean([x[f] for x in rows])), 5) for f in rows[0]}
+            out[k][meth]["max_gap"] = round(float(max(x["max_gap"] for x in rows)), 5)
     return out
 
 
@@ -176,7 +191,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--topk", type=int, default=16)
+    ap.add_argument("--topk", default="16,32,48", help="comma-separated list sizes to evaluate")
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--out", default=None, help="write the trained parameters here")
     ap.add_argument("--report", default=None, help="write the evaluation as JSON here")
@@ -204,15 +219,17 @@ def main(argv=None):
         pruner.save(a.out)
     report = dict(groups=int(sum(len(it.groups) for it in items)), label_s=t1 - t0, train_s=t2 - t1,
                   loss=hist, test=[])
+    topks = tuple(int(x) for x in a.topk.split(","))
     for s in seeds(a.test_seeds):
         w = synth.config2(s)
         ds = B.DevicePoints.from_host(w.scenes[0])
         for m in w.models:
-            r = evaluate(ctx, pruner, B.DevicePoints.from_host(m), ds, w.params, topk=a.topk)
+            r = evaluate(ctx, pruner, B.DevicePoints.from_host(m), ds, w.params, topks=topks)
             r["seed"] = s
             report["test"].append(r)
-        log(f"test seed {s}: mlp gap {np.mean([r['mlp']['mean_gap'] for r in report['test']]):.4f}")
-    print(json.dumps(report))
+        log(f"test seed {s}: {json.dumps(summarise(report['test']))}")
+    report["summary"] = summarise(report["test"])
+    print(json.dumps(report["summary"]))
     if a.report:
         with open(a.report, "w") as f:
             json.dump(report, f, indent=1)

@@ -144,3 +144,15 @@ def test_match_lists_checks_arguments_before_the_device():
                              cand.ctypes.data, cnt.ctypes.data, 4, e.ctypes.data, None, None,
                              a.ctypes.data, None)
     assert rc == stm.STM_EINVAL and "context" in lib.stm_last_error().decode()
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the library binds it to torch's HIP runtime: a process that
+    touches libstm.so before torch must not end up with two runtimes."""
+    import subprocess
+    import sys
+    code = ("import paper_1505_00581_amd as s; s.load(); "
+            "print(sorted(set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l)))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         check=True).stdout.strip().splitlines()[-1]
+    assert out.count("libamdhip64") == 1, out

@@ -77,12 +77,17 @@ def test_features_hand_derived():
     U_1 = np.array([0.0, 0.5, 0.25, 0.0])
     # point i = 1 at tau = 0 (target frame 1); neighbours a = 0 (q_a = node 0),
     # b = 2 (q_b = node 3); candidate node 2 at frame 1
-    phi = PR.features(m, s, 0, 1, [2], 0, 3, U_1)[0]
+    phi = PR.features(m, s, 0, 1, [1, 2], 0, 3, U_1)[1]
     assert phi[0] == 0.0                                   # frame offset 1 - 1
     assert np.allclose(phi[1:3], [((112 - 100) - 10) / 64, ((49 - 50) - 0) / 64])
     assert np.allclose(phi[3:5], [((112 - 111) - 0) / 64, ((49 - 70) - (-20)) / 64])
     assert abs(phi[5] - math.log((math.hypot(12, -1) + 1) / (10 + 1))) < 1e-12
-    assert phi[6] == 0.25 and phi[7] == 0.5
+    # U relative to the group's best candidate: node 2 (0.25) is the best
+    assert phi[6] == 0.0 and phi[7] == 0.5
+    assert PR.features(m, s, 0, 1, [1, 2], 0, 3, U_1)[0][6] == 0.25
+    # descriptors enter scaled by their dimension
+    x = PR.inputs(m, s, 1, [1, 2], np.zeros((2, 8)))
+    assert np.allclose(x[:, :2], 2 * m.desc[1]) and np.allclose(x[1, 2:4], 2 * s.desc[2])
     # chain end: point 0 uses neighbour 1 for both sides
     phi0 = PR.features(m, s, 0, 0, [0], 1, 1, np.zeros(4))[0]
     assert np.allclose(phi0[1:3], phi0[3:5])
