@@ -147,6 +147,65 @@ def bench_batched(ctx, seed: int, runs: int, cache_path: str):
                                 "feasible": round(counts["feasible_cells"] / dt, 1)})
 
 
+def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, steps: int, topks, train_seeds, n_groups: int,
+                 epochs: int):
+    """The learned candidate pruner on the same workload: trained on labels
+    from the exact recursion on other seeds (realistic single-scene
+    workloads), then per list size k: the pruned matching's time per step
+    (inference, recursion on the pruned lists, exact fallback, re-score) and
+    its energy gap, recall and fallback rate against the exact matching, beside
+    the U-ranked and time-nearest top-k lists."""
+    import torch
+
+    import paper_1505_00581_amd as stm
+    from paper_1505_00581_amd import pruner_train as PT
+    from paper_1505_00581_amd import synth
+    p = w.params
+    t0 = time.perf_counter()
+    per_model = max(1, n_groups // (10 * len(train_seeds)))
+    items = PT.training_set(ctx, train_seeds, per_model, log=lambda m: log("  " + m))
+    t1 = time.perf_counter()
+    pr = stm.Pruner(ctx, synth.DIM)
+    pr.set_params(synth.pruner_init(synth.DIM, 0))
+    hist = PT.train(pr, items, p, epochs=epochs, log=lambda m: log("  " + m))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    n_train = int(sum(len(it.groups) for it in items))
+    del items
+    log(f"  pruner: {n_train} labelled groups in {t1 - t0:.1f}s, trained in {t2 - t1:.1f}s")
+    evals = [PT.evaluate(ctx, pr, dm, ds, p, topks=topks) for dm in dms]
+    summary = PT.summarise(evals)
+    n_match = sum(e["offsets"] for e in evals)
+    per_k = {}
+    for k in topks:
+        outs = []
+        for dm in dms:
+            outs.append(pr.match(dm, ds, p, topk=k))
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(steps):
+            for dm, o in zip(dms, outs):
+                pr.match(dm, ds, p, topk=k, out=o)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - ta) / steps
+        per_k[str(k)] = dict(ms_per_step=round(ms, 3), matchings_per_s=round(n_match / ms * 1e3, 1),
+                             speedup_vs_exact=round(exact_ms_per_step / ms, 3),
+                             mlp=summary[k]["mlp"], time_nearest=summary[k]["time_nearest"],
+                             u_ranked=summary[k]["u_ranked"])
+        log(f"  k={k}: {ms:.2f} ms/step (exact {exact_ms_per_step:.2f}), mlp {summary[k]['mlp']}, "
+            f"time-nearest {summary[k]['time_nearest']}")
+    ok = [k for k in topks if summary[k]["mlp"]["mean_gap"] <= 0.01]
+    best = min(ok) if ok else None
+    pr.close()
+    return dict(k_exact=int(p.k_max), train=dict(groups=n_train, seeds=f"{train_seeds[0]}-{train_seeds[-1]}",
+                                                 epochs=epochs, label_s=round(t1 - t0, 2),
+                                                 train_s=round(t2 - t1, 2),
+                                                 loss=[round(x, 4) for x in hist]),
+                test="the benchmark workload's own seed (held out from the training seeds)",
+                per_k=per_k, gap_target=0.01, smallest_k_within_target=best,
+                speedup_at_target=(per_k[str(best)]["speedup_vs_exact"] if best else None))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +219,13 @@ def main():
                     help="also time the batched uneven workload (persistent plan vs per-pair launches)")
     ap.add_argument("--batched-runs", type=int, default=3)
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "stm_tuning_cache.json"))
+    ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruner section")
+    ap.add_argument("--pruned-k", default="16,32,48", help="pruned list sizes to evaluate")
+    ap.add_argument("--pruned-groups", type=int, default=200000, help="training groups")
+    ap.add_argument("--pruned-epochs", type=int, default=4)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of this many MiB (a known-size "
+                         "reference for HBM traffic counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -177,6 +243,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"calibration copy: {args.calibrate_copy} MiB read, {args.calibrate_copy} MiB written")
     log("generating workload ...")
     w = synth.config2(args.seed)
     s, p = w.scenes[0], w.params
@@ -242,6 +316,12 @@ def main():
             log(f"cpu baseline failed: {ex!r}")
             cpu = dict(value=None, unit="matchings/s", cores=None, kind="oracle", sample=f"failed: {ex!r}")
 
+    pruned = None
+    if not args.no_pruned:
+        pruned = bench_pruned(ctx, w, dms, ds, ms_per_step, args.steps,
+                              tuple(int(x) for x in args.pruned_k.split(",")), list(range(100, 130)),
+                              args.pruned_groups, args.pruned_epochs)
+
     batched = None
     if args.batched:
         batched = bench_batched(ctx, args.seed, args.batched_runs, args.tune_cache)
@@ -273,6 +353,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if pruned is not None:
+        line["pruned"] = pruned
     if batched is not None:
         line["batched"] = batched
     print(json.dumps(line), flush=True)
