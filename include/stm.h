@@ -300,6 +300,16 @@ STM_API int64_t stm_pruner_num_params(int32_t dim);
 STM_API int stm_pruner_create(stm_ctx* ctx, int32_t dim, stm_pruner** out);
 STM_API void stm_pruner_destroy(stm_pruner* pruner);
 
+/* Selection rule of the kept candidates (the ranking of stm_pruner_infer and
+ * stm_match_pruned):
+ *   STM_PRUNE_SCORE         the topk highest scores (lower slot first on ties);
+ *   STM_PRUNE_FRAMES_FIRST  (default) candidates in frames nearer the shifted
+ *                           model frame first (|t'_n - (tau + t_i - t_0)|), the
+ *                           score rule among candidates of one frame distance. */
+#define STM_PRUNE_SCORE 0
+#define STM_PRUNE_FRAMES_FIRST 1
+STM_API int stm_pruner_set_rule(stm_pruner* pruner, int32_t rule);
+
 /* Copies n = stm_pruner_num_params(dim) FP32 parameters from / to host
  * memory.  Setting them also resets the Adam moments and step count. */
 STM_API int stm_pruner_set_params(stm_pruner* pruner, const float* theta, int64_t n);
@@ -332,9 +342,9 @@ STM_API int stm_pruner_train_step(stm_pruner* pruner, const stm_points* model, c
 
 /* BF16 inference over G groups: scores [G][64] (-inf for empty slots), and the
  * kept nodes cand [G][topk] (ascending; entries past count are unspecified)
- * with count [G] (min(topk, list length)).  Kept: the topk highest scores,
- * the lower slot first on equal scores.  1 <= topk <= 64.  Host outputs;
- * any may be NULL. */
+ * with count [G] (min(topk, list length)).  Kept: the first topk in the order
+ * of the pruner's selection rule.  1 <= topk <= 64.  Host outputs; any may be
+ * NULL. */
 STM_API int stm_pruner_infer(stm_pruner* pruner, const stm_points* model, const stm_points* scene,
                              const stm_params* params, const int32_t* groups, int32_t G, int32_t topk,
                              float* scores, int32_t* cand, int32_t* count, void* hip_stream);

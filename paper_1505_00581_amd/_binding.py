@@ -30,7 +30,7 @@ EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_ma
            "stm_match_batch", "stm_pruner_num_params", "stm_pruner_create", "stm_pruner_destroy",
            "stm_pruner_set_params", "stm_pruner_get_params", "stm_pruner_save", "stm_pruner_load",
            "stm_pruner_features", "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
-           "stm_match_pruned", "stm_match_lists")
+           "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule")
 
 
 class StmError(RuntimeError):
@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
         lib.stm_pruner_infer.argtypes = [P, PP, PP, PS, P, i32, i32, P, P, P, P]
         lib.stm_match_pruned.argtypes = [P, P, PP, PP, PS, i32, i32, i32, P, P, P, P, P, P]
         lib.stm_match_lists.argtypes = [P, PP, PP, PS, i32, i32, P, P, i32, P, P, P, P, P]
+        lib.stm_pruner_set_rule.argtypes = [P, i32]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
                      "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
@@ -117,7 +118,7 @@ def load() -> ctypes.CDLL:
                      "stm_pruner_create", "stm_pruner_set_params", "stm_pruner_get_params",
                      "stm_pruner_save", "stm_pruner_load", "stm_pruner_features",
                      "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
-                     "stm_match_pruned", "stm_match_lists"):
+                     "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -451,6 +452,7 @@ class Pruner:
         h = ctypes.c_void_p()
         _check(self._lib.stm_pruner_create(ctx.handle, self.dim, ctypes.byref(h)))
         self.handle = h
+        self.rule = Pruner.FRAMES_FIRST
 
     def close(self):
         if getattr(self, "handle", None):
@@ -462,6 +464,13 @@ class Pruner:
             self.close()
         except Exception:
             pass
+
+    SCORE, FRAMES_FIRST = 0, 1
+
+    def set_rule(self, rule: int):
+        """Selection rule: Pruner.SCORE or Pruner.FRAMES_FIRST (the default)."""
+        _check(self._lib.stm_pruner_set_rule(self.handle, int(rule)))
+        self.rule = int(rule)
 
     def set_params(self, theta):
         th = np.ascontiguousarray(theta, np.float32).reshape(-1)

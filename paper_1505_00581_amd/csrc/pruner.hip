@@ -330,13 +330,13 @@ __global__ void k_cast_rows_bf16(const float* __restrict__ W, int rows, int ld, 
   out[e] = d < D ? to_bf16(W[(long long)o * ld + off + d]) : 0;
 }
 
-// P[n][o] = scale * sum_d X[n][d] Wp[o][d] for o < 128: BF16 inputs on MFMA,
-// FP32 accumulation and output.
+// P[n][o] = scale * sum_d X[n][d] Wp[o][d] + bias[o] for o < 128 (bias
+// nullable): BF16 inputs on MFMA, FP32 accumulation and output.
 // Xb [np][dp] zero-padded to a multiple of 16 rows; one 4-wave block per 16
 // rows, each wave 32 output columns (two 16x16 tiles).
 __global__ __launch_bounds__(256) void k_project_bf16(const uint16_t* __restrict__ Xb, int n, int dp,
                                                      const uint16_t* __restrict__ Wb, float scale,
-                                                     float* __restrict__ P) {
+                                                     const float* __restrict__ bias, float* __restrict__ P) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row0 = blockIdx.x * 16, lr = lane & 15, kq = (lane >> 4) * 8;
   f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
@@ -354,131 +354,155 @@ __global__ __launch_bounds__(256) void k_project_bf16(const uint16_t* __restrict
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = row0 + (lane >> 4) * 4 + j;
-      if (row < n) P[(long long)row * H + wv * 32 + t * 16 + lr] = scale * acc[t][j];
+      if (row < n) {
+        const int o = wv * 32 + t * 16 + lr;
+        P[(long long)row * H + o] = scale * acc[t][j] + (bias ? bias[o] : 0.f);
+      }
     }
 }
 
+// Inference: one wave per group, no block barriers after the set-up.
+//
+// Layer 1 runs transposed, Z1^T [hidden k][candidate c], per 16 x 16 tile
+// (kt, ct): the accumulator starts at A'_i[k] + B_n[k] (A' = W1a (D f) + b1,
+// B = W1b (D g), both from the BF16 projections) and takes W1c phi on
+// v_mfma_f32_16x16x4_f32 (K = 8 as two steps, FP32).  Its accumulator layout
+// (lane l: k = 16 kt + 4 (l / 16) + j, c = 16 ct + l % 16) is used directly as
+// the B operand of layer 2 on v_mfma_f32_16x16x32_bf16: the 32-wide K block p
+// takes tiles kt = 2p and 2p + 1, so lane l supplies hidden units
+// 32p + 16h + 4 (l / 16) + j (h, j in {0,1} x {0..3}); W2 sits in LDS permuted
+// to the same order, so no data moves between the layers.
+constexpr int kInferWaves = 8;
+constexpr int kW2Row = H + 8;  // bf16 per permuted W2 row (padding against bank conflicts)
+
 struct alignas(16) InferShared {
-  uint16_t w2[H][H + 8];    // W2 in BF16, row o = output unit (padded rows)
-  uint16_t h1[64][H + 8];   // first-layer activations of the group's 64 rows
-  float w1c[H][8];          // W1 columns of phi
-  float b1[H], b2[H], w3[H], arow[H];
-  float phi[64][8];
-  int32_t node[64];
-  float part[4][64];        // per-wave partial scores
+  uint16_t w2p[H * kW2Row];   // W2 rows o, K order of the MFMA operand
+  float b2[H], w3[H];
+  float phi[kInferWaves][64][9];  // per wave: features of the 64 slots (+ pad)
+  int32_t node[kInferWaves][64];
 };
 
-// One 4-wave block per group (grid-stride): features, h1 = relu(A_i + B_n +
-// W1c phi + b1) in BF16, layer 2 on MFMA, score, top-k.  Output: the kept nodes
-// in ascending order, cand [group][topk], count [group]; scores [group][64]
-// when non-null.  Groups are (tau0 + g / M, g % M), or groups[g] when given.
-__global__ __launch_bounds__(256) void k_pruner_infer(ModelView m, SceneView s, const float* __restrict__ U,
-                                                     long long us, SearchParams sp, const int2* __restrict__ groups,
-                                                     long long n_groups, int tau0, const float* __restrict__ theta,
-                                                     int D, const uint16_t* __restrict__ w2b,
-                                                     const float* __restrict__ A, const float* __restrict__ B,
-                                                     int topk, int32_t* __restrict__ cand,
-                                                     int32_t* __restrict__ count, float* __restrict__ scores) {
+// Position of hidden unit u inside a permuted W2 row.
+__device__ __forceinline__ int w2_pos(int u) {
+  const int p = u >> 5, r = u & 31, h = r >> 4, g = (r & 15) >> 2, j = r & 3;
+  return ((p * 4 + g) * 8) + h * 4 + j;
+}
+
+__global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_pruner_infer(
+    ModelView m, SceneView s, const float* __restrict__ U, long long us, SearchParams sp,
+    const int2* __restrict__ groups, long long n_groups, int tau0, const float* __restrict__ theta, int D,
+    const float* __restrict__ A, const float* __restrict__ B, int topk, int rule, int32_t* __restrict__ cand,
+    int32_t* __restrict__ count, float* __restrict__ scores) {
   __shared__ InferShared sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int NI = 2 * D + 8;
   const float* W1 = theta;
   const float* b1 = W1 + (long long)H * NI;
-  const float* b2 = b1 + H + H * H;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
   const float* w3 = b2 + H;
   const float b3 = w3[H];
-  for (int e = tid; e < H * H; e += 256) sh.w2[e / H][e % H] = w2b[e];
-  for (int e = tid; e < H * 8; e += 256) sh.w1c[e / 8][e % 8] = W1[(long long)(e / 8) * NI + 2 * D + (e % 8)];
-  for (int e = tid; e < H; e += 256) {
-    sh.b1[e] = b1[e];
+  for (int e = tid; e < H * H; e += kInferWaves * 64) {
+    const int o = e >> 7, u = e & 127;
+    sh.w2p[o * kW2Row + w2_pos(u)] = to_bf16(W2[e]);
+  }
+  for (int e = tid; e < H; e += kInferWaves * 64) {
     sh.b2[e] = b2[e];
     sh.w3[e] = w3[e];
   }
+  // layer-1 A operands (W1 phi columns): lane l holds W1c[16 kt + l % 16][l / 16 + 4 h]
+  float w1c[8][2];
+  const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+  for (int kt = 0; kt < 8; ++kt)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) w1c[kt][h] = W1[(long long)(16 * kt + lr) * NI + 2 * D + lq + 4 * h];
   __syncthreads();
-  for (long long g = blockIdx.x; g < n_groups; g += gridDim.x) {
+
+  float(*phi)[9] = sh.phi[wv];
+  int32_t* node = sh.node[wv];
+  const long long stride = (long long)gridDim.x * kInferWaves;
+  for (long long g = (long long)blockIdx.x * kInferWaves + wv; g < n_groups; g += stride) {
     const int2 gi = groups ? groups[g] : make_int2(tau0 + static_cast<int>(g / m.M), static_cast<int>(g % m.M));
-    if (wv == 0) {
-      int n, qa, qb;
+    int n, qa, qb;
+    {
       float f[8];
       group_features(m, s, U, us, sp, gi.x, gi.y, lane, n, f, qa, qb);
-      sh.node[lane] = n;
+      node[lane] = n;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) sh.phi[lane][k] = f[k];
+      for (int k = 0; k < 8; ++k) phi[lane][k] = f[k];
     }
-    for (int e = tid; e < H; e += 256) sh.arow[e] = A[(long long)gi.y * H + e];
-    __syncthreads();
-    {  // h1: thread -> row tid / 4, columns 32 (tid % 4) .. + 31
-      const int row = tid >> 2, c0 = (tid & 3) * 32;
-      const int n = sh.node[row];
-      const float* brow = B + (long long)(n < 0 ? 0 : n) * H + c0;
-      float f[8];
+    // the wave's LDS writes above are read by other lanes of the same wave below
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // A'_i rows for this lane's hidden units: k = 16 kt + 4 lq + j
+    float4 arow[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) f[k] = sh.phi[row][k];
-#pragma unroll 8
-      for (int c = 0; c < 32; ++c) {
-        const int o = c0 + c;
-        float h = sh.arow[o] + brow[c] + sh.b1[o];
+    for (int kt = 0; kt < 8; ++kt) arow[kt] = *reinterpret_cast<const float4*>(A + (long long)gi.y * H + 16 * kt + 4 * lq);
+    float sc = -__builtin_inff();
+#pragma unroll 1
+    for (int ct = 0; ct < 4; ++ct) {
+      const int c = 16 * ct + lr;  // this lane's candidate in the tile
+      const int nc = node[c];
+      const float p0 = phi[c][lq], p1 = phi[c][lq + 4];
+      const float* brow = B + (long long)(nc < 0 ? 0 : nc) * H + 4 * lq;
+      bf16x8_t hb[4];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) h = fmaf(sh.w1c[o][k], f[k], h);
-        sh.h1[row][o] = n < 0 ? 0 : to_bf16(fmaxf(h, 0.f));
-      }
-    }
-    __syncthreads();
-    {  // layer 2: wave wv owns output columns 32 wv .. 32 wv + 31, all 64 rows
-      const int lr = lane & 15, kq = (lane >> 4) * 8;
-      float ps[4][4];
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
-        f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-        for (int k0 = 0; k0 < H; k0 += 32) {
-          const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sh.h1[rt * 16 + lr][k0 + kq]);
-#pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&sh.w2[wv * 32 + t * 16 + lr][k0 + kq]);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-          }
-        }
+      for (int kt = 0; kt < 8; ++kt) {
+        const float4 bv = *reinterpret_cast<const float4*>(brow + 16 * kt);
+        f32x4_t z = {arow[kt].x + bv.x, arow[kt].y + bv.y, arow[kt].z + bv.z, arow[kt].w + bv.w};
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(w1c[kt][0], p0, z, 0, 0, 0);
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(w1c[kt][1], p1, z, 0, 0, 0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          float v = 0.f;
-#pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const int col = wv * 32 + t * 16 + lr;
-            v = fmaf(fmaxf(acc[t][j] + sh.b2[col], 0.f), sh.w3[col], v);
-          }
-          ps[rt][j] = v;
+          const float hv = nc < 0 ? 0.f : fmaxf(z[j], 0.f);
+          hb[kt >> 1][(kt & 1) * 4 + j] = __builtin_bit_cast(__bf16, to_bf16(hv));
         }
       }
-      // sum over the 16 lanes that share rows (lane % 16 = column)
+      float part = 0.f;
+#pragma unroll 2
+      for (int ot = 0; ot < 8; ++ot) {
+        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+        const uint16_t* wrow = sh.w2p + (16 * ot + lr) * kW2Row + lq * 8;
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+        for (int pb = 0; pb < 4; ++pb) {
+          const bf16x8_t wa = *reinterpret_cast<const bf16x8_t*>(wrow + pb * 32);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, hb[pb], acc, 0, 0, 0);
+        }
+        // rows of acc: output units o = 16 ot + 4 lq + j, column: candidate c
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          float v = ps[rt][j];
-          for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off);
-          if (lr == 0) sh.part[wv][rt * 16 + (lane >> 4) * 4 + j] = v;
+          const int o = 16 * ot + 4 * lq + j;
+          part = fmaf(fmaxf(acc[j] + sh.b2[o], 0.f), sh.w3[o], part);
         }
-    }
-    __syncthreads();
-    if (wv == 0) {
-      const int n = sh.node[lane];
-      const float sc = n < 0 ? -__builtin_inff() : sh.part[0][lane] + sh.part[1][lane] + sh.part[2][lane] +
-                                                      sh.part[3][lane] + b3;
-      if (scores) scores[g * 64 + lane] = sc;
-      // rank: candidates with a higher score, or an equal score and a lower slot
-      int rank = 0;
-      for (int j = 0; j < 64; ++j) {
-        const float o = __shfl(sc, j);
-        rank += (o > sc) || (o == sc && j < lane);
       }
-      const bool keep = n >= 0 && rank < topk;
-      const unsigned long long mask = __ballot(keep);
-      const int pos = __popcll(mask & ((1ull << lane) - 1ull));
-      if (keep) cand[g * topk + pos] = n;
-      if (lane == 0) count[g] = __popcll(mask);
+      part += __shfl_xor(part, 16);
+      part += __shfl_xor(part, 32);
+      if (ct == lq) sc = part + b3;  // lane l = 16 ct + l % 16 owns candidate l
     }
-    __syncthreads();
+    if (n < 0) sc = -__builtin_inff();
+    if (scores) scores[g * 64 + lane] = sc;
+    // rank: candidates ahead in the selection order.  Score rule: a higher
+    // score, or an equal score and a lower slot.  Frames-first rule: a frame
+    // nearer the shifted model frame, then the score rule inside a frame.
+    const int df = n < 0 ? 0x7fffffff : abs(s.t[n] - (gi.x + m.t[gi.y] - m.t[0]));
+    const int key = rule ? df : 0;
+    int rank = 0;
+    for (int j = 0; j < 64; ++j) {
+      const float o = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sc), j));
+      const int ok = __builtin_amdgcn_readlane(key, j);
+      rank += (ok < key) || (ok == key && ((o > sc) || (o == sc && j < lane)));
+    }
+    const bool keep = n >= 0 && rank < topk;
+    const unsigned long long mask = __ballot(keep);
+    const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+    if (keep) cand[g * topk + pos] = n;
+    if (lane == 0) count[g] = __popcll(mask);
+    // every lane has read this group's LDS rows before the next group rewrites them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -603,10 +627,10 @@ hipError_t launch_cast_rows_bf16(const float* W, int rows, int ld, int off, int 
   return hipGetLastError();
 }
 
-hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float scale, float* P,
-                               hipStream_t st) {
+hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float scale,
+                               const float* bias, float* P, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_project_bf16, dim3(blocks(n, 16)), dim3(256), 0, st, Xb, n, dp, Wb, scale, P);
+  hipLaunchKernelGGL(k_project_bf16, dim3(blocks(n, 16)), dim3(256), 0, st, Xb, n, dp, Wb, scale, bias, P);
   return hipGetLastError();
 }
 
@@ -615,9 +639,11 @@ hipError_t launch_pruner_infer(const PrunerInfer& q, hipStream_t st) {
   int n_cu = 256, dev = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  const long long grid = q.n_groups < (long long)n_cu * 8 ? q.n_groups : (long long)n_cu * 8;
-  hipLaunchKernelGGL(k_pruner_infer, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st, q.m, q.s, q.U, q.us, q.sp,
-                     q.groups, q.n_groups, q.tau0, q.theta, q.D, q.w2b, q.A, q.B, q.topk, q.cand, q.count, q.scores);
+  const long long want = (q.n_groups + kInferWaves - 1) / kInferWaves;
+  const long long grid = want < (long long)n_cu * 2 ? want : (long long)n_cu * 2;
+  hipLaunchKernelGGL(k_pruner_infer, dim3(static_cast<unsigned>(grid)), dim3(kInferWaves * 64), 0, st, q.m, q.s,
+                     q.U, q.us, q.sp, q.groups, q.n_groups, q.tau0, q.theta, q.D, q.A, q.B, q.topk, q.rule, q.cand,
+                     q.count, q.scores);
   return hipGetLastError();
 }
 

@@ -27,10 +27,11 @@ struct stm_pruner {
   int dim = 0;
   long long n = 0;
   long long step = 0;  // Adam steps taken since the parameters were set
+  int rule = STM_PRUNE_FRAMES_FIRST;
   DevBuf theta, grad, am, av;
   // per-call scratch
   DevBuf groups, labels, node, phi, q, h1, h2, dz1, dz2, ds, loss, scores, part;
-  DevBuf wa, wb, w2b, A, B, xm, xs, norms, cand, count;
+  DevBuf wa, wb, A, B, xm, xs, norms, cand, count;
   DevBuf taus, f32, f64, fu, fas, fell;
 };
 
@@ -155,8 +156,8 @@ int gradient(stm_pruner* P, const stm_points* m, const stm_points* s, const stm_
   return STM_OK;
 }
 
-// BF16 first-layer projections A = W1[:, :D] (D f) (model) and
-// B = W1[:, D:2D] (D g) (scene), and W2 in BF16.
+// BF16 first-layer projections A = W1[:, :D] (D f) + b1 (model) and
+// B = W1[:, D:2D] (D g) (scene).
 int project(stm_pruner* P, const Prepared& pr) {
   stm_ctx* ctx = P->ctx;
   const int D = P->dim, M = pr.m.M, S = pr.s.S, NI = 2 * D + 8;
@@ -164,23 +165,20 @@ int project(stm_pruner* P, const Prepared& pr) {
   int rc;
   if ((rc = grow(ctx, P->wa, (size_t)H * dp * 2, pr.st))) return rc;
   if ((rc = grow(ctx, P->wb, (size_t)H * dp * 2, pr.st))) return rc;
-  if ((rc = grow(ctx, P->w2b, (size_t)H * H * 2, pr.st))) return rc;
   if ((rc = grow(ctx, P->xm, (size_t)Mp * dp * 2, pr.st))) return rc;
   if ((rc = grow(ctx, P->xs, (size_t)Sp * dp * 2, pr.st))) return rc;
   if ((rc = grow(ctx, P->norms, (size_t)std::max(Mp, Sp) * sizeof(float), pr.st))) return rc;
   if ((rc = grow(ctx, P->A, (size_t)M * H * sizeof(float), pr.st))) return rc;
   if ((rc = grow(ctx, P->B, (size_t)S * H * sizeof(float), pr.st))) return rc;
   const float* W1 = as<const float>(P->theta);
-  const float* W2 = W1 + (long long)H * NI + H;
   STM_HIP(stm::launch_cast_rows_bf16(W1, H, NI, 0, D, dp, as<uint16_t>(P->wa), pr.st));
   STM_HIP(stm::launch_cast_rows_bf16(W1, H, NI, D, D, dp, as<uint16_t>(P->wb), pr.st));
-  STM_HIP(stm::launch_cast_rows_bf16(W2, H, H, 0, H, H, as<uint16_t>(P->w2b), pr.st));
   STM_HIP(stm::launch_to_bf16(pr.m.desc, M, D, Mp, as<uint16_t>(P->xm), as<float>(P->norms), pr.st));
   STM_HIP(stm::launch_project_bf16(as<const uint16_t>(P->xm), M, dp, as<const uint16_t>(P->wa),
-                                   static_cast<float>(D), as<float>(P->A), pr.st));
+                                   static_cast<float>(D), W1 + (long long)H * NI, as<float>(P->A), pr.st));
   STM_HIP(stm::launch_to_bf16(pr.s.desc, S, D, Sp, as<uint16_t>(P->xs), as<float>(P->norms), pr.st));
   STM_HIP(stm::launch_project_bf16(as<const uint16_t>(P->xs), S, dp, as<const uint16_t>(P->wb),
-                                   static_cast<float>(D), as<float>(P->B), pr.st));
+                                   static_cast<float>(D), nullptr, as<float>(P->B), pr.st));
   return STM_OK;
 }
 
@@ -196,10 +194,10 @@ stm::PrunerInfer infer_args(stm_pruner* P, const Prepared& pr, int topk) {
   q.tau0 = 0;
   q.theta = as<const float>(P->theta);
   q.D = P->dim;
-  q.w2b = as<const uint16_t>(P->w2b);
   q.A = as<const float>(P->A);
   q.B = as<const float>(P->B);
   q.topk = topk;
+  q.rule = P->rule;
   q.cand = nullptr;
   q.count = nullptr;
   q.scores = nullptr;
@@ -391,11 +389,20 @@ void stm_pruner_destroy(stm_pruner* P) {
   }
   DevBuf* bufs[] = {&P->theta, &P->grad, &P->am,  &P->av,    &P->groups, &P->labels, &P->node,  &P->phi,
                     &P->q,     &P->h1,   &P->h2,  &P->dz1,   &P->dz2,    &P->ds,     &P->loss,  &P->scores,
-                    &P->part,  &P->wa,   &P->wb,  &P->w2b,   &P->A,      &P->B,      &P->xm,    &P->xs,
+                    &P->part,  &P->wa,   &P->wb,  &P->A,      &P->B,      &P->xm,    &P->xs,
                     &P->norms, &P->cand, &P->count, &P->taus, &P->f32,   &P->f64,    &P->fu,    &P->fas,
                     &P->fell};
   for (DevBuf* b : bufs) release(*b);
   delete P;
+}
+
+int stm_pruner_set_rule(stm_pruner* P, int32_t rule) {
+  err().clear();
+  int rc = check_pruner(P);
+  if (rc) return rc;
+  if (rule != STM_PRUNE_SCORE && rule != STM_PRUNE_FRAMES_FIRST) return fail(STM_EINVAL, "unknown selection rule");
+  P->rule = rule;
+  return STM_OK;
 }
 
 int stm_pruner_set_params(stm_pruner* P, const float* theta, int64_t n) {

@@ -241,8 +241,8 @@ hipError_t launch_adam(float* theta, const float* g, float* m, float* v, long lo
 // BF16 inference.
 hipError_t launch_cast_rows_bf16(const float* W, int rows, int ld, int off, int D, int dp, uint16_t* out,
                                  hipStream_t st);
-hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float scale, float* P,
-                               hipStream_t st);
+hipError_t launch_project_bf16(const uint16_t* Xb, int n, int dp, const uint16_t* Wb, float scale,
+                               const float* bias, float* P, hipStream_t st);
 struct PrunerInfer {
   ModelView m;
   SceneView s;
@@ -252,12 +252,12 @@ struct PrunerInfer {
   const int2* groups;  // null: groups (tau0 + g / M, g % M)
   long long n_groups;
   int tau0;
-  const float* theta;  // FP32 parameters (biases, W1 phi columns, w3)
+  const float* theta;  // FP32 parameters (W1 phi columns, W2, b2, w3, b3)
   int D;
-  const uint16_t* w2b;  // W2 in BF16 [128][128]
-  const float* A;       // [M][128] model projection W1[:, 0:D] (D f)
+  const float* A;       // [M][128] model projection W1[:, 0:D] (D f) + b1
   const float* B;       // [S][128] scene projection W1[:, D:2D] (D g)
   int topk;
+  int rule;             // 0: top-k by score; 1: nearest frames first, score inside
   int32_t* cand;        // [n_groups][topk]
   int32_t* count;       // [n_groups]
   float* scores;        // [n_groups][64], nullable

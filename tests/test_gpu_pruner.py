@@ -12,6 +12,7 @@
   nothing is pruned, equal to the oracle's recursion on the same lists
   otherwise, exact fallback rows identical to stm_match.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -235,10 +236,11 @@ def test_training_lowers_the_loss(ctx, mid):
     pr.close()
 
 
-@pytest.mark.parametrize("which", ["small", "mid"])
-def test_infer_bf16_and_topk(ctx, request, which):
+@pytest.mark.parametrize("which,rule", [("small", 0), ("mid", 0), ("small", 1), ("mid", 1)])
+def test_infer_bf16_and_topk(ctx, request, which, rule):
     model, scene, p = request.getfixturevalue(which)
     pr = stm.Pruner(ctx, model.dim)
+    pr.set_rule(rule)
     pr.set_params(synth.pruner_init(model.dim, 6))
     groups = random_groups(model, scene, 32, seed=6)
     node, _, _ = pr.features(model, scene, p, groups)
@@ -253,17 +255,42 @@ def test_infer_bf16_and_topk(ctx, request, which):
         assert err <= 0.03 * scale, (err, scale)
         for g in range(len(groups)):
             k = int(valid[g].sum())
-            order = sorted(range(k), key=lambda a: (-sb[g, a], a))[:topk]
+            tau, i = groups[g]
+            df = np.abs(scene.t[node[g, :k]] - (tau + model.t[i] - model.t[0]))
+            order = sorted(range(k), key=lambda a: ((df[a] if rule else 0), -sb[g, a], a))[:topk]
             want = np.sort(node[g, order])
             assert count[g] == min(topk, k)
             np.testing.assert_array_equal(cand[g, :count[g]], want)
     say(f"  {which}: bf16 score err {err:.3e} (scale {scale:.3f})")
-    # the zero network scores every candidate 0: the first slots are kept
+    # the zero network scores every candidate 0: the score rule keeps the
+    # first slots, the frames-first rule the windowed rule's first k
     pr.set_params(np.zeros(pr.n_params, np.float32))
     sb, cand, count = pr.infer(model, scene, p, groups, 4)
     for g in range(len(groups)):
         k = int((node[g] >= 0).sum())
-        np.testing.assert_array_equal(cand[g, :count[g]], node[g, :min(4, k)])
+        if rule == 0:
+            np.testing.assert_array_equal(cand[g, :count[g]], node[g, :min(4, k)])
+        else:
+            want = oracle.candidate_list(model, scene, dataclasses.replace(p, k_max=4), int(groups[g][0]),
+                                           int(groups[g][1]))
+            np.testing.assert_array_equal(cand[g, :count[g]], want)
+    pr.close()
+
+
+@pytest.mark.parametrize("which,topk", [("small", 6), ("mid", 16)])
+def test_zero_network_frames_first_is_the_windowed_rule(ctx, request, which, topk):
+    """With every score equal, the frames-first selection keeps exactly the
+    windowed rule's first k, so the pruned matching is stm_match at k_max = k
+    wherever that is feasible (elsewhere the exact fallback answers)."""
+    model, scene, p = request.getfixturevalue(which)
+    pr = stm.Pruner(ctx, model.dim)
+    pr.set_params(np.zeros(pr.n_params, np.float32))
+    got = pr.match(model, scene, p, topk=topk)
+    small = ctx.match(model, scene, dataclasses.replace(p, k_max=topk))
+    ok = np.isfinite(small["energy32"])
+    assert (got["fell_back"][ok] == 0).all() and (got["fell_back"][~ok] == 1).all()
+    for k in ("energy32", "energy64", "assign"):
+        np.testing.assert_array_equal(got[k][ok], small[k][ok])
     pr.close()
 
 
@@ -328,11 +355,15 @@ def test_pruned_keeping_everything_equals_exact(ctx, small):
     pr.close()
 
 
-@pytest.mark.parametrize("which,topk", [("small", 6), ("mid", 16), ("small", 1)])
-def test_pruned_against_oracle_and_fallback(ctx, request, which, topk):
+@pytest.mark.parametrize("which,topk,rule", [("small", 6, 1), ("mid", 16, 1), ("small", 6, 0), ("small", 1, 0)])
+def test_pruned_against_oracle_and_fallback(ctx, request, which, topk, rule):
+    """Pruned matchings against the oracle on the same lists; with the score
+    rule and one candidate per point most offsets are infeasible and must be
+    answered by the exact fallback."""
     import torch
     model, scene, p = request.getfixturevalue(which)
     pr = stm.Pruner(ctx, model.dim)
+    pr.set_rule(rule)
     pr.set_params(synth.pruner_init(model.dim, 3))
     ex = ctx.match(model, scene, p)
     got = pr.match(model, scene, p, topk=topk)
@@ -364,7 +395,7 @@ def test_pruned_against_oracle_and_fallback(ctx, request, which, topk):
             for i in range(M):
                 assert got["assign"][t, i] in cand[t, i, :count[t, i]]
     gap = (got["energy32"][fin] - ex["energy32"][fin]) / np.maximum(ex["energy32"][fin], 1e-6)
-    say(f"  {which} top-{topk}: fallback {fell.mean():.3f}, mean gap {gap.mean():.4f}, "
+    say(f"  {which} top-{topk} rule {rule}: fallback {fell.mean():.3f}, mean gap {gap.mean():.4f}, "
         f"{len(taus)} offsets checked against the oracle")
     if topk == 1:
         assert fell.any()
