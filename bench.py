@@ -95,6 +95,7 @@ def cpu_baseline(workload, target_s: float, seed: int):
     threads = oracle.num_threads()
     done, elapsed, pos = 0, 0.0, 0
     batch = threads
+    solved = []  # (model, offset, FP64 optimum, assignment) of every sampled matching
     while elapsed < target_s and pos < len(order):
         sel = [pairs[j] for j in order[pos:pos + batch]]
         pos += len(sel)
@@ -103,7 +104,9 @@ def cpu_baseline(workload, target_s: float, seed: int):
             by_model.setdefault(mi, []).append(t)
         t0 = time.perf_counter()
         for mi, taus in by_model.items():
-            oracle.match(workload.models[mi], s, p, taus=np.array(sorted(taus), np.int32))
+            taus = np.array(sorted(taus), np.int32)
+            r = oracle.match(workload.models[mi], s, p, taus=taus)
+            solved += [(mi, int(t), float(e), a) for t, e, a in zip(taus, r["energy"], r["assign"])]
         dt = time.perf_counter() - t0
         elapsed += dt
         done += len(sel)
@@ -111,11 +114,37 @@ def cpu_baseline(workload, target_s: float, seed: int):
         # grow the next batch towards the time target
         per = dt / max(len(sel), 1)
         batch = int(max(threads, min(8 * batch, (target_s - elapsed) / max(per, 1e-6))))
-    return dict(value=done / elapsed if elapsed > 0 else None, unit="matchings/s", cores=threads,
+    return solved, dict(value=done / elapsed if elapsed > 0 else None, unit="matchings/s", cores=threads,
                 kind="oracle",
                 sample=(f"{done} (model, offset) matchings drawn uniformly (seed {seed + 77}) from "
                         f"the same workload, FP64 C oracle (literal backward recursion), "
                         f"OpenMP over offsets, {elapsed:.1f}s"))
+
+
+def sample_parity(solved, outs, outs_bf):
+    """The FP32 and split-precision GPU results on the matchings the CPU
+    baseline solved: relative energy error against the FP64 optimum, the gap of
+    the FP64 re-score of the GPU assignment above it, and the fraction of
+    identical assignments."""
+    rows = {}
+    for name, o in (("fp32", outs), ("bf16_unary", outs_bf)):
+        e32 = [o_["energy32"].cpu().numpy() for o_ in o]
+        e64 = [o_["energy64"].cpu().numpy() for o_ in o]
+        asg = [o_["assign"].cpu().numpy() for o_ in o]
+        err, gap, same, n = [], [], 0, 0
+        for mi, t, e, a in solved:
+            if not np.isfinite(e):
+                continue
+            n += 1
+            err.append(abs(float(e32[mi][t]) - e) / max(abs(e), 1e-12))
+            gap.append((float(e64[mi][t]) - e) / max(abs(e), 1e-12))
+            same += int(np.array_equal(asg[mi][t], a))
+        rows[name] = dict(matchings=n, max_rel_err=float(max(err)) if err else None,
+                          mean_rel_err=float(np.mean(err)) if err else None,
+                          max_rescored_gap=float(max(gap)) if gap else None,
+                          mean_rescored_gap=float(np.mean(gap)) if gap else None,
+                          assignment_agreement=same / n if n else None)
+    return rows
 
 
 def bench_batched(ctx, seed: int, runs: int, cache_path: str):
@@ -359,10 +388,27 @@ def main():
                     kernel="k_dp (fast variant)", avg_launch_ms=round(1e3 * avg_launch_s, 4),
                     ops_per_relax=OPS_PER_RELAX)
 
-    cpu = None
+    # split precision: the same step with the unary table from BF16 MFMA dot products
+    pb = dataclasses.replace(p, unary_bf16=True)
+    outs_bf = [{k: torch.empty_like(v) for k, v in o.items() if torch.is_tensor(v)} for o in outs]
+    for dm, o in zip(dms, outs_bf):
+        ctx.match(dm, ds, pb, out=o)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(args.steps):
+        for dm, o in zip(dms, outs_bf):
+            ctx.match(dm, ds, pb, out=o)
+    torch.cuda.synchronize()
+    ms_bf = 1e3 * (time.perf_counter() - tb) / args.steps
+    split = dict(ms_per_step=round(ms_bf, 3), value=round(n_match / ms_bf * 1e3, 2), unit="matchings/s",
+                 unary="BF16 MFMA dot products (D padded 162->192), FP32 norms and accumulation")
+    log(f"split precision: {ms_bf:.2f} ms/step")
+
+    cpu, parity = None, None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(w, args.cpu_seconds, args.seed)
+            solved, cpu = cpu_baseline(w, args.cpu_seconds, args.seed)
+            parity = sample_parity(solved, outs, outs_bf)
         except Exception as ex:  # report, do not hide the GPU result
             log(f"cpu baseline failed: {ex!r}")
             cpu = dict(value=None, unit="matchings/s", cores=None, kind="oracle", sample=f"failed: {ex!r}")
@@ -403,6 +449,8 @@ def main():
         "dp_kernel_share": round(prof["dp_ms"] / 1e3 / elapsed, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "split_precision": split,
+        "parity_on_cpu_sample": parity,
     }
     if pruned is not None:
         line["pruned"] = pruned
