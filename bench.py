@@ -286,6 +286,82 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, steps: int, topks, t
                 speedup_at_target=(per_k[str(best)]["speedup_vs_exact"] if best else None))
 
 
+def bench_paper_blocks(ctx, steps: int):
+    """The paper's own streaming workload (Table 2): 50 models of M=30 points
+    against a 723-frame video of 754 points, each model matched against every
+    overlapping block of 60 consecutive points (one candidate list per block,
+    the same for every model point; stm_match_lists).  Reported per frame (one
+    new block per frame) beside the paper's GTX580 figure, as context only."""
+    import torch
+
+    import paper_1505_00581_amd as stm
+    from paper_1505_00581_amd import synth
+    w = synth.paper_blocks(0)
+    s, p = w.scenes[0], w.params
+    ds = stm.DevicePoints.from_host(s)
+    dms = [stm.DevicePoints.from_host(m) for m in w.models]
+    n_blocks = min(min(int(s.n_frames - (m.t[-1] - m.t[0])) for m in w.models), s.n - 59)
+    lists, relax, outs = [], 0, []
+    for m in w.models:
+        cand, cnt = synth.block_lists(m, s, n_blocks)
+        lists.append((torch.as_tensor(cand, device="cuda"), torch.as_tensor(cnt, device="cuda")))
+    # feasible relaxations: lists are the same for every point, so per step
+    # sum over middle nodes of (admissible predecessors) x (admissible successors)
+    t = s.t.astype(np.int64)
+    for b in range(n_blocks):
+        f = t[b:b + 60]
+        d = f[None, :] - f[:, None]          # d[u, v] = frame(v) - frame(u)
+        adm = (d >= 1) & (d < p.T)
+        per_step = int((adm.sum(0) * adm.sum(1)).sum())
+        relax += per_step * sum(m.n - 2 for m in w.models)
+
+    def step():
+        return [ctx.match_lists(dm, ds, p, c, n, 0, n_blocks) for dm, (c, n) in zip(dms, lists)]
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    n = n_blocks * len(w.models)
+    log(f"  paper blocks: {n} matchings, {ms:.2f} ms per pass, {ms / n_blocks:.4f} ms per frame")
+    return dict(workload="paper streaming blocks: 50 models M=30 (160x120) vs a 723-frame video of "
+                         "754 points, every overlapping block of 60 consecutive points (one per frame)",
+                matchings=n, blocks=n_blocks, ms_per_pass=round(ms, 3), value=round(n / ms * 1e3, 1),
+                unit="matchings/s", ms_per_frame_50_models=round(ms / n_blocks, 5),
+                feasible_relax_per_s=round(relax / ms * 1e3, 1),
+                paper_context="GTX580: 3.5 ms per frame for 50 models on 60-node blocks (4 ms per model per "
+                              "block); different hardware and inputs, context only")
+
+
+def bench_t_sweep(ctx, w, dms, ds, steps: int, values):
+    """Run time of the exact step against the closeness limit T (the run-time
+    half of the paper's Fig. 7; T <= 0 means no limit), on the same workload."""
+    import torch
+    out = []
+    for T in values:
+        pt = dataclasses.replace(w.params, T=int(T))
+        work = dict(feasible_relax=0, feasible_cells=0)
+        for dm in dms:
+            c = ctx.count_work(dm, ds, pt)
+            for k in work:
+                work[k] += c[k]
+        outs = [ctx.match(dm, ds, pt) for dm in dms]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for dm, o in zip(dms, outs):
+                ctx.match(dm, ds, pt, out=o)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        out.append(dict(T=int(T), ms_per_step=round(ms, 3), feasible_relax=work["feasible_relax"],
+                        feasible_relax_per_s=round(work["feasible_relax"] / ms * 1e3, 1)))
+        log(f"  T={T}: {ms:.2f} ms/step, {work['feasible_relax']:.3e} feasible relaxations")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +376,10 @@ def main():
     ap.add_argument("--batched-runs", type=int, default=3)
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "stm_tuning_cache.json"))
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruner section")
+    ap.add_argument("--t-sweep", default="", help="comma-separated closeness limits T to time "
+                    "(e.g. 2,4,6,8,10,0; 0 = no limit)")
+    ap.add_argument("--paper-blocks", action="store_true",
+                    help="also time the paper's own streaming workload (60-point blocks)")
     ap.add_argument("--pruned-k", default="16,32,48", help="pruned list sizes to evaluate")
     ap.add_argument("--pruned-groups", type=int, default=200000, help="training groups")
     ap.add_argument("--pruned-epochs", type=int, default=4)
@@ -419,6 +499,14 @@ def main():
                               tuple(int(x) for x in args.pruned_k.split(",")), list(range(100, 130)),
                               args.pruned_groups, args.pruned_epochs)
 
+    sweep = None
+    if args.t_sweep:
+        sweep = bench_t_sweep(ctx, w, dms, ds, args.steps, [int(x) for x in args.t_sweep.split(",")])
+
+    blocks = None
+    if args.paper_blocks:
+        blocks = bench_paper_blocks(ctx, args.steps)
+
     batched = None
     if args.batched:
         batched = bench_batched(ctx, args.seed, args.batched_runs, args.tune_cache)
@@ -456,6 +544,10 @@ def main():
         line["pruned"] = pruned
     if batched is not None:
         line["batched"] = batched
+    if blocks is not None:
+        line["paper_blocks"] = blocks
+    if sweep is not None:
+        line["t_sweep"] = sweep
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -221,6 +221,43 @@ def tiny(seed: int, m: int | None = None, max_per_frame: int = 3, n_frames: int 
     return Workload([model], [scene], p, [], f"tiny_{seed}")
 
 
+def paper_blocks(seed: int = 0, n_models: int = 50, block: int = 60) -> Workload:
+    """The paper's own timing workload (Table 2, streaming mode): models of
+    M=30 points (160x120 px, frames in 0..45) against one video of 723 frames
+    with 754 points (about one per frame, as KTH's interest points are), matched
+    against overlapping blocks of `block` consecutive scene points (about 55
+    frames).  Five models have one planted copy each; the rest is clutter.
+    W and K do not apply: each block is one candidate list for every point."""
+    rng = _rng(seed)
+    p = Params(window=0, k_max=block)
+    models = [make_model(rng, 30, 160.0, 120.0, p.T, frame_hi=45) for _ in range(n_models)]
+    n_frames, n_points, n_planted = 723, 754, min(5, n_models)
+    counts = rng.multinomial(n_points - 30 * n_planted, np.full(n_frames, 1.0 / n_frames))
+    xy, t, d = clutter(rng, counts, 160.0, 120.0)
+    parts = ([xy], [t], [d])
+    planted = []
+    for mi in range(n_planted):
+        pxy, pt, pd, tau = plant_copy(rng, models[mi], n_frames, 160.0, 120.0)
+        parts[0].append(pxy)
+        parts[1].append(pt)
+        parts[2].append(pd)
+        planted.append((mi, 0, tau))
+    scene = assemble_scene(*parts, n_frames)
+    return Workload(models, [scene], p, planted, f"paper_blocks_m30_s{n_points}_b{block}")
+
+
+def block_lists(model: Points, scene: Points, n_blocks: int, block: int = 60):
+    """Candidate lists of the block workload: offset b lists scene points
+    b .. b + block - 1 for every model point.  Returns cand [n, M, block] and
+    count [n, M] (int32)."""
+    M = model.n
+    base = np.arange(block, dtype=np.int32)
+    cand = np.broadcast_to((np.arange(n_blocks, dtype=np.int32)[:, None] + base[None, :])[:, None, :],
+                           (n_blocks, M, block)).copy()
+    count = np.full((n_blocks, M), block, np.int32)
+    return cand, count
+
+
 def pruner_init(dim: int = DIM, seed: int = 0, hidden: int = 128) -> np.ndarray:
     """Initial weights of the learned candidate pruner, packed float32
     [W1 (hidden x (2 dim + 8)), b1, W2 (hidden x hidden), b2, w3, b3]:

@@ -318,3 +318,20 @@ def test_config2_full_size(ctx):
         st = check(m, s, p, res, ora, rows=taus)
         say(f"  model {mi} M={m.n}: n_tau={e32.size} {st}")
     assert total > 13000
+
+
+@pytest.mark.parametrize("T", [4, 0])
+def test_closeness_variants_at_realistic_sizes(ctx, T):
+    """K = 64 lists of the realistic workload (one model, the first 300
+    frames) with a tight and with no closeness limit, sampled offsets against
+    the oracle: the limits the run-time sweep over T uses."""
+    w = synth.config2(31, n_models=1)
+    m, s = w.models[0], w.scenes[0]
+    keep = s.t < 300
+    s = synth.Points(np.ascontiguousarray(s.xy[keep]), np.ascontiguousarray(s.t[keep]),
+                     np.ascontiguousarray(s.desc[keep]), 300)
+    p = dataclasses.replace(w.params, T=T)
+    res = ctx.match(m, s, p)
+    n = res["energy32"].shape[0]
+    taus = np.unique(np.linspace(0, n - 1, 6).astype(np.int32))
+    check(m, s, p, res, oracle.match(m, s, p, taus=taus), rows=taus)
