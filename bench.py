@@ -5,9 +5,11 @@ Workload (one step = the whole path over one batch): 10 models with M in
 50..100 points against one 1500-frame scene (320x240 px, 20 clutter points
 per frame, 5 planted copies per model, ~33.8k points, 162-D descriptors),
 K = 64 candidates per point within +-3 frames, T = 10, every offset of every
-model (~13.9k matchings).  Per model one stm_match call runs the unary table,
-the FP32 min-sum recursion, backtracking and the FP64 re-score, with inputs
-and outputs resident in device memory.
+model (~13.9k matchings).  A step is one replay of a captured plan: the unary
+tables, one persistent launch of the FP32 min-sum recursion over every
+(model, offset) with backtracking fused, and the FP64 re-score, with inputs
+and outputs resident in device memory.  The same step as one stm_match call
+per model is timed beside it (per_model_launches).
 
 Prints one JSON line: matchings/s, DP cells/s and relaxations/s, the
 roofline of the recursion kernel (VALU-bound) from HIP events around its
@@ -46,6 +48,7 @@ def log(*a):
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_dp_realistic_single_scene_traffic.md")
+TRAFFIC_FILE_PLAN = os.path.join(HERE, "profiles", "k_dp_persistent_realistic_single_scene_traffic.md")
 DP_SOURCES = [os.path.join(HERE, "paper_1505_00581_amd", "csrc", f) for f in ("dp.hip", "stm_internal.h")]
 
 
@@ -57,13 +60,13 @@ def dp_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the recursion kernel from the committed counter
+def measured_traffic(path):
+    """HBM bytes per launch of a recursion kernel from its committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy of
     known size), or None when the summary is missing or the kernel sources have
     changed since the counters were taken."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     vals = {}
@@ -451,22 +454,53 @@ def main():
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     elapsed = t1 - t0
+    loop_ms = 1e3 * elapsed / args.steps
+    log(f"per-model launches, {args.steps} steps: {loop_ms:.2f} ms/step, "
+        f"{n_match * args.steps / elapsed:.1f} matchings/s, DP kernel {prof}")
+    peak = VALU_PEAK_OPS / 1e12
+
+    def roof(prof_, launches_per_step, kernel, traffic):
+        # algorithmic lane-ops per launch over the launch's average duration
+        # (HIP events on the stream the kernel runs on)
+        avg_s = prof_["dp_ms"] / 1e3 / max(prof_["dp_launches"], 1)
+        ach = counts["feasible_relax"] * OPS_PER_RELAX / launches_per_step / avg_s / 1e12
+        return dict(bound="alu", achieved=round(ach, 3), peak=round(peak, 3), unit="TOP/s",
+                    frac=round(ach / peak, 4), traffic=traffic, kernel=kernel,
+                    avg_launch_ms=round(1e3 * avg_s, 4), ops_per_relax=OPS_PER_RELAX)
+
+    per_model = dict(ms_per_step=round(loop_ms, 3), value=round(n_match / loop_ms * 1e3, 2),
+                     unit="matchings/s", launches="one stm_match call per model (10 recursion launches "
+                                                  "per step, then backtracking and re-score per model)",
+                     roofline=roof(prof, prof["dp_launches"] / args.steps, "k_dp (fast variant)",
+                                   measured_traffic(TRAFFIC_FILE)))
+
+    # the measured configuration: every model's offsets in one persistent
+    # launch, captured once as a HIP graph and replayed (backtracking fused)
+    pairs = np.array([(i, 0) for i in range(len(dms))], np.int32)
+    plan = stm.Plan(ctx, dms, [ds], pairs, p)
+    tuning = plan.autotune(args.tune_cache)
+    pout = plan.run()
+    for _ in range(args.warmup):
+        plan.run(pout)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run(pout)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pprof = ctx.profile_read()
+    ctx.profile_enable(False)
+    elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = n_match * args.steps / elapsed
-    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} matchings/s, "
-        f"DP kernel {prof}")
-
-    # roofline of the recursion kernel: algorithmic lane-ops per launch over its
-    # average duration (HIP events on its stream)
-    launches_per_step = prof["dp_launches"] / args.steps
-    avg_launch_s = prof["dp_ms"] / 1e3 / max(prof["dp_launches"], 1)
-    ops_per_launch = counts["feasible_relax"] * OPS_PER_RELAX / launches_per_step
-    achieved = ops_per_launch / avg_launch_s / 1e12
-    peak = VALU_PEAK_OPS / 1e12
-    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=round(peak, 3), unit="TOP/s",
-                    frac=round(achieved / peak, 4), traffic=measured_traffic(),
-                    kernel="k_dp (fast variant)", avg_launch_ms=round(1e3 * avg_launch_s, 4),
-                    ops_per_relax=OPS_PER_RELAX)
+    same = all(bool(torch.equal(plan.pair_rows(pout, q)[0], outs[q]["energy32"]))
+               and bool(torch.equal(plan.pair_rows(pout, q)[3], outs[q]["assign"])) for q in range(len(dms)))
+    log(f"persistent plan, {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} matchings/s, "
+        f"kernel {pprof}, tuning {tuning}, identical to per-model launches: {same}")
+    roofline = roof(pprof, 1.0, "k_dp_persistent (fast variant + degenerate re-run)",
+                    measured_traffic(TRAFFIC_FILE_PLAN))
+    plan.close()
 
     # split precision: the same step with the unary table from BF16 MFMA dot products
     pb = dataclasses.replace(p, unary_bf16=True)
@@ -495,7 +529,7 @@ def main():
 
     pruned = None
     if not args.no_pruned:
-        pruned = bench_pruned(ctx, w, dms, ds, ms_per_step, args.steps,
+        pruned = bench_pruned(ctx, w, dms, ds, loop_ms, args.steps,
                               tuple(int(x) for x in args.pruned_k.split(",")), list(range(100, 130)),
                               args.pruned_groups, args.pruned_epochs)
 
@@ -529,13 +563,16 @@ def main():
                                "1500 frames x 20 pts (320x240, 5 planted copies/model), D=162, "
                                "K=64, W=3, T=10, all offsets",
                    "matchings": n_match, "scene_points": int(s.n), "seed": args.seed,
-                   "dp_waves": args.dp_waves or 8},
+                   "launch": "one persistent recursion launch for all models per step, graph-replayed "
+                             "(unary tables, recursion, fused backtracking, FP64 re-score)",
+                   "tuning": tuning, "identical_to_per_model_launches": same},
         "dp_cells_per_s": {"dense": round(counts["dense_cells"] / sec, 1),
                            "feasible": round(counts["feasible_cells"] / sec, 1)},
         "relax_per_s": {"dense": round(counts["dense_relax"] / sec, 1),
                         "feasible": round(counts["feasible_relax"] / sec, 1)},
-        "dp_kernel_share": round(prof["dp_ms"] / 1e3 / elapsed, 4),
+        "dp_kernel_share": round(pprof["dp_ms"] / 1e3 / elapsed, 4),
         "roofline": roofline,
+        "per_model_launches": per_model,
         "cpu_baseline": cpu,
         "split_precision": split,
         "parity_on_cpu_sample": parity,

@@ -381,7 +381,11 @@ STM_API int stm_set_dp_waves(stm_ctx* ctx, int waves);
 
 /* Enables (1) or disables (0) timing and resets the totals.  While enabled,
  * every launch of the recursion kernel (the fast variant) is bracketed by two
- * HIP events recorded on the stream it is launched on. */
+ * HIP events recorded on the stream it is launched on.  A plan run launches
+ * its kernels directly on the plan's stream instead of replaying its graph,
+ * with two events around its persistent recursion launches (the fast kernel
+ * and the re-run of flagged degenerate matchings), and waits for the second
+ * event to read the time. */
 STM_API int stm_profile_enable(stm_ctx* ctx, int enable);
 
 /* Waits for the recorded events and writes the summed kernel time in

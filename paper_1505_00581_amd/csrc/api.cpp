@@ -417,6 +417,8 @@ int stm_profile_enable(stm_ctx* ctx, int enable) {
   ctx->prof = enable != 0;
   ctx->prof_used = 0;
   ctx->prof_matchings = 0;
+  ctx->prof_plan_ms = 0.0;
+  ctx->prof_plan_launches = 0;
   return STM_OK;
 }
 
@@ -431,8 +433,8 @@ int stm_profile_read(stm_ctx* ctx, double* dp_ms, int64_t* dp_launches, int64_t*
     STM_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[q], ctx->prof_ev[q + 1]));
     total += ms;
   }
-  if (dp_ms) *dp_ms = total;
-  if (dp_launches) *dp_launches = static_cast<int64_t>(ctx->prof_used / 2);
+  if (dp_ms) *dp_ms = total + ctx->prof_plan_ms;
+  if (dp_launches) *dp_launches = static_cast<int64_t>(ctx->prof_used / 2) + ctx->prof_plan_launches;
   if (dp_matchings) *dp_matchings = ctx->prof_matchings;
   return STM_OK;
 }

@@ -52,6 +52,8 @@ struct stm_ctx {
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
   size_t prof_used = 0;             // events in use
   int64_t prof_matchings = 0;
+  double prof_plan_ms = 0.0;      // recursion launches of plan runs (events inside the graph)
+  int64_t prof_plan_launches = 0;
   int dp_waves = 8;
 };
 

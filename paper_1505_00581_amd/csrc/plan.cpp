@@ -42,6 +42,7 @@ struct stm_plan {
   // graph of the last run
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the recursion launch, when profiled
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void* cap_out[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -80,6 +81,8 @@ void plan_free(stm_plan* p) {
   for (void* q : p->owned) (void)hipFree(q);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->ev_out) (void)hipEventDestroy(p->ev_out);
+  if (p->ev_k0) (void)hipEventDestroy(p->ev_k0);
+  if (p->ev_k1) (void)hipEventDestroy(p->ev_k1);
   if (p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
@@ -140,12 +143,17 @@ int plan_enqueue_tables(stm_plan* p, hipStream_t st) {
   return STM_OK;
 }
 
-int plan_enqueue_run(stm_plan* p, float* e32, double* e64, double* eu, int32_t* assign, hipStream_t st) {
+int plan_enqueue_run(stm_plan* p, float* e32, double* e64, double* eu, int32_t* assign, hipStream_t st,
+                     bool timed) {
   int rc;
   if ((rc = plan_enqueue_tables(p, st))) return rc;
   STM_HIP(stm::launch_fill_i32(p->counters, 3, 0, st));
   const stm::BatchLaunch b = plan_launch(p, p->pairs_dev, p->items_dev, p->n_items, e32, assign);
+  // timed: the two events bracket the recursion launches (the fast persistent
+  // kernel and the re-run of flagged degenerate matchings)
+  if (timed) STM_HIP(hipEventRecord(p->ev_k0, st));
   STM_HIP(stm::launch_dp_persistent(b, p->n_cu * p->wgs_per_cu, st));
+  if (timed) STM_HIP(hipEventRecord(p->ev_k1, st));
   STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, p->params.T,
                                     p->params.lambda1, p->params.lambda2, p->params.lambda3, assign,
                                     e64, eu, st));
@@ -204,6 +212,8 @@ int stm_plan_create(stm_ctx* ctx, const stm_points* models, int32_t n_models, co
     STM_HIP(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
     STM_HIP(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
     STM_HIP(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
+    STM_HIP(hipEventCreate(&p->ev_k0));
+    STM_HIP(hipEventCreate(&p->ev_k1));
     const hipStream_t st = p->stream;
     // point sets on the device, validated
     p->mv.resize(n_models);
@@ -412,10 +422,14 @@ int stm_plan_run(stm_plan* p, float* energy32, double* energy64, double* energy_
   double* eu = p->device ? energy_u64 : (energy_u64 ? p->o_eu : nullptr);
   int32_t* asg = p->device ? assign : p->o_asg;
   const void* outs[4] = {e32, e64, eu, asg};
-  if (!p->exec || !std::equal(outs, outs + 4, p->cap_out)) {
+  // timed runs launch the same kernels directly on the plan stream, with two
+  // events around the recursion launches (HIP cannot time events recorded
+  // inside a graph); other runs replay the captured graph
+  const bool timed = p->ctx->prof;
+  if (!timed && (!p->exec || !std::equal(outs, outs + 4, p->cap_out))) {
     plan_drop_graph(p);
     STM_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-    int rc = plan_enqueue_run(p, e32, e64, eu, asg, p->stream);
+    int rc = plan_enqueue_run(p, e32, e64, eu, asg, p->stream, false);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(p->stream, &g);
     if (rc) {
@@ -430,9 +444,22 @@ int stm_plan_run(stm_plan* p, float* energy32, double* energy64, double* energy_
   // order: caller's stream -> plan stream (graph) -> caller's stream
   STM_HIP(hipEventRecord(p->ev_in, user));
   STM_HIP(hipStreamWaitEvent(p->stream, p->ev_in, 0));
-  STM_HIP(hipGraphLaunch(p->exec, p->stream));
+  if (timed) {
+    int rc = plan_enqueue_run(p, e32, e64, eu, asg, p->stream, true);
+    if (rc) return rc;
+  } else {
+    STM_HIP(hipGraphLaunch(p->exec, p->stream));
+  }
   STM_HIP(hipEventRecord(p->ev_out, p->stream));
   STM_HIP(hipStreamWaitEvent(user, p->ev_out, 0));
+  if (timed) {  // the events are re-recorded by every timed run: read this one's now
+    STM_HIP(hipEventSynchronize(p->ev_k1));
+    float ms = 0.f;
+    STM_HIP(hipEventElapsedTime(&ms, p->ev_k0, p->ev_k1));
+    p->ctx->prof_plan_ms += ms;
+    p->ctx->prof_plan_launches += 1;
+    p->ctx->prof_matchings += p->row_off.back();
+  }
   if (!p->device) {
     const int64_t nr = p->row_off.back(), na = p->asg_off.back();
     STM_HIP(hipMemcpyAsync(energy32, e32, (size_t)nr * sizeof(float), hipMemcpyDeviceToHost, p->stream));

@@ -170,3 +170,24 @@ def test_invalid_pairs_rejected(ctx):
     bad = synth.Points(scenes[0].xy, scenes[0].t[::-1].copy(), scenes[0].desc, scenes[0].n_frames)
     with pytest.raises(stm.StmError):
         stm.Plan(ctx, models, [bad], np.array([[0, 0]], np.int32), p)
+
+
+def test_profiled_plan_runs(ctx):
+    """Timed plan runs launch the kernels directly with two events around the
+    recursion; the results do not change and each run adds one timed launch."""
+    models, scenes, p = _small_batch(5, n_models=3, n_scenes=1)
+    pairs = _all_pairs(len(models), len(scenes))
+    plan = stm.Plan(ctx, models, scenes, pairs, p)
+    ref = {k: v.copy() for k, v in plan.run().items()}
+    ctx.profile_enable(True)
+    for _ in range(3):
+        out = plan.run()
+        for k in ("energy32", "energy64", "assign"):
+            np.testing.assert_array_equal(out[k], ref[k])
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    assert prof["dp_launches"] == 3 and prof["dp_ms"] > 0
+    assert prof["dp_matchings"] == 3 * plan.n_rows
+    out = plan.run()   # graph replay again
+    np.testing.assert_array_equal(out["energy32"], ref["energy32"])
+    plan.close()
