@@ -52,7 +52,7 @@
 namespace stm {
 namespace {
 
-constexpr int KL = 64;  // candidate slots = wavefront lanes
+constexpr int kMaxList = 64;  // longest candidate list = wavefront lanes
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kTwoPi = 6.28318530717958647692f;
 constexpr float kInvTwoPi = 0.15915494309189533577f;
@@ -219,7 +219,7 @@ __device__ void build_schedule(const int32_t* trow, int nrow, const int32_t* tco
   if (lane == 0) *nout = total;
 }
 
-template <int NW>
+template <int NW, int KL>
 struct DPShared {
   float2 va[KL * KL];   // [a_{i-2}][a_{i-1}]: (V_{i-1}, -phi(z_{i-2} -> z_{i-1}))
   float ct[KL * KL];    // [a_{i-2}][a_i]: -phi(z_{i-2} -> z_i)
@@ -293,9 +293,10 @@ struct DPResult {
 
 // Forward pass of one matching by the whole workgroup (NW waves): writes the
 // value tables of steps 1..M-2 to vtm and returns the optimum to every thread.
-template <int NW, bool DEGEN>
-__device__ DPResult dp_forward(DPShared<NW>& sh, const MatchView& a, float* vtm) {
-  constexpr int RPW = KL / NW;  // chunk slots per wave (a step has <= 64 chunks)
+template <int NW, bool DEGEN, int KL>
+__device__ DPResult dp_forward(DPShared<NW, KL>& sh, const MatchView& a, float* vtm) {
+  static_assert(KL == 16 || KL == 32 || KL == 64, "list capacity");
+  constexpr int RPW = KL / NW;  // chunk slots per wave (a step has <= KL chunks)
   const int tau = a.tau;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -382,7 +383,7 @@ __device__ DPResult dp_forward(DPShared<NW>& sh, const MatchView& a, float* vtm)
     if (wv == kBuilder)
       build_schedule(sh.ctt[s1], Kp, sh.ctt[s0], Kn, sh.ctt[s2], Kq, T, sh.sched[cur], &sh.nch[cur], lane);
     for (int e = threadIdx.x; e < Kq * KL; e += NW * 64) {
-      const int k = e >> 6, c = e & 63;
+      const int k = e / KL, c = e & (KL - 1);
       if (c < Kn) {
         // a pair is used only if some z_{i-1} fits strictly between its frames
         // and within T of both: 2 <= t_i - t_{i-2} <= 2T - 2
@@ -561,12 +562,12 @@ __device__ __forceinline__ float* scratch_of(const DPLaunch& a, int tl) {
   return a.vt + (long long)tl * (a.m.M - 2) * a.sp.K * a.sp.K;
 }
 
-template <int NW, bool DEGEN>
+template <int NW, bool DEGEN, int KL>
 __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
-  __shared__ DPShared<NW> sh;
+  __shared__ DPShared<NW, KL> sh;
   const int tl = blockIdx.x;
   if (DEGEN && a.degen[tl] == 0) return;
-  const DPResult r = dp_forward<NW, DEGEN>(sh, view_of(a, tl), scratch_of(a, tl));
+  const DPResult r = dp_forward<NW, DEGEN, KL>(sh, view_of(a, tl), scratch_of(a, tl));
   if (threadIdx.x == 0) {
     a.e32[tl] = r.v;
     a.last2[tl] = make_int2(r.idx / KL, r.idx % KL);
@@ -614,10 +615,10 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
 // The fast variant takes every item; an item whose matching has coincident
 // points is appended to the degenerate list instead of being backtracked, and
 // the degenerate variant (a second launch) takes the items of that list.
-template <int NW, bool DEGEN>
+template <int NW, bool DEGEN, int KL = kMaxList>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW >= 8 ? 6 : 3)))
 void k_dp_persistent(BatchLaunch b) {
-  __shared__ DPShared<NW> sh;
+  __shared__ DPShared<NW, KL> sh;
   __shared__ int item_sh;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* vtm = b.vt + (long long)blockIdx.x * b.vt_stride;
@@ -631,7 +632,7 @@ void k_dp_persistent(BatchLaunch b) {
     const int2 it = b.items[item];
     const PairDev pd = b.pairs[it.x];
     const MatchView mv = view_of(b, pd, it.y);
-    const DPResult r = dp_forward<NW, DEGEN>(sh, mv, vtm);
+    const DPResult r = dp_forward<NW, DEGEN, KL>(sh, mv, vtm);
     if (!DEGEN && r.flag) {
       if (threadIdx.x == 0) b.degen_items[atomicAdd(b.degen_count, 1)] = item;
     } else if (wv == 0) {
@@ -755,18 +756,30 @@ __global__ __launch_bounds__(64) void k_rescore_batch(const PairDev* __restrict_
                pd.row0 + it.y, e64, eu64);
 }
 
+// Lists of at most 16 or 32 candidates take a smaller LDS layout and fewer
+// waves per matching (more matchings resident per CU); longer lists take the
+// 64-slot layout with the requested number of waves.  The arithmetic of every
+// cell is the same, so the results do not depend on the variant.
 template <bool DEGEN>
 hipError_t launch_dp_waves(const DPLaunch& a, hipStream_t st) {
   if (a.n_tau <= 0) return hipSuccess;
+  if (a.sp.K <= 16) {
+    hipLaunchKernelGGL((k_dp<1, DEGEN, 16>), dim3(a.n_tau), dim3(64), 0, st, a);
+    return hipGetLastError();
+  }
+  if (a.sp.K <= 32) {
+    hipLaunchKernelGGL((k_dp<2, DEGEN, 32>), dim3(a.n_tau), dim3(2 * 64), 0, st, a);
+    return hipGetLastError();
+  }
   switch (a.waves) {
     case 4:
-      hipLaunchKernelGGL((k_dp<4, DEGEN>), dim3(a.n_tau), dim3(4 * 64), 0, st, a);
+      hipLaunchKernelGGL((k_dp<4, DEGEN, 64>), dim3(a.n_tau), dim3(4 * 64), 0, st, a);
       break;
     case 16:
-      hipLaunchKernelGGL((k_dp<16, DEGEN>), dim3(a.n_tau), dim3(16 * 64), 0, st, a);
+      hipLaunchKernelGGL((k_dp<16, DEGEN, 64>), dim3(a.n_tau), dim3(16 * 64), 0, st, a);
       break;
     default:
-      hipLaunchKernelGGL((k_dp<8, DEGEN>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
+      hipLaunchKernelGGL((k_dp<8, DEGEN, 64>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
   }
   return hipGetLastError();
 }

@@ -335,3 +335,29 @@ def test_closeness_variants_at_realistic_sizes(ctx, T):
     n = res["energy32"].shape[0]
     taus = np.unique(np.linspace(0, n - 1, 6).astype(np.int32))
     check(m, s, p, res, oracle.match(m, s, p, taus=taus), rows=taus)
+
+
+@pytest.mark.parametrize("k_max", [12, 24, 40])
+def test_list_capacity_variants(ctx, k_max):
+    """Lists of <= 16, <= 32 and <= 64 candidates run on recursion variants
+    with different LDS layouts and waves per matching: sampled offsets against
+    the oracle, and the same lists handed over with a wider stride (which
+    selects the 64-slot variant) give bit-identical rows."""
+    w = synth.config2(33, n_models=1)
+    m, s = w.models[0], w.scenes[0]
+    keep = s.t < 300
+    s = synth.Points(np.ascontiguousarray(s.xy[keep]), np.ascontiguousarray(s.t[keep]),
+                     np.ascontiguousarray(s.desc[keep]), 300)
+    p = dataclasses.replace(w.params, k_max=k_max)
+    res = ctx.match(m, s, p)
+    n = res["energy32"].shape[0]
+    taus = np.unique(np.linspace(0, n - 1, 6).astype(np.int32))
+    check(m, s, p, res, oracle.match(m, s, p, taus=taus), rows=taus)
+    cand, cnt = ctx.candidates(m, s, p)
+    wide = np.full((cand.shape[0], cand.shape[1], 48), -1, np.int32)
+    wide[:, :, :k_max] = cand
+    a = ctx.match_lists(m, s, p, cand, cnt)
+    b = ctx.match_lists(m, s, p, wide, cnt)
+    for k in ("energy32", "energy64", "assign"):
+        np.testing.assert_array_equal(a[k], res[k])
+        np.testing.assert_array_equal(b[k], res[k])
