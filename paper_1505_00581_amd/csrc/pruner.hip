@@ -83,20 +83,24 @@ __device__ void group_features(const ModelView& m, const SceneView& s, const flo
 }
 
 // One 64-lane block per group: rows node [G*64], phi [G*64][8], q [G][2].
+// Groups are groups[g] = (tau, i), or (tau0 + g / M, g % M) when groups is
+// null; q may be null.
 __global__ __launch_bounds__(64) void k_group_rows(ModelView m, SceneView s, const float* __restrict__ U,
                                                   long long us, SearchParams sp, const int2* __restrict__ groups,
-                                                  int32_t* __restrict__ node, float* __restrict__ phi,
+                                                  int tau0, int32_t* __restrict__ node, float* __restrict__ phi,
                                                   int32_t* __restrict__ q) {
-  const int g = blockIdx.x, lane = threadIdx.x;
-  const int2 gi = groups[g];  // (tau, i)
+  const long long g = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int2 gi = groups ? groups[g] : make_int2(tau0 + static_cast<int>(g / m.M), static_cast<int>(g % m.M));
   int n, qa, qb;
   float f[8];
   group_features(m, s, U, us, sp, gi.x, gi.y, lane, n, f, qa, qb);
-  const long long r = (long long)g * 64 + lane;
+  const long long r = g * 64 + lane;
   node[r] = n;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) phi[r * 8 + k] = f[k];
-  if (lane == 0) {
+  float4* ph = reinterpret_cast<float4*>(phi + r * 8);
+  ph[0] = make_float4(f[0], f[1], f[2], f[3]);
+  ph[1] = make_float4(f[4], f[5], f[6], f[7]);
+  if (q && lane == 0) {
     q[2 * g] = qa;
     q[2 * g + 1] = qb;
   }
@@ -380,7 +384,17 @@ struct alignas(16) InferShared {
   float b2[H], w3[H];
   float phi[kInferWaves][64][9];  // per wave: features of the 64 slots (+ pad)
   int32_t node[kInferWaves][64];
+  unsigned long long key[kInferWaves][64];  // per wave: selection keys of the 64 slots
 };
+
+// Selection key of a slot: smaller is kept first.  Frame distance (0 under the
+// score rule), then the score descending, then the slot; unique per slot.
+__device__ __forceinline__ unsigned long long select_key(int df, float sc, int slot) {
+  unsigned int u = __float_as_uint(sc + 0.f);  // -0 counts as +0
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // order-preserving map of floats to unsigned
+  return (static_cast<unsigned long long>(df) << 38) | (static_cast<unsigned long long>(~u) << 6) |
+         static_cast<unsigned long long>(slot);
+}
 
 // Position of hidden unit u inside a permuted W2 row.
 __device__ __forceinline__ int w2_pos(int u) {
@@ -389,7 +403,7 @@ __device__ __forceinline__ int w2_pos(int u) {
 }
 
 __global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_pruner_infer(
-    ModelView m, SceneView s, const float* __restrict__ U, long long us, SearchParams sp,
+    ModelView m, SceneView s, const int32_t* __restrict__ gnode, const float* __restrict__ gphi,
     const int2* __restrict__ groups, long long n_groups, int tau0, const float* __restrict__ theta, int D,
     const float* __restrict__ A, const float* __restrict__ B, int topk, int rule, int32_t* __restrict__ cand,
     int32_t* __restrict__ count, float* __restrict__ scores) {
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_e
   const float b3 = w3[H];
   for (int e = tid; e < H * H; e += kInferWaves * 64) {
     const int o = e >> 7, u = e & 127;
-    sh.w2p[o * kW2Row + w2_pos(u)] = to_bf16(W2[e]);
+    sh.w2p[o * kW2Row + w2_pos(u)] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(W2[e]));
   }
   for (int e = tid; e < H; e += kInferWaves * 64) {
     sh.b2[e] = b2[e];
@@ -424,13 +438,13 @@ __global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_e
   const long long stride = (long long)gridDim.x * kInferWaves;
   for (long long g = (long long)blockIdx.x * kInferWaves + wv; g < n_groups; g += stride) {
     const int2 gi = groups ? groups[g] : make_int2(tau0 + static_cast<int>(g / m.M), static_cast<int>(g % m.M));
-    int n, qa, qb;
+    const int n = gnode[g * 64 + lane];
     {
-      float f[8];
-      group_features(m, s, U, us, sp, gi.x, gi.y, lane, n, f, qa, qb);
+      const float4* gp = reinterpret_cast<const float4*>(gphi + (g * 64 + lane) * 8);
+      const float4 f0 = gp[0], f1 = gp[1];
       node[lane] = n;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) phi[lane][k] = f[k];
+      phi[lane][0] = f0.x; phi[lane][1] = f0.y; phi[lane][2] = f0.z; phi[lane][3] = f0.w;
+      phi[lane][4] = f1.x; phi[lane][5] = f1.y; phi[lane][6] = f1.z; phi[lane][7] = f1.w;
     }
     // the wave's LDS writes above are read by other lanes of the same wave below
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -457,7 +471,7 @@ __global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_e
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const float hv = nc < 0 ? 0.f : fmaxf(z[j], 0.f);
-          hb[kt >> 1][(kt & 1) * 4 + j] = __builtin_bit_cast(__bf16, to_bf16(hv));
+          hb[kt >> 1][(kt & 1) * 4 + j] = static_cast<__bf16>(hv);  // v_cvt_pk_bf16_f32, nearest even
         }
       }
       float part = 0.f;
@@ -486,13 +500,19 @@ __global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_e
     // rank: candidates ahead in the selection order.  Score rule: a higher
     // score, or an equal score and a lower slot.  Frames-first rule: a frame
     // nearer the shifted model frame, then the score rule inside a frame.
-    const int df = n < 0 ? 0x7fffffff : abs(s.t[n] - (gi.x + m.t[gi.y] - m.t[0]));
-    const int key = rule ? df : 0;
+    // Empty slots carry -inf and the largest frame distance: ranked last.
+    const int df = n < 0 ? (1 << 25) : abs(s.t[n] - (gi.x + m.t[gi.y] - m.t[0]));
+    const unsigned long long key = select_key(rule ? df : (n < 0 ? 1 : 0), sc, lane);
+    sh.key[wv][lane] = key;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     int rank = 0;
-    for (int j = 0; j < 64; ++j) {
-      const float o = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sc), j));
-      const int ok = __builtin_amdgcn_readlane(key, j);
-      rank += (ok < key) || (ok == key && ((o > sc) || (o == sc && j < lane)));
+    const ulonglong2* kk = reinterpret_cast<const ulonglong2*>(sh.key[wv]);
+#pragma unroll 8
+    for (int j = 0; j < 32; ++j) {
+      const ulonglong2 o = kk[j];  // the same address in every lane: a broadcast read
+      rank += (o.x < key) + (o.y < key);
     }
     const bool keep = n >= 0 && rank < topk;
     const unsigned long long mask = __ballot(keep);
@@ -553,10 +573,11 @@ inline int blocks(long long n, int per) { return static_cast<int>((n + per - 1) 
 }  // namespace
 
 hipError_t launch_group_rows(const ModelView& m, const SceneView& s, const float* U, long long us,
-                             const SearchParams& sp, const int2* groups, int G, int32_t* node, float* phi,
-                             int32_t* q, hipStream_t st) {
+                             const SearchParams& sp, const int2* groups, int tau0, long long G, int32_t* node,
+                             float* phi, int32_t* q, hipStream_t st) {
   if (G <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_group_rows, dim3(G), dim3(64), 0, st, m, s, U, us, sp, groups, node, phi, q);
+  hipLaunchKernelGGL(k_group_rows, dim3(static_cast<unsigned>(G)), dim3(64), 0, st, m, s, U, us, sp, groups, tau0,
+                     node, phi, q);
   return hipGetLastError();
 }
 
@@ -641,8 +662,11 @@ hipError_t launch_pruner_infer(const PrunerInfer& q, hipStream_t st) {
   (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   const long long want = (q.n_groups + kInferWaves - 1) / kInferWaves;
   const long long grid = want < (long long)n_cu * 2 ? want : (long long)n_cu * 2;
+  hipError_t e = launch_group_rows(q.m, q.s, q.U, q.us, q.sp, q.groups, q.tau0, q.n_groups, q.node, q.phi, nullptr,
+                                  st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pruner_infer, dim3(static_cast<unsigned>(grid)), dim3(kInferWaves * 64), 0, st, q.m, q.s,
-                     q.U, q.us, q.sp, q.groups, q.n_groups, q.tau0, q.theta, q.D, q.A, q.B, q.topk, q.rule, q.cand,
+                     q.node, q.phi, q.groups, q.n_groups, q.tau0, q.theta, q.D, q.A, q.B, q.topk, q.rule, q.cand,
                      q.count, q.scores);
   return hipGetLastError();
 }

@@ -83,7 +83,7 @@ int group_rows(stm_pruner* P, const Prepared& pr, int G) {
   if ((rc = grow(P->ctx, P->phi, R * 8 * sizeof(float), pr.st))) return rc;
   if ((rc = grow(P->ctx, P->q, (size_t)G * 2 * sizeof(int32_t), pr.st))) return rc;
   STM_HIP(stm::launch_group_rows(pr.m, pr.s, static_cast<const float*>(P->ctx->U.p), pr.s.S, pr.sp,
-                                 as<const int2>(P->groups), G, as<int32_t>(P->node), as<float>(P->phi),
+                                 as<const int2>(P->groups), 0, G, as<int32_t>(P->node), as<float>(P->phi),
                                  as<int32_t>(P->q), pr.st));
   return STM_OK;
 }
@@ -192,6 +192,8 @@ stm::PrunerInfer infer_args(stm_pruner* P, const Prepared& pr, int topk) {
   q.groups = nullptr;
   q.n_groups = 0;
   q.tau0 = 0;
+  q.node = nullptr;
+  q.phi = nullptr;
   q.theta = as<const float>(P->theta);
   q.D = P->dim;
   q.A = as<const float>(P->A);
@@ -532,9 +534,13 @@ int stm_pruner_infer(stm_pruner* P, const stm_points* model, const stm_points* s
   if ((rc = grow(P->ctx, P->cand, (size_t)G * topk * sizeof(int32_t), pr.st))) return rc;
   if ((rc = grow(P->ctx, P->count, (size_t)G * sizeof(int32_t), pr.st))) return rc;
   if ((rc = grow(P->ctx, P->scores, (size_t)G * kSlots * sizeof(float), pr.st))) return rc;
+  if ((rc = grow(P->ctx, P->node, (size_t)G * kSlots * sizeof(int32_t), pr.st))) return rc;
+  if ((rc = grow(P->ctx, P->phi, (size_t)G * kSlots * 8 * sizeof(float), pr.st))) return rc;
   stm::PrunerInfer q = infer_args(P, pr, topk);
   q.groups = as<const int2>(P->groups);
   q.n_groups = G;
+  q.node = as<int32_t>(P->node);
+  q.phi = as<float>(P->phi);
   q.cand = as<int32_t>(P->cand);
   q.count = as<int32_t>(P->count);
   q.scores = as<float>(P->scores);
@@ -571,13 +577,17 @@ int stm_match_pruned(stm_ctx* ctx, stm_pruner* P, const stm_points* model, const
 
   // pruned lists and the recursion on them, in chunks of offsets
   const int kp = std::min(topk, pr.sp.K);
-  const int chunk = dp_chunk(ctx, pr, n_tau, kp, (size_t)std::max(1, (1 << 22) / M));
+  const int chunk = dp_chunk(ctx, pr, n_tau, kp, (size_t)std::max(1, (1 << 20) / M));
   if ((rc = dp_scratch(ctx, pr, chunk, kp))) return rc;
   if ((rc = grow(ctx, P->cand, (size_t)chunk * M * kp * sizeof(int32_t), pr.st))) return rc;
   if ((rc = grow(ctx, P->count, (size_t)chunk * M * sizeof(int32_t), pr.st))) return rc;
+  if ((rc = grow(ctx, P->node, (size_t)chunk * M * kSlots * sizeof(int32_t), pr.st))) return rc;
+  if ((rc = grow(ctx, P->phi, (size_t)chunk * M * kSlots * 8 * sizeof(float), pr.st))) return rc;
   stm::PrunerInfer q = infer_args(P, pr, kp);
   q.cand = as<int32_t>(P->cand);
   q.count = as<int32_t>(P->count);
+  q.node = as<int32_t>(P->node);
+  q.phi = as<float>(P->phi);
   stm::DPLaunch b = dp_base(ctx, pr, params);
   b.sp.K = kp;
   b.cand = q.cand;

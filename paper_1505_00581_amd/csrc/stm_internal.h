@@ -212,10 +212,11 @@ hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_i
 constexpr int kPrunerHidden = 128;
 
 // Candidate nodes, features and the neighbours' chosen candidates of groups
-// (tau, i): node [G * 64] (-1 past the list), phi [G * 64][8], q [G][2].
+// (tau, i) = groups[g], or (tau0 + g / M, g % M) without a list: node [G * 64]
+// (-1 past the list), phi [G * 64][8], q [G][2] (nullable).
 hipError_t launch_group_rows(const ModelView& m, const SceneView& s, const float* U, long long us,
-                             const SearchParams& sp, const int2* groups, int G, int32_t* node, float* phi,
-                             int32_t* q, hipStream_t st);
+                             const SearchParams& sp, const int2* groups, int tau0, long long G, int32_t* node,
+                             float* phi, int32_t* q, hipStream_t st);
 
 // One FP32 training pass over G groups (rows = 64 G): forward, scores and
 // per-group losses; with labels also the gradient of the mean loss into grad
@@ -252,6 +253,8 @@ struct PrunerInfer {
   const int2* groups;  // null: groups (tau0 + g / M, g % M)
   long long n_groups;
   int tau0;
+  int32_t* node;        // scratch [n_groups][64]: candidate of each slot (written here)
+  float* phi;           // scratch [n_groups][64][8]: its features (written here)
   const float* theta;  // FP32 parameters (W1 phi columns, W2, b2, w3, b3)
   int D;
   const float* A;       // [M][128] model projection W1[:, 0:D] (D f) + b1
