@@ -218,8 +218,8 @@ def bench_batched(ctx, seed: int, runs: int, cache_path: str):
                                 "feasible": round(counts["feasible_cells"] / dt, 1)})
 
 
-def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, steps: int, topks, train_seeds, n_groups: int,
-                 epochs: int):
+def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, plan_ms_per_step: float, steps: int, topks,
+                 train_seeds, n_groups: int, epochs: int, tune_cache: str):
     """The learned candidate pruner on the same workload: trained on labels
     from the exact recursion on other seeds (realistic single-scene
     workloads), then per list size k: the pruned matching's time per step
@@ -247,6 +247,19 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, steps: int, topks, t
     evals = [PT.evaluate(ctx, pr, dm, ds, p, topks=topks) for dm in dms]
     summary = PT.summarise(evals)
     n_match = sum(e["offsets"] for e in evals)
+    pairs = np.array([(i, 0) for i in range(len(dms))], np.int32)
+    plan = stm.Plan(ctx, dms, [ds], pairs, p)
+    plan.autotune(tune_cache)
+
+    def time_plan(run):
+        out = run(None)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(steps):
+            run(out)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - ta) / steps
+
     per_k = {}
     for k in topks:
         outs = []
@@ -269,16 +282,29 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, steps: int, topks, t
                 ctx.match(dm, ds, pk, out=o)
         torch.cuda.synchronize()
         ms_t = 1e3 * (time.perf_counter() - ta) / steps
+        # the same in one persistent plan run per step (lists, recursion and
+        # exact fallback on the device), against the exact plan run
+        ms_pp = time_plan(lambda o: plan.run_pruned(pr, k, out=o))
+        tplan = stm.Plan(ctx, dms, [ds], pairs, pk)
+        tplan.autotune(tune_cache)
+        ms_tp = time_plan(lambda o: tplan.run(o))
+        tplan.close()
         per_k[str(k)] = dict(ms_per_step=round(ms, 3), matchings_per_s=round(n_match / ms * 1e3, 1),
                              speedup_vs_exact=round(exact_ms_per_step / ms, 3),
+                             plan_ms_per_step=round(ms_pp, 3),
+                             plan_speedup_vs_exact_plan=round(plan_ms_per_step / ms_pp, 3),
                              mlp=summary[k]["mlp"],
                              time_nearest=dict(summary[k]["time_nearest"], ms_per_step=round(ms_t, 3),
-                                               speedup_vs_exact=round(exact_ms_per_step / ms_t, 3)),
+                                               speedup_vs_exact=round(exact_ms_per_step / ms_t, 3),
+                                               plan_ms_per_step=round(ms_tp, 3),
+                                               plan_speedup_vs_exact_plan=round(plan_ms_per_step / ms_tp, 3)),
                              u_ranked=summary[k]["u_ranked"])
-        log(f"  k={k}: {ms:.2f} ms/step (exact {exact_ms_per_step:.2f}), mlp {summary[k]['mlp']}, "
+        log(f"  k={k}: {ms:.2f} ms/step per model (exact {exact_ms_per_step:.2f}), plan {ms_pp:.2f} "
+            f"(exact plan {plan_ms_per_step:.2f}, time-nearest plan {ms_tp:.2f}), mlp {summary[k]['mlp']}, "
             f"time-nearest {summary[k]['time_nearest']}")
     ok = [k for k in topks if summary[k]["mlp"]["mean_gap"] <= 0.01]
     best = min(ok) if ok else None
+    plan.close()
     pr.close()
     return dict(k_exact=int(p.k_max), train=dict(groups=n_train, seeds=f"{train_seeds[0]}-{train_seeds[-1]}",
                                                  epochs=epochs, label_s=round(t1 - t0, 2),
@@ -286,7 +312,8 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, steps: int, topks, t
                                                  loss=[round(x, 4) for x in hist]),
                 test="the benchmark workload's own seed (held out from the training seeds)",
                 per_k=per_k, gap_target=0.01, smallest_k_within_target=best,
-                speedup_at_target=(per_k[str(best)]["speedup_vs_exact"] if best else None))
+                speedup_at_target=(per_k[str(best)]["speedup_vs_exact"] if best else None),
+                plan_speedup_at_target=(per_k[str(best)]["plan_speedup_vs_exact_plan"] if best else None))
 
 
 def bench_paper_blocks(ctx, steps: int):
@@ -529,9 +556,9 @@ def main():
 
     pruned = None
     if not args.no_pruned:
-        pruned = bench_pruned(ctx, w, dms, ds, loop_ms, args.steps,
+        pruned = bench_pruned(ctx, w, dms, ds, loop_ms, ms_per_step, args.steps,
                               tuple(int(x) for x in args.pruned_k.split(",")), list(range(100, 130)),
-                              args.pruned_groups, args.pruned_epochs)
+                              args.pruned_groups, args.pruned_epochs, args.tune_cache)
 
     sweep = None
     if args.t_sweep:

@@ -371,6 +371,20 @@ STM_API int stm_match_lists(stm_ctx* ctx, const stm_points* model, const stm_poi
                             const int32_t* cand, const int32_t* count, int32_t kc, float* energy32,
                             double* energy64, double* energy_u64, int32_t* assign, void* hip_stream);
 
+/* A plan run on pruned candidate lists (the batched form of stm_match_pruned):
+ * the pruner's lists of every (pair, offset, point), one persistent launch of
+ * the recursion on them, the items they left infeasible solved again exactly
+ * in a second persistent launch, the FP64 re-score; all on the device, as one
+ * captured graph (replayed while the outputs, pruner, topk and rule are the
+ * same; the pruner's current parameters are read at each run).  Outputs as
+ * stm_plan_run plus fell_back [rows] (nullable): 1 where the exact fallback
+ * answered.  The pruner must belong to the plan's context and match its
+ * descriptor dimension; plans with STM_UNARY_BF16 are not supported
+ * (STM_EUNSUPPORTED).  Rows equal stm_match_pruned's for each pair. */
+STM_API int stm_plan_run_pruned(stm_plan* plan, stm_pruner* pruner, int32_t topk, float* energy32,
+                                double* energy64, double* energy_u64, int32_t* assign, int32_t* fell_back,
+                                void* hip_stream);
+
 /* ---- tuning ----------------------------------------------------------------- */
 
 /* Waves per workgroup of the recursion kernel (one workgroup per matching):

@@ -30,7 +30,7 @@ EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_ma
            "stm_match_batch", "stm_pruner_num_params", "stm_pruner_create", "stm_pruner_destroy",
            "stm_pruner_set_params", "stm_pruner_get_params", "stm_pruner_save", "stm_pruner_load",
            "stm_pruner_features", "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
-           "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule")
+           "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned")
 
 
 class StmError(RuntimeError):
@@ -111,6 +111,7 @@ def load() -> ctypes.CDLL:
         lib.stm_match_pruned.argtypes = [P, P, PP, PP, PS, i32, i32, i32, P, P, P, P, P, P]
         lib.stm_match_lists.argtypes = [P, PP, PP, PS, i32, i32, P, P, i32, P, P, P, P, P]
         lib.stm_pruner_set_rule.argtypes = [P, i32]
+        lib.stm_plan_run_pruned.argtypes = [P, P, i32, P, P, P, P, P, P]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
                      "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
@@ -118,7 +119,7 @@ def load() -> ctypes.CDLL:
                      "stm_pruner_create", "stm_pruner_set_params", "stm_pruner_get_params",
                      "stm_pruner_save", "stm_pruner_load", "stm_pruner_features",
                      "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
-                     "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule"):
+                     "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -413,6 +414,22 @@ class Plan:
         _check(self._lib.stm_plan_run(self.handle, _ptr(out["energy32"]), _ptr(out["energy64"]),
                                       _ptr(out["energy_u64"]), _ptr(out["assign"]),
                                       _stream() if self.device else None))
+        return out
+
+    def run_pruned(self, pruner, topk: int = 48, out=None):
+        """A run on the pruner's top-k lists with the exact fallback on the
+        device; adds fell_back [rows] to the outputs."""
+        out = out if out is not None else self.outputs()
+        if "fell_back" not in out:
+            if self.device:
+                import torch
+                out["fell_back"] = torch.empty(self.n_rows, dtype=torch.int32, device="cuda")
+            else:
+                out["fell_back"] = np.empty(self.n_rows, np.int32)
+        _check(self._lib.stm_plan_run_pruned(self.handle, pruner.handle, int(topk), _ptr(out["energy32"]),
+                                             _ptr(out["energy64"]), _ptr(out["energy_u64"]),
+                                             _ptr(out["assign"]), _ptr(out["fell_back"]),
+                                             _stream() if self.device else None))
         return out
 
     def pair_rows(self, out, q):

@@ -606,9 +606,9 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
   v.lambda2 = b.lambda2;
   v.w = b.w;
   v.tau = tau;
-  v.cand = nullptr;
-  v.ccount = nullptr;
-  v.cstride = 0;
+  v.cand = pd.cand ? pd.cand + (long long)tau * pd.m.M * pd.cstride : nullptr;
+  v.ccount = pd.cand ? pd.ccount + (long long)tau * pd.m.M : nullptr;
+  v.cstride = pd.cstride;
   return v;
 }
 
@@ -622,12 +622,15 @@ void k_dp_persistent(BatchLaunch b) {
   __shared__ int item_sh;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* vtm = b.vt + (long long)blockIdx.x * b.vt_stride;
-  const int n_items = DEGEN ? *b.degen_count : b.n_items;
+  const int n_items = DEGEN ? *b.degen_count : (b.list ? *b.list_count : b.n_items);
   int32_t* counter = DEGEN ? b.counter + 1 : b.counter;
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
     __syncthreads();
-    const int item = DEGEN ? (item_sh < n_items ? b.degen_items[item_sh] : -1) : item_sh;
+    const int item = item_sh >= n_items ? -1
+                     : DEGEN           ? b.degen_items[item_sh]
+                     : b.list          ? b.list[item_sh]
+                                       : item_sh;
     if (item_sh >= n_items) break;
     const int2 it = b.items[item];
     const PairDev pd = b.pairs[it.x];
@@ -646,6 +649,20 @@ void k_dp_persistent(BatchLaunch b) {
       }
     }
     __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_collect_infeasible(const PairDev* __restrict__ pairs,
+                                                           const int2* __restrict__ items, int n_items,
+                                                           const float* __restrict__ e32, int32_t* __restrict__ list,
+                                                           int32_t* __restrict__ count, int32_t* __restrict__ fell) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n_items) return;
+  const int2 it = items[q];
+  const long long row = pairs[it.x].row0 + it.y;
+  if (!(e32[row] < __builtin_inff())) {
+    list[atomicAdd(count, 1)] = q;
+    if (fell) fell[row] = 1;
   }
 }
 
@@ -815,6 +832,14 @@ hipError_t launch_item_cost(const PairDev* pairs, const int2* items, int n_items
                             long long* cost, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_item_cost, dim3(n_items), dim3(64), 0, st, pairs, items, n_items, sp, cost);
+  return hipGetLastError();
+}
+
+hipError_t launch_collect_infeasible(const PairDev* pairs, const int2* items, int n_items, const float* e32,
+                                     int32_t* list, int32_t* count, int32_t* fell, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_collect_infeasible, dim3((n_items + 255) / 256), dim3(256), 0, st, pairs, items, n_items, e32,
+                     list, count, fell);
   return hipGetLastError();
 }
 

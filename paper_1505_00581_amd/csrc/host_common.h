@@ -57,6 +57,22 @@ struct stm_ctx {
   int dp_waves = 8;
 };
 
+// The learned candidate pruner: FP32 parameters packed as
+// [W1 (128 x (2 dim + 8)), b1, W2 (128 x 128), b2, w3, b3], Adam moments, and
+// per-call scratch.
+struct stm_pruner {
+  stm_ctx* ctx = nullptr;
+  int dim = 0;
+  long long n = 0;
+  long long step = 0;  // Adam steps taken since the parameters were set
+  int rule = STM_PRUNE_FRAMES_FIRST;
+  stmh::DevBuf theta, grad, am, av;
+  // per-call scratch
+  stmh::DevBuf groups, labels, node, phi, q, h1, h2, dz1, dz2, ds, loss, scores, part;
+  stmh::DevBuf wa, wb, A, B, xm, xs, norms, cand, count;
+  stmh::DevBuf taus, f32, f64, fu, fas, fell;
+};
+
 namespace stmh {
 
 // Grows `b` to at least `bytes` (waiting for `st` before freeing); the old

@@ -51,6 +51,21 @@ struct stm_plan {
   double* o_e64 = nullptr;
   double* o_eu = nullptr;
   int32_t* o_asg = nullptr;
+  int32_t* o_fell = nullptr;
+  // pruned runs: projections, per-pair lists, the exact fallback's item list
+  std::vector<stm::PairDev> pairs_host;
+  std::vector<int2> pair_ms;            // (model, scene) of each pair
+  int pr_dim = 0, pr_k = 0;             // buffers sized for this dim / list length
+  uint16_t *pr_wa = nullptr, *pr_wb = nullptr, *pr_xm = nullptr;
+  float *pr_A = nullptr, *pr_norm = nullptr;
+  std::vector<uint16_t*> pr_xs;
+  std::vector<float*> pr_B;
+  int32_t *pr_cand = nullptr, *pr_cnt = nullptr, *pr_node = nullptr, *pr_list = nullptr;
+  float* pr_phi = nullptr;
+  stm::PairDev* pr_pairs_dev = nullptr;
+  hipGraph_t graph_pr = nullptr;
+  hipGraphExec_t exec_pr = nullptr;
+  const void* cap_pr[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -73,11 +88,19 @@ void plan_drop_graph(stm_plan* p) {
   p->graph = nullptr;
 }
 
+void plan_drop_pruned_graph(stm_plan* p) {
+  if (p->exec_pr) (void)hipGraphExecDestroy(p->exec_pr);
+  if (p->graph_pr) (void)hipGraphDestroy(p->graph_pr);
+  p->exec_pr = nullptr;
+  p->graph_pr = nullptr;
+}
+
 void plan_free(stm_plan* p) {
   if (!p) return;
   (void)hipSetDevice(p->ctx->device);
   (void)hipDeviceSynchronize();
   plan_drop_graph(p);
+  plan_drop_pruned_graph(p);
   for (void* q : p->owned) (void)hipFree(q);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->ev_out) (void)hipEventDestroy(p->ev_out);
@@ -345,6 +368,9 @@ int stm_plan_create(stm_ctx* ctx, const stm_points* models, int32_t n_models, co
     if (!p->pairs_dev || !p->items_dev || !p->counters || !p->degen_items || !cost) return rc2;
     if (!ph.empty())
       STM_HIP(hipMemcpyAsync(p->pairs_dev, ph.data(), ph.size() * sizeof(stm::PairDev), hipMemcpyHostToDevice, st));
+    p->pairs_host = ph;
+    p->pair_ms.resize(n_pairs);
+    for (int q = 0; q < n_pairs; ++q) p->pair_ms[q] = make_int2(pairs[2 * q], pairs[2 * q + 1]);
     if (!items.empty()) {
       STM_HIP(hipMemcpyAsync(p->items_dev, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, st));
       const stm::SearchParams sp{p->params.T, p->params.window, p->params.k_max,
@@ -472,6 +498,205 @@ int stm_plan_run(stm_plan* p, float* energy32, double* energy64, double* energy_
   }
   return STM_OK;
 }
+
+}  // extern "C"
+
+// ---- pruned plan runs ------------------------------------------------------------
+
+namespace {
+
+constexpr int kHid = stm::kPrunerHidden;
+
+// Buffers of pruned runs for pruner dimension `dim` and lists of `kp` nodes.
+int plan_pruned_buffers(stm_plan* p, int dim, int kp) {
+  int rc = STM_OK;
+  if (p->pr_dim != dim) {
+    const int dp = stm::bf16_padded_dim(dim);
+    const long long mp = (p->m_total + 15) / 16 * 16;
+    p->pr_wa = static_cast<uint16_t*>(plan_alloc(p, (size_t)kHid * dp * 2, &rc));
+    p->pr_wb = static_cast<uint16_t*>(plan_alloc(p, (size_t)kHid * dp * 2, &rc));
+    p->pr_xm = static_cast<uint16_t*>(plan_alloc(p, (size_t)mp * dp * 2, &rc));
+    p->pr_A = static_cast<float*>(plan_alloc(p, (size_t)std::max(1LL, p->m_total) * kHid * sizeof(float), &rc));
+    long long smax = 16;
+    for (const auto& sv : p->sv) smax = std::max<long long>(smax, (sv.S + 15) / 16 * 16);
+    p->pr_norm = static_cast<float*>(plan_alloc(p, (size_t)std::max(mp, smax) * sizeof(float), &rc));
+    p->pr_xs.assign(p->n_scenes, nullptr);
+    p->pr_B.assign(p->n_scenes, nullptr);
+    for (int j = 0; j < p->n_scenes; ++j) {
+      const size_t sp = (size_t)(p->sv[j].S + 15) / 16 * 16;
+      p->pr_xs[j] = static_cast<uint16_t*>(plan_alloc(p, sp * dp * 2, &rc));
+      p->pr_B[j] = static_cast<float*>(plan_alloc(p, (size_t)std::max(1, p->sv[j].S) * kHid * sizeof(float), &rc));
+    }
+    if (rc) return rc;
+    p->pr_dim = dim;
+  }
+  if (p->pr_k < kp) {
+    long long groups = 0, gmax = 1;
+    for (const auto& d : p->pairs_host) {
+      groups += (long long)d.n_tau * d.m.M;
+      gmax = std::max(gmax, (long long)d.n_tau * d.m.M);
+    }
+    p->pr_cand = static_cast<int32_t*>(plan_alloc(p, (size_t)std::max(1LL, groups) * kp * sizeof(int32_t), &rc));
+    p->pr_cnt = static_cast<int32_t*>(plan_alloc(p, (size_t)std::max(1LL, groups) * sizeof(int32_t), &rc));
+    if (!p->pr_node) {
+      p->pr_node = static_cast<int32_t*>(plan_alloc(p, (size_t)gmax * 64 * sizeof(int32_t), &rc));
+      p->pr_phi = static_cast<float*>(plan_alloc(p, (size_t)gmax * 64 * 8 * sizeof(float), &rc));
+      p->pr_list = static_cast<int32_t*>(plan_alloc(p, (size_t)std::max(1, p->n_items) * sizeof(int32_t), &rc));
+      p->pr_pairs_dev = static_cast<stm::PairDev*>(
+          plan_alloc(p, (size_t)std::max(1, p->n_pairs) * sizeof(stm::PairDev), &rc));
+    }
+    if (rc) return rc;
+    // the pair table of pruned runs: each pair's lists inside pr_cand / pr_cnt
+    std::vector<stm::PairDev> ph = p->pairs_host;
+    long long off = 0;
+    for (auto& d : ph) {
+      d.cand = p->pr_cand + off * kp;
+      d.ccount = p->pr_cnt + off;
+      d.cstride = kp;
+      off += (long long)d.n_tau * d.m.M;
+    }
+    if (!ph.empty())
+      STM_HIP(hipMemcpy(p->pr_pairs_dev, ph.data(), ph.size() * sizeof(stm::PairDev), hipMemcpyHostToDevice));
+    p->pr_k = kp;
+  }
+  return STM_OK;
+}
+
+int plan_enqueue_pruned(stm_plan* p, stm_pruner* P, int kp, float* e32, double* e64, double* eu, int32_t* asg,
+                        int32_t* fell, hipStream_t st) {
+  int rc;
+  if ((rc = plan_enqueue_tables(p, st))) return rc;
+  const int D = P->dim, NI = 2 * D + 8, dp = stm::bf16_padded_dim(D);
+  const float* W1 = static_cast<const float*>(P->theta.p);
+  const int mp = static_cast<int>((p->m_total + 15) / 16 * 16);
+  // first-layer projections: models (with b1) and scenes
+  STM_HIP(stm::launch_cast_rows_bf16(W1, kHid, NI, 0, D, dp, p->pr_wa, st));
+  STM_HIP(stm::launch_cast_rows_bf16(W1, kHid, NI, D, D, dp, p->pr_wb, st));
+  STM_HIP(stm::launch_to_bf16(p->mdesc_all, static_cast<int32_t>(p->m_total), D, mp, p->pr_xm, p->pr_norm, st));
+  STM_HIP(stm::launch_project_bf16(p->pr_xm, static_cast<int>(p->m_total), dp, p->pr_wa, static_cast<float>(D),
+                                   W1 + (long long)kHid * NI, p->pr_A, st));
+  for (int j = 0; j < p->n_scenes; ++j) {
+    const int S = p->sv[j].S, sp = (S + 15) / 16 * 16;
+    STM_HIP(stm::launch_to_bf16(p->sv[j].desc, S, D, sp, p->pr_xs[j], p->pr_norm, st));
+    STM_HIP(stm::launch_project_bf16(p->pr_xs[j], S, dp, p->pr_wb, static_cast<float>(D), nullptr, p->pr_B[j], st));
+  }
+  // the pruned lists of every pair
+  const stm::SearchParams sp{p->params.T, std::min(p->params.window, 0x3fffffff), p->params.k_max,
+                             (p->params.flags & STM_K_DENSITY) ? 1 : 0};
+  long long off = 0;
+  for (int q = 0; q < p->n_pairs; ++q) {
+    const stm::PairDev& d = p->pairs_host[q];
+    const int i = p->pair_ms[q].x, js = p->pair_ms[q].y;
+    const long long G = (long long)d.n_tau * d.m.M;
+    stm::PrunerInfer q_;
+    q_.m = d.m;
+    q_.s = d.s;
+    q_.U = d.U;
+    q_.us = d.us;
+    q_.sp = sp;
+    q_.sp.W = std::min(q_.sp.W, d.s.F);
+    q_.groups = nullptr;
+    q_.n_groups = G;
+    q_.tau0 = 0;
+    q_.node = p->pr_node;
+    q_.phi = p->pr_phi;
+    q_.theta = W1;
+    q_.D = D;
+    q_.A = p->pr_A + p->mrow[i] * kHid;
+    q_.B = p->pr_B[js];
+    q_.topk = kp;
+    q_.rule = P->rule;
+    q_.cand = p->pr_cand + off * kp;
+    q_.count = p->pr_cnt + off;
+    q_.scores = nullptr;
+    STM_HIP(stm::launch_pruner_infer(q_, st));
+    off += G;
+  }
+  // the recursion on the pruned lists, then the exact one on the items they left infeasible
+  int32_t* inf_count = p->counters + 3;
+  STM_HIP(stm::launch_fill_i32(p->counters, 4, 0, st));
+  if (fell) STM_HIP(stm::launch_fill_i32(fell, static_cast<int>(p->row_off.back()), 0, st));
+  stm::BatchLaunch b = plan_launch(p, p->pr_pairs_dev, p->items_dev, p->n_items, e32, asg);
+  b.sp.K = kp;
+  STM_HIP(stm::launch_dp_persistent(b, p->n_cu * p->wgs_per_cu, st));
+  STM_HIP(stm::launch_collect_infeasible(p->pairs_dev, p->items_dev, p->n_items, e32, p->pr_list, inf_count, fell,
+                                         st));
+  STM_HIP(stm::launch_fill_i32(p->counters, 3, 0, st));
+  stm::BatchLaunch x = plan_launch(p, p->pairs_dev, p->items_dev, p->n_items, e32, asg);
+  x.list = p->pr_list;
+  x.list_count = inf_count;
+  STM_HIP(stm::launch_dp_persistent(x, p->n_cu * p->wgs_per_cu, st));
+  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, p->params.T, p->params.lambda1,
+                                    p->params.lambda2, p->params.lambda3, asg, e64, eu, st));
+  return STM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stm_plan_run_pruned(stm_plan* p, stm_pruner* P, int32_t topk, float* energy32, double* energy64,
+                        double* energy_u64, int32_t* assign, int32_t* fell_back, void* hip_stream) {
+  err().clear();
+  if (!p || !P) return fail(STM_EINVAL, "null plan or pruner");
+  if (P->ctx != p->ctx) return fail(STM_EINVAL, "the pruner belongs to another context");
+  if (P->dim != p->dim) return fail(STM_EINVAL, "descriptor dimension differs from the pruner's");
+  if (topk < 1 || topk > 64) return fail(STM_EINVAL, "topk must be in [1, 64]");
+  if (p->bf16) return fail(STM_EUNSUPPORTED, "pruned runs of plans with the BF16 unary table are not built");
+  if (p->row_off.back() > 0 && (!energy32 || !assign)) return fail(STM_EINVAL, "energy32 and assign are required");
+  STM_HIP(hipSetDevice(p->ctx->device));
+  const int kp = std::min<int>(topk, p->params.k_max);
+  int rc;
+  if ((rc = plan_pruned_buffers(p, P->dim, kp))) return rc;
+  const hipStream_t user = static_cast<hipStream_t>(hip_stream);
+  if (!p->device && fell_back && !p->o_fell) {
+    p->o_fell = static_cast<int32_t*>(plan_alloc(p, (size_t)std::max<int64_t>(1, p->row_off.back()) * 4, &rc));
+    if (rc) return rc;
+  }
+  float* e32 = p->device ? energy32 : p->o_e32;
+  double* e64 = p->device ? energy64 : (energy64 ? p->o_e64 : nullptr);
+  double* eu = p->device ? energy_u64 : (energy_u64 ? p->o_eu : nullptr);
+  int32_t* asg = p->device ? assign : p->o_asg;
+  int32_t* fell = p->device ? fell_back : (fell_back ? p->o_fell : nullptr);
+  const void* key[7] = {e32, e64, eu, asg, fell, P, reinterpret_cast<const void*>((intptr_t)(kp * 4 + P->rule))};
+  if (!p->exec_pr || !std::equal(key, key + 7, p->cap_pr)) {
+    plan_drop_pruned_graph(p);
+    STM_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    rc = plan_enqueue_pruned(p, P, kp, e32, e64, eu, asg, fell, p->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return fail(STM_EHIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    p->graph_pr = g;
+    STM_HIP(hipGraphInstantiate(&p->exec_pr, p->graph_pr, nullptr, nullptr, 0));
+    std::copy(key, key + 7, p->cap_pr);
+  }
+  STM_HIP(hipEventRecord(p->ev_in, user));
+  STM_HIP(hipStreamWaitEvent(p->stream, p->ev_in, 0));
+  STM_HIP(hipGraphLaunch(p->exec_pr, p->stream));
+  STM_HIP(hipEventRecord(p->ev_out, p->stream));
+  STM_HIP(hipStreamWaitEvent(user, p->ev_out, 0));
+  if (!p->device) {
+    const int64_t nr = p->row_off.back(), na = p->asg_off.back();
+    STM_HIP(hipMemcpyAsync(energy32, e32, (size_t)nr * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+    STM_HIP(hipMemcpyAsync(assign, asg, (size_t)na * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+    if (energy64)
+      STM_HIP(hipMemcpyAsync(energy64, e64, (size_t)nr * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    if (energy_u64)
+      STM_HIP(hipMemcpyAsync(energy_u64, eu, (size_t)nr * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    if (fell_back)
+      STM_HIP(hipMemcpyAsync(fell_back, fell, (size_t)nr * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+    STM_HIP(hipStreamSynchronize(p->stream));
+  }
+  return STM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 int stm_plan_autotune(stm_plan* p, const char* cache_path, int32_t n_sample, int32_t* chosen) {
   err().clear();

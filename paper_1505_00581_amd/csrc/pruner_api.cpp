@@ -22,19 +22,6 @@ long long n_params(int dim) {
 
 }  // namespace
 
-struct stm_pruner {
-  stm_ctx* ctx = nullptr;
-  int dim = 0;
-  long long n = 0;
-  long long step = 0;  // Adam steps taken since the parameters were set
-  int rule = STM_PRUNE_FRAMES_FIRST;
-  DevBuf theta, grad, am, av;
-  // per-call scratch
-  DevBuf groups, labels, node, phi, q, h1, h2, dz1, dz2, ds, loss, scores, part;
-  DevBuf wa, wb, A, B, xm, xs, norms, cand, count;
-  DevBuf taus, f32, f64, fu, fas, fell;
-};
-
 namespace {
 
 template <class T>

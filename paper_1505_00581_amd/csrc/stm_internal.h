@@ -179,6 +179,11 @@ struct PairDev {
   long long row0;       // first output row (offset 0) of the pair
   long long assign0;    // first assignment element of the pair
   int32_t n_tau;
+  // explicit candidate lists (null: the windowed rule): offset tau, point j has
+  // cand[(tau * M + j) * cstride + a], a < ccount[tau * M + j], ascending
+  const int32_t* cand = nullptr;
+  const int32_t* ccount = nullptr;
+  int32_t cstride = 0;
 };
 
 struct BatchLaunch {
@@ -188,6 +193,10 @@ struct BatchLaunch {
   int32_t* counter;     // two work counters (fast, degenerate), 0 at launch
   int32_t* degen_count; // items whose matching has coincident points, 0 at launch
   int32_t* degen_items; // [n_items] their indices into items
+  // the fast variant's items: all of items (list null), or items[list[q]] for
+  // q < *list_count (read on the device)
+  const int32_t* list = nullptr;
+  const int32_t* list_count = nullptr;
   SearchParams sp;
   float lambda1, lambda2, w;
   float* vt;            // value-table scratch, vt_stride floats per workgroup
@@ -203,6 +212,11 @@ hipError_t launch_dp_persistent(const BatchLaunch& b, int n_wg, hipStream_t st);
 hipError_t launch_item_cost(const PairDev* pairs, const int2* items, int n_items, const SearchParams& sp,
                             long long* cost, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st);
+// Items whose matching is infeasible (e32 of its row is +inf): their indices
+// appended to list (order unspecified) and counted in *count; fell[row] = 1
+// for them when fell is given (rows of the other items are left as they are).
+hipError_t launch_collect_infeasible(const PairDev* pairs, const int2* items, int n_items, const float* e32,
+                                     int32_t* list, int32_t* count, int32_t* fell, hipStream_t st);
 hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, int32_t T,
                                 double lambda1, double lambda2, double lambda3, const int32_t* assign,
                                 double* e64, double* eu64, hipStream_t st);

@@ -417,3 +417,45 @@ def test_save_load_roundtrip(ctx, small, tmp_path):
         c.load(path)
     for x in (a, b, c):
         x.close()
+
+
+@pytest.mark.parametrize("topk,rule,device", [(16, 1, True), (1, 0, False), (48, 1, False)])
+def test_plan_pruned_equals_per_pair_pruned(ctx, topk, rule, device):
+    """The batched pruned run (lists, recursion, device-side fallback, all in
+    one graph) gives every pair the rows of stm_match_pruned bit for bit; with
+    one candidate per point under the score rule the fallback answers most
+    offsets."""
+    import torch
+    w = synth.config2(41, n_models=3)
+    scene = cut(w.scenes[0], 320)
+    models, p = w.models, w.params
+    pr = stm.Pruner(ctx, models[0].dim)
+    pr.set_rule(rule)
+    pr.set_params(synth.pruner_init(models[0].dim, 12))
+    pairs = np.array([(i, 0) for i in range(len(models))], np.int32)
+    if device:
+        dm = [stm.DevicePoints.from_host(m) for m in models]
+        plan = stm.Plan(ctx, dm, [stm.DevicePoints.from_host(scene)], pairs, p)
+    else:
+        plan = stm.Plan(ctx, models, [scene], pairs, p)
+    out = plan.run_pruned(pr, topk)
+    out2 = plan.run_pruned(pr, topk, out=out)     # graph replay
+    if device:
+        torch.cuda.synchronize()
+    fell_total = 0
+    for q, (i, _) in enumerate(pairs):
+        e32, e64, _, A = [x.cpu().numpy() if hasattr(x, "cpu") else x for x in plan.pair_rows(out2, q)]
+        r0, r1 = plan.row_offsets[q], plan.row_offsets[q + 1]
+        fb = out2["fell_back"][r0:r1]
+        fb = fb.cpu().numpy() if hasattr(fb, "cpu") else fb
+        ref = pr.match(models[i], scene, p, topk=topk)
+        np.testing.assert_array_equal(e32, ref["energy32"])
+        np.testing.assert_array_equal(e64, ref["energy64"])
+        np.testing.assert_array_equal(A, ref["assign"])
+        np.testing.assert_array_equal(fb, ref["fell_back"])
+        fell_total += int(fb.sum())
+    say(f"  plan top-{topk} rule {rule}: {plan.n_rows} rows identical, {fell_total} answered by the fallback")
+    if topk == 1:
+        assert fell_total > 0
+    plan.close()
+    pr.close()
