@@ -156,3 +156,9 @@ def test_one_hip_runtime_per_process():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
                          check=True).stdout.strip().splitlines()[-1]
     assert out.count("libamdhip64") == 1, out
+
+
+def test_plan_run_pruned_rejects_null_arguments():
+    lib = stm.load()
+    assert lib.stm_plan_run_pruned(None, None, 16, None, None, None, None, None, None) == stm.STM_EINVAL
+    assert "null" in lib.stm_last_error().decode()
