@@ -48,13 +48,13 @@ def _load():
             i32, f64 = ctypes.c_int32, ctypes.c_double
             lib.oracle_match.restype = ctypes.c_int
             lib.oracle_match.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
-                                         i32, i32, i32, i32, P, i32, P, P, P, P, i32]
+                                         i32, i32, i32, i32, i32, f64, P, i32, P, P, P, P, i32]
             lib.oracle_match_lists.restype = ctypes.c_int
             lib.oracle_match_lists.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
-                                               i32, i32, P, P, i32, P, P, P, i32]
+                                               i32, i32, i32, f64, P, P, i32, P, P, P, i32]
             lib.oracle_energies.restype = None
             lib.oracle_energies.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
-                                            i32, P, i32, P, P]
+                                            i32, i32, f64, P, i32, P, P]
             lib.oracle_candidate_list.restype = i32
             lib.oracle_candidate_list.argtypes = [i32, P, i32, P, i32, i32, i32, i32, i32, P]
             lib.oracle_num_threads.restype = ctypes.c_int
@@ -78,11 +78,18 @@ def offsets(model, scene) -> range:
     return energy.offsets(model.t, scene.n_frames)
 
 
+def _dummy(params):
+    """(enabled, W^d) of the dummy assignment (Eq. 2); params.w_dummy None = off."""
+    w = getattr(params, "w_dummy", None)
+    return (0, 0.0) if w is None else (1, float(w))
+
+
 def match(model, scene, params, taus=None, n_threads: int = 0):
     """Exact optimum at each offset in `taus` (default: every offset).
 
-    Returns dict(energy [n] f64, energy_u [n] f64, assign [n,M] int32,
-    counts dict(dense_cells, feasible_cells, dense_relax, feasible_relax), taus)."""
+    Returns dict(energy [n] f64, energy_u [n] f64, assign [n,M] int32 (-1 rows
+    if infeasible, -2 for a dummy), counts dict(dense_cells, feasible_cells,
+    dense_relax, feasible_relax) over scene candidates, taus)."""
     lib = _load()
     if taus is None:
         taus = np.arange(len(offsets(model, scene)), dtype=np.int32)
@@ -97,7 +104,8 @@ def match(model, scene, params, taus=None, n_threads: int = 0):
     rc = lib.oracle_match(M, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n, scene.n_frames,
                           _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]), model.dim,
                           params.lambda1, params.lambda2, params.lambda3, params.T,
-                          params.window, params.k_max, int(params.k_density), _ptr(taus), n,
+                          params.window, params.k_max, int(params.k_density), *_dummy(params),
+                          _ptr(taus), n,
                           _ptr(e), _ptr(eu), _ptr(z), _ptr(c), n_threads)
     if rc != 0:
         raise RuntimeError(f"oracle_match failed ({rc}): recursion and literal energy disagree")
@@ -123,7 +131,8 @@ def match_lists(model, scene, params, lists, counts, n_threads: int = 0):
     rc = lib.oracle_match_lists(M, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n,
                                 scene.n_frames, _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]),
                                 model.dim, params.lambda1, params.lambda2, params.lambda3, params.T,
-                                K, _ptr(lists), _ptr(counts), n, _ptr(e), _ptr(eu), _ptr(z),
+                                K, *_dummy(params), _ptr(lists), _ptr(counts), n, _ptr(e), _ptr(eu),
+                                _ptr(z),
                                 n_threads)
     if rc != 0:
         raise RuntimeError(f"oracle_match_lists failed ({rc}): recursion and literal energy disagree")
@@ -141,7 +150,8 @@ def energies(model, scene, params, assign):
             _f32(scene.desc)]
     lib.oracle_energies(model.n, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n,
                         scene.n_frames, _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]), model.dim,
-                        params.lambda1, params.lambda2, params.lambda3, params.T, _ptr(z), n,
+                        params.lambda1, params.lambda2, params.lambda3, params.T, *_dummy(params),
+                        _ptr(z), n,
                         _ptr(e), _ptr(eu))
     return e, eu
 

@@ -11,7 +11,9 @@ listed, with reasons, in the design notes of the repository.
 Conventions (all FP64; float32 inputs are upcast exactly):
   * model: M points, xy [M,2], frames t [M] strictly increasing, desc [M,D];
   * scene: S points sorted by frame, xy [S,2], frames t' [S], desc [S,D];
-  * an assignment z maps model point i (0-based here) to a scene node id.
+  * an assignment z maps model point i (0-based here) to a scene node id, or
+    to the dummy value epsilon (DUMMY = -2) when dummy assignments are enabled
+    (params.w_dummy = W^d, the dummy's unary cost of Eq. 2; None = disabled).
 """
 from __future__ import annotations
 
@@ -21,6 +23,12 @@ import math
 import numpy as np
 
 INF = math.inf
+DUMMY = -2  # the dummy value epsilon of Eq. 2 in assignments
+
+
+def w_dummy(params):
+    """W^d of Eq. 2, or None when dummy assignments are disabled."""
+    return getattr(params, "w_dummy", None)
 
 
 def offsets(model_t: np.ndarray, n_frames: int) -> range:
@@ -109,25 +117,46 @@ def triangle_cost(model, scene, i: int, zi: int, zj: int, zk: int, lambda3: floa
 
     D^t = Delta(i, j) + Delta(j, k) (Eq. 4).
     D^g = L2 norm of the wrapped differences of the angle at j and the angle
-    at i between model and scene triangles (Eq. 6)."""
+    at i between model and scene triangles (Eq. 6).
+
+    READING for dummies (the paper defines only U for them, Eq. 2): a Delta
+    term counts only when both of its points are scene points, D^g only when
+    all three are."""
     j, k = i - 1, i - 2
     mt, st = model.t, scene.t
-    dt = delta(mt[i], mt[j], st[zi], st[zj]) + delta(mt[j], mt[k], st[zj], st[zk])
+    dt = 0.0
+    if zi != DUMMY and zj != DUMMY:
+        dt += delta(mt[i], mt[j], st[zi], st[zj])
+    if zj != DUMMY and zk != DUMMY:
+        dt += delta(mt[j], mt[k], st[zj], st[zk])
+    if DUMMY in (zi, zj, zk):
+        return dt
     p, q = model.xy.astype(np.float64), scene.xy.astype(np.float64)
     d_mid = wrap(ang(p[i], p[j], p[k]) - ang(q[zi], q[zj], q[zk]))
     d_end = wrap(ang(p[j], p[i], p[k]) - ang(q[zj], q[zi], q[zk]))
     return dt + lambda3 * math.sqrt(d_mid * d_mid + d_end * d_end)
 
 
+def unary_of(model, scene, i: int, zi: int, params) -> float:
+    """U(z_i) of Eq. 2: the descriptor distance, or W^d for the dummy."""
+    return float(w_dummy(params)) if zi == DUMMY else unary(model.desc[i], scene.desc[zi])
+
+
 def energy(model, scene, z, params) -> float:
     """E(z) = lambda1 sum_i U(z_i) + lambda2 sum_{i>=3} D(z_i, z_{i-1}, z_{i-2})
     (Eq. 1 restricted to the chain hypergraph, Eq. 9), or +inf when a pair of
-    consecutive points breaks causality or closeness (Eq. 7, Eq. 8)."""
+    consecutive points breaks causality or closeness (Eq. 7, Eq. 8).  READING:
+    the constraints bind consecutive points that are both scene points; a
+    dummy on either side lifts them."""
     M = len(z)
+    if DUMMY in list(z) and w_dummy(params) is None:
+        return INF
     for i in range(1, M):
+        if z[i - 1] == DUMMY or z[i] == DUMMY:
+            continue
         if not admissible(int(scene.t[z[i - 1]]), int(scene.t[z[i]]), params.T):
             return INF
-    eu = sum(unary(model.desc[i], scene.desc[z[i]]) for i in range(M))
+    eu = sum(unary_of(model, scene, i, z[i], params) for i in range(M))
     ed = sum(triangle_cost(model, scene, i, z[i], z[i - 1], z[i - 2], params.lambda3)
              for i in range(2, M))
     return params.lambda1 * eu + params.lambda2 * ed
@@ -136,7 +165,7 @@ def energy(model, scene, z, params) -> float:
 def energy_u(model, scene, z, params) -> float:
     """The appearance part lambda1 sum_i U(z_i) alone (the distance used by the
     paper's nearest-prototype classifier, Section 4)."""
-    return params.lambda1 * sum(unary(model.desc[i], scene.desc[z[i]]) for i in range(len(z)))
+    return params.lambda1 * sum(unary_of(model, scene, i, z[i], params) for i in range(len(z)))
 
 
 def candidate_lists(model, scene, params, tau: int):
@@ -149,9 +178,13 @@ def brute_force(model, scene, params, tau: int, lists=None):
     enumeration: the definition of the exact matching (Section 2.2).  `lists`
     replaces the windowed lists of offset tau when given.
 
+    With dummy assignments enabled every point may also take DUMMY.
+
     Returns (E*, list of all optimal assignments); E* = +inf and [] when no
     assignment is admissible.  Only for tiny inputs."""
     cands = candidate_lists(model, scene, params, tau) if lists is None else lists
+    if w_dummy(params) is not None:
+        cands = [list(c) + [DUMMY] for c in cands]
     if any(len(c) == 0 for c in cands):
         return INF, []
     best, arg = INF, []

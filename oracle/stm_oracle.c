@@ -18,6 +18,13 @@
  * nodes within W frames of the shifted model frame, first K by
  * (|frame difference|, node id), stored in ascending node order.
  *
+ * Dummy assignments (Eq. 2): when enabled, every model point may also take the
+ * dummy value z_i = epsilon (node id -2 in assignments) at the cost U = W^d.
+ * READING (the paper defines only U for a dummy): each term of D is evaluated
+ * where its points exist -- Delta(p, q) only when z_p and z_q are both scene
+ * points, D^g only when all three are -- and causality and closeness apply
+ * to consecutive points that are both scene points.
+ *
  * Indices are 0-based: model points 0..M-1, the triangle ending at point i
  * (i >= 2) is (i, i-1, i-2).  Everything is FP64; float inputs are upcast.
  */
@@ -30,6 +37,7 @@
 #endif
 
 #define ORACLE_PI 3.14159265358979323846
+#define ORACLE_EPS (-2) /* the dummy value epsilon in assignments */
 
 typedef struct {
   int32_t M, S, F, dim;
@@ -37,6 +45,8 @@ typedef struct {
   const int32_t *mt, *st;
   double lambda1, lambda2, lambda3;
   int32_t T, W, K, k_density;
+  int32_t dummy; /* dummy assignments enabled */
+  double wd;     /* W^d, the unary cost of a dummy (Eq. 2) */
 } problem;
 
 /* Oriented angle at vertex b of triangle (a, b, c), ray b->a to ray b->c;
@@ -62,11 +72,21 @@ static double delta(int32_t tp, int32_t tq, int32_t sp, int32_t sq) {
   return (double)(d < 0 ? -d : d);
 }
 
-/* D(z_i, z_{i-1}, z_{i-2}) = D^t + lambda3 * D^g (Eq. 3, 4, 6). */
+/* A consecutive pair (z_{i-1}, z_i) is allowed: admissible, or a dummy on
+ * either side. */
+static int pair_ok(const problem* p, int32_t zprev, int32_t zcur) {
+  if (zprev == ORACLE_EPS || zcur == ORACLE_EPS) return 1;
+  return admissible(p->st[zprev], p->st[zcur], p->T);
+}
+
+/* D(z_i, z_{i-1}, z_{i-2}) = D^t + lambda3 * D^g (Eq. 3, 4, 6); with dummies,
+ * each Delta needs both of its points and D^g all three. */
 static double triangle_cost(const problem* p, int i, int32_t zi, int32_t zj, int32_t zk) {
   int j = i - 1, k = i - 2;
-  double dt = delta(p->mt[i], p->mt[j], p->st[zi], p->st[zj]) +
-              delta(p->mt[j], p->mt[k], p->st[zj], p->st[zk]);
+  double dt = 0.0;
+  if (zi != ORACLE_EPS && zj != ORACLE_EPS) dt += delta(p->mt[i], p->mt[j], p->st[zi], p->st[zj]);
+  if (zj != ORACLE_EPS && zk != ORACLE_EPS) dt += delta(p->mt[j], p->mt[k], p->st[zj], p->st[zk]);
+  if (zi == ORACLE_EPS || zj == ORACLE_EPS || zk == ORACLE_EPS) return dt;
   const float *m = p->mxy, *s = p->sxy;
   double mid_m = ang(m[2 * i], m[2 * i + 1], m[2 * j], m[2 * j + 1], m[2 * k], m[2 * k + 1]);
   double mid_s = ang(s[2 * zi], s[2 * zi + 1], s[2 * zj], s[2 * zj + 1], s[2 * zk], s[2 * zk + 1]);
@@ -76,8 +96,10 @@ static double triangle_cost(const problem* p, int i, int32_t zi, int32_t zj, int
   return dt + p->lambda3 * sqrt(d1 * d1 + d2 * d2);
 }
 
-/* U(z_i) = ||f_i - f'_{z_i}|| (Eq. 2), squares summed in index order. */
+/* U(z_i) = ||f_i - f'_{z_i}|| (Eq. 2), squares summed in index order; W^d
+ * for the dummy. */
 static double unary(const problem* p, int i, int32_t n) {
+  if (n == ORACLE_EPS) return p->wd;
   double s = 0.0;
   for (int d = 0; d < p->dim; ++d) {
     double v = (double)p->mdesc[(size_t)i * p->dim + d] - (double)p->sdesc[(size_t)n * p->dim + d];
@@ -87,10 +109,11 @@ static double unary(const problem* p, int i, int32_t n) {
 }
 
 /* E(z) of Eq. 1 / Eq. 9 for a full assignment; +inf if a consecutive pair is
- * inadmissible.  If eu is non-null it receives lambda1 * sum U. */
+ * inadmissible (or z holds -1, or a dummy while dummies are off).  If eu is
+ * non-null it receives lambda1 * sum U. */
 double oracle_energy(const problem* p, const int32_t* z, double* eu) {
-  for (int i = 1; i < p->M; ++i)
-    if (z[i] < 0 || z[i - 1] < 0 || !admissible(p->st[z[i - 1]], p->st[z[i]], p->T)) {
+  for (int i = 0; i < p->M; ++i)
+    if (z[i] == -1 || (z[i] == ORACLE_EPS && !p->dummy) || (i > 0 && !pair_ok(p, z[i - 1], z[i]))) {
       if (eu) *eu = INFINITY;
       return INFINITY;
     }
@@ -166,13 +189,16 @@ int32_t oracle_candidates(const problem* p, int32_t tau, int32_t i, int32_t* out
 static int match_one(const problem* p, int32_t tau, const int32_t* given, const int32_t* given_cnt,
                      double* energy, double* energy_u, int32_t* assign, long long* counts) {
   const int M = p->M, K = p->K;
+  /* States of point i: its cnt[i] candidates, then the dummy when enabled. */
+  const int KS = K + 1;
   int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (size_t)M * K);
   int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+  int32_t* nst = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
   keyed* tmp = (keyed*)malloc(sizeof(keyed) * (size_t)(p->S > 0 ? p->S : 1));
-  double* u = (double*)malloc(sizeof(double) * (size_t)M * K);
+  double* u = (double*)malloc(sizeof(double) * (size_t)M * KS);
   /* alpha_i(z_{i-1}, z_{i-2}) and beta_i for i = 2..M-1: [a_{i-1}][a_{i-2}] */
-  double* alpha = (double*)malloc(sizeof(double) * (size_t)M * K * K);
-  int32_t* beta = (int32_t*)malloc(sizeof(int32_t) * (size_t)M * K * K);
+  double* alpha = (double*)malloc(sizeof(double) * (size_t)M * KS * KS);
+  int32_t* beta = (int32_t*)malloc(sizeof(int32_t) * (size_t)M * KS * KS);
   int32_t* z = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
   int rc = 0;
 
@@ -184,13 +210,15 @@ static int match_one(const problem* p, int32_t tau, const int32_t* given, const 
     } else {
       cnt[i] = build_candidates(p, tau, i, cand + (size_t)i * K, tmp);
     }
-    if (cnt[i] == 0) empty = 1;
+    nst[i] = cnt[i] + (p->dummy ? 1 : 0);
+    if (nst[i] == 0) empty = 1;
   }
-  /* Unary look-up table (Section 3.3): U of every (point, candidate), lambda1 absorbed. */
+#define NODE(i, a) ((a) < cnt[i] ? cand[(size_t)(i) * K + (a)] : ORACLE_EPS)
+  /* Unary look-up table (Section 3.3): U of every (point, state), lambda1 absorbed. */
   for (int i = 0; i < M; ++i)
-    for (int a = 0; a < cnt[i]; ++a) u[(size_t)i * K + a] = p->lambda1 * unary(p, i, cand[(size_t)i * K + a]);
+    for (int a = 0; a < nst[i]; ++a) u[(size_t)i * KS + a] = p->lambda1 * unary(p, i, NODE(i, a));
 
-  /* work counts */
+  /* work counts (scene candidates only) */
   for (int i = 1; i < M; ++i)
     for (int b = 0; b < cnt[i - 1]; ++b)
       for (int a = 0; a < cnt[i]; ++a) {
@@ -211,21 +239,22 @@ static int match_one(const problem* p, int32_t tau, const int32_t* given, const 
 
   /* alpha_M (Eq. 11) and alpha_i (Eq. 10), i from the last point down to 2. */
   for (int i = M - 1; i >= 2; --i) {
-    const int32_t *ci = cand + (size_t)i * K, *cj = cand + (size_t)(i - 1) * K, *ck = cand + (size_t)(i - 2) * K;
-    for (int aj = 0; aj < cnt[i - 1]; ++aj)
-      for (int ak = 0; ak < cnt[i - 2]; ++ak) {
+    for (int aj = 0; aj < nst[i - 1]; ++aj)
+      for (int ak = 0; ak < nst[i - 2]; ++ak) {
+        const int32_t zj = NODE(i - 1, aj), zk = NODE(i - 2, ak);
         double best = INFINITY;
         int32_t arg = -1;
-        if (admissible(p->st[ck[ak]], p->st[cj[aj]], p->T)) {
-          for (int ai = 0; ai < cnt[i]; ++ai) {
-            if (!admissible(p->st[cj[aj]], p->st[ci[ai]], p->T)) continue;
-            double v = u[(size_t)i * K + ai] + p->lambda2 * triangle_cost(p, i, ci[ai], cj[aj], ck[ak]);
-            if (i < M - 1) v += alpha[((size_t)(i + 1) * K + ai) * K + aj];
+        if (pair_ok(p, zk, zj)) {
+          for (int ai = 0; ai < nst[i]; ++ai) {
+            const int32_t zi = NODE(i, ai);
+            if (!pair_ok(p, zj, zi)) continue;
+            double v = u[(size_t)i * KS + ai] + p->lambda2 * triangle_cost(p, i, zi, zj, zk);
+            if (i < M - 1) v += alpha[((size_t)(i + 1) * KS + ai) * KS + aj];
             if (v < best) { best = v; arg = ai; }
           }
         }
-        alpha[((size_t)i * K + aj) * K + ak] = best;
-        beta[((size_t)i * K + aj) * K + ak] = arg;
+        alpha[((size_t)i * KS + aj) * KS + ak] = best;
+        beta[((size_t)i * KS + aj) * KS + ak] = arg;
       }
   }
   /* Initial search for (z_1, z_2) (Eq. 13): first lexicographic argmin over
@@ -233,22 +262,23 @@ static int match_one(const problem* p, int32_t tau, const int32_t* given, const 
   {
     double best = INFINITY;
     int32_t b0 = -1, b1 = -1;
-    for (int a0 = 0; a0 < cnt[0]; ++a0)
-      for (int a1 = 0; a1 < cnt[1]; ++a1) {
-        double v = u[a0] + u[(size_t)K + a1] + alpha[((size_t)2 * K + a1) * K + a0];
+    for (int a0 = 0; a0 < nst[0]; ++a0)
+      for (int a1 = 0; a1 < nst[1]; ++a1) {
+        double v = u[a0] + u[(size_t)KS + a1] + alpha[((size_t)2 * KS + a1) * KS + a0];
         if (v < best) { best = v; b0 = a0; b1 = a1; }
       }
     if (!(best < INFINITY)) goto infeasible;
     /* Backtracking (Eq. 12). */
     int32_t a_prev2 = b0, a_prev1 = b1;
-    z[0] = cand[b0];
-    z[1] = cand[(size_t)K + b1];
+    z[0] = NODE(0, b0);
+    z[1] = NODE(1, b1);
     for (int i = 2; i < M; ++i) {
-      int32_t ai = beta[((size_t)i * K + a_prev1) * K + a_prev2];
-      z[i] = cand[(size_t)i * K + ai];
+      int32_t ai = beta[((size_t)i * KS + a_prev1) * KS + a_prev2];
+      z[i] = NODE(i, ai);
       a_prev2 = a_prev1;
       a_prev1 = ai;
     }
+#undef NODE
     double eu = 0.0;
     double e = oracle_energy(p, z, &eu);
     /* The recursion's optimum must equal the literal energy of its argmin. */
@@ -264,30 +294,33 @@ infeasible:
   if (energy_u) *energy_u = INFINITY;
   for (int i = 0; i < M; ++i) assign[i] = -1;
 done:
-  free(cand); free(cnt); free(tmp); free(u); free(alpha); free(beta); free(z);
+  free(cand); free(cnt); free(nst); free(tmp); free(u); free(alpha); free(beta); free(z);
   return rc;
 }
 
 static problem make_problem(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                             int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
                             int32_t dim, double l1, double l2, double l3, int32_t T, int32_t W, int32_t K,
-                            int32_t k_density) {
+                            int32_t k_density, int32_t dummy, double wd) {
   problem p;
   p.M = M; p.S = S; p.F = F; p.dim = dim;
   p.mxy = mxy; p.mt = mt; p.mdesc = mdesc; p.sxy = sxy; p.st = st; p.sdesc = sdesc;
   p.lambda1 = l1; p.lambda2 = l2; p.lambda3 = l3; p.T = T; p.W = W; p.K = K; p.k_density = k_density;
+  p.dummy = dummy; p.wd = wd;
   return p;
 }
 
 /* Exact matching at offsets taus[0..n_tau-1]: energy [n_tau], energy_u [n_tau]
- * (nullable), assign [n_tau*M] (-1 rows if infeasible), counts[4] totals.
+ * (nullable), assign [n_tau*M] (-1 rows if infeasible, -2 for a dummy),
+ * counts[4] totals.  dummy != 0 enables dummy assignments of cost wd.
  * Returns 0, or -5 if a re-evaluated optimum disagreed with the recursion. */
 int oracle_match(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                  int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
                  int32_t dim, double l1, double l2, double l3, int32_t T, int32_t W, int32_t K,
-                 int32_t k_density, const int32_t* taus, int32_t n_tau, double* energy,
-                 double* energy_u, int32_t* assign, long long* counts, int32_t n_threads) {
-  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, W, K, k_density);
+                 int32_t k_density, int32_t dummy, double wd, const int32_t* taus, int32_t n_tau,
+                 double* energy, double* energy_u, int32_t* assign, long long* counts, int32_t n_threads) {
+  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, W, K, k_density,
+                           dummy, wd);
   long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
   int rc = 0;
 #ifdef _OPENMP
@@ -310,9 +343,9 @@ int oracle_match(int32_t M, const float* mxy, const int32_t* mt, const float* md
 int oracle_match_lists(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                        int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
                        int32_t dim, double l1, double l2, double l3, int32_t T, int32_t K,
-                       const int32_t* lists, const int32_t* counts_in, int32_t n_tau, double* energy,
-                       double* energy_u, int32_t* assign, int32_t n_threads) {
-  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, K, 0);
+                       int32_t dummy, double wd, const int32_t* lists, const int32_t* counts_in,
+                       int32_t n_tau, double* energy, double* energy_u, int32_t* assign, int32_t n_threads) {
+  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, K, 0, dummy, wd);
   int rc = 0;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -327,12 +360,13 @@ int oracle_match_lists(int32_t M, const float* mxy, const int32_t* mt, const flo
   return rc;
 }
 
-/* E(z) for n assignments z [n*M] (Eq. 1); energy_u nullable. */
+/* E(z) for n assignments z [n*M] (Eq. 1; -2 = dummy when dummy != 0);
+ * energy_u nullable. */
 void oracle_energies(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                      int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
-                     int32_t dim, double l1, double l2, double l3, int32_t T, const int32_t* z,
-                     int32_t n, double* energy, double* energy_u) {
-  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, 1, 0);
+                     int32_t dim, double l1, double l2, double l3, int32_t T, int32_t dummy, double wd,
+                     const int32_t* z, int32_t n, double* energy, double* energy_u) {
+  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, 1, 0, dummy, wd);
   for (int32_t j = 0; j < n; ++j)
     energy[j] = oracle_energy(&p, z + (size_t)j * M, energy_u ? energy_u + j : NULL);
 }
@@ -341,7 +375,7 @@ void oracle_energies(int32_t M, const float* mxy, const int32_t* mt, const float
 int32_t oracle_candidate_list(int32_t M, const int32_t* mt, int32_t S, const int32_t* st,
                               int32_t W, int32_t K, int32_t k_density, int32_t tau, int32_t i,
                               int32_t* out) {
-  problem p = make_problem(M, NULL, mt, NULL, S, 0, NULL, st, NULL, 0, 0, 0, 0, 0, W, K, k_density);
+  problem p = make_problem(M, NULL, mt, NULL, S, 0, NULL, st, NULL, 0, 0, 0, 0, 0, W, K, k_density, 0, 0.0);
   return oracle_candidates(&p, tau, i, out);
 }
 

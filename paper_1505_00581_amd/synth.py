@@ -54,6 +54,7 @@ class Params:
     k_max: int = 16      # candidate cap K
     k_density: bool = False  # per-point K from local density (batched workload)
     unary_bf16: bool = False  # unary table from BF16 descriptors on MFMA
+    w_dummy: float | None = None  # W^d: unary cost of a dummy assignment (Eq. 2); None = no dummies
 
 
 @dataclasses.dataclass
