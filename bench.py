@@ -366,6 +366,45 @@ def bench_paper_blocks(ctx, steps: int):
                               "block); different hardware and inputs, context only")
 
 
+def bench_dummy(ctx, dms, ds, p, wd: float, steps: int, warmup: int, exact_ms: float, outs):
+    """The measured step with dummy assignments (Eq. 2, W^d = wd): the same
+    plan over every model's offsets, each point also free to stay unmatched."""
+    import torch
+
+    import paper_1505_00581_amd as stm
+    pd = dataclasses.replace(p, w_dummy=wd)
+    pairs = np.array([(i, 0) for i in range(len(dms))], np.int32)
+    plan = stm.Plan(ctx, dms, [ds], pairs, pd)
+    out = plan.run()
+    for _ in range(warmup):
+        plan.run(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(out)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    e_d, rows_with, n_dummy, n_points = [], 0, 0, 0
+    for q, dm in enumerate(dms):
+        r = plan.pair_rows(out, q)
+        e_d.append(r[0].cpu().numpy())
+        A = r[3].cpu().numpy().reshape(r[0].shape[0], int(dm.t.shape[0]))
+        rows_with += int((A == -2).any(1).sum())
+        n_dummy += int((A == -2).sum())
+        n_points += A.size
+    plan.close()
+    e_d = np.concatenate(e_d).astype(np.float64)
+    e_x = np.concatenate([o["energy32"].cpu().numpy() for o in outs]).astype(np.float64)
+    fin = np.isfinite(e_x)
+    res = dict(w_dummy=wd, ms_per_step=round(ms, 3), value=round(e_d.size / ms * 1e3, 2), unit="matchings/s",
+               exact_plan_ms_per_step=round(exact_ms, 3),
+               offsets_with_dummies=round(rows_with / e_d.size, 5), dummy_points=round(n_dummy / n_points, 5),
+               mean_energy_drop=round(float(((e_x[fin] - e_d[fin]) / e_x[fin]).mean()), 5),
+               never_above_exact=bool((e_d[fin] <= e_x[fin]).all()), all_feasible=bool(np.isfinite(e_d).all()))
+    log(f"dummy assignments: {res}")
+    return res
+
+
 def bench_t_sweep(ctx, w, dms, ds, steps: int, values):
     """Run time of the exact step against the closeness limit T (the run-time
     half of the paper's Fig. 7; T <= 0 means no limit), on the same workload."""
@@ -406,6 +445,8 @@ def main():
     ap.add_argument("--batched-runs", type=int, default=3)
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "stm_tuning_cache.json"))
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruner section")
+    ap.add_argument("--dummy-cost", default="0.16,0.5,1.0",
+                    help="comma-separated W^d values of the dummy-assignment section (Eq. 2); empty: skip it")
     ap.add_argument("--t-sweep", default="", help="comma-separated closeness limits T to time "
                     "(e.g. 2,4,6,8,10,0; 0 = no limit)")
     ap.add_argument("--paper-blocks", action="store_true",
@@ -545,6 +586,11 @@ def main():
                  unary="BF16 MFMA dot products (D padded 162->192), FP32 norms and accumulation")
     log(f"split precision: {ms_bf:.2f} ms/step")
 
+    dummy = None
+    if args.dummy_cost:
+        dummy = [bench_dummy(ctx, dms, ds, p, float(x), args.steps, args.warmup, ms_per_step, outs)
+                 for x in args.dummy_cost.split(",")]
+
     cpu, parity = None, None
     if not args.no_cpu_baseline:
         try:
@@ -602,6 +648,7 @@ def main():
         "per_model_launches": per_model,
         "cpu_baseline": cpu,
         "split_precision": split,
+        "dummy_assignments": dummy,
         "parity_on_cpu_sample": parity,
     }
     if pruned is not None:

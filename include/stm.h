@@ -83,6 +83,20 @@ extern "C" {
                                  rho = points in frames f-1..f+1 around the shifted
                                  model frame f, K = clamp(floor((56 rho - 1170) / 60),
                                  8, 64), never above k_max                                */
+#define STM_DUMMY       0x8u  /* dummy assignments (Eq. 2): a model point may stay
+                                 unmatched (node id STM_DUMMY_NODE) at unary cost
+                                 w_dummy.  The paper defines only that cost; here a
+                                 Delta term of D^t (Eq. 4-5) counts only when both of
+                                 its points are matched, D^g (Eq. 6) only when all
+                                 three are, and causality and closeness (Eq. 7-8)
+                                 bind matched consecutive points only.  Every offset
+                                 is then feasible.  stm_match, stm_match_lists and
+                                 plans (stm_plan_run) take it; the pruned entry
+                                 points return STM_EUNSUPPORTED.                       */
+
+/* Node id of a dummy assignment in assignment rows (STM_DUMMY); -1 marks the
+ * rows of infeasible offsets. */
+#define STM_DUMMY_NODE (-2)
 
 /* ---- types -------------------------------------------------------------- */
 typedef struct stm_ctx stm_ctx;
@@ -111,7 +125,10 @@ typedef struct {
   int32_t T;            /* temporal closeness in frames (Eq. 8); <= 0: no limit    */
   int32_t window;       /* candidate window half-width in frames, >= 0             */
   int32_t k_max;        /* candidate cap K, 1..STM_K_LIMIT                         */
-  uint32_t flags;       /* STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY         */
+  uint32_t flags;       /* STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY |
+                           STM_DUMMY                                                */
+  double w_dummy;       /* W^d, the unary cost of a dummy (Eq. 2), finite, >= 0;
+                           read only with STM_DUMMY                                 */
 } stm_params;
 
 /* ---- context ------------------------------------------------------------ */
@@ -147,14 +164,16 @@ STM_API int stm_offsets(stm_ctx* ctx, const stm_points* model, const stm_points*
  *   energy32   FP32 optimum of the recursion, +inf if infeasible     (required)
  *   energy64   FP64 energy of the returned assignment (Eq. 1)         (nullable)
  *   energy_u64 FP64 appearance part lambda1 * sum_i U(z_i) (Eq. 2)    (nullable)
- *   assign     scene node id of every model point, -1 if infeasible   (required)
+ *   assign     scene node id of every model point, -1 if infeasible,  (required)
+ *              STM_DUMMY_NODE for a dummy (STM_DUMMY)
  * Ties are broken towards the lowest candidate index inside each minimum and
- * the first (row-major) final state pair.
+ * the first (row-major) final state pair; the dummy state counts after every
+ * candidate.
  * Errors: STM_EINVAL for n < 3 (model) or < 1 (scene), dim mismatch, model
  * frames not strictly increasing, scene frames decreasing or outside
  * [0, n_frames), non-finite coordinates or descriptors, window < 0, k_max
- * outside 1..STM_K_LIMIT, a negative or non-finite lambda, or an offset range
- * outside [0, n_frames - span). */
+ * outside 1..STM_K_LIMIT, a negative or non-finite lambda or w_dummy (with
+ * STM_DUMMY), or an offset range outside [0, n_frames - span). */
 STM_API int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
               const stm_params* params, int32_t tau_begin, int32_t tau_end,
               float* energy32, double* energy64, double* energy_u64, int32_t* assign,

@@ -22,6 +22,8 @@ STM_K_LIMIT = 64
 STM_DEVICE_PTRS = 0x1
 STM_UNARY_BF16 = 0x2
 STM_K_DENSITY = 0x4
+STM_DUMMY = 0x8
+STM_DUMMY_NODE = -2  # assignment value of a dummy (unmatched model point)
 
 EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_match",
            "stm_candidates", "stm_unary", "stm_count_work", "stm_set_dp_waves",
@@ -48,7 +50,7 @@ class _Points(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double),
                 ("lambda3", ctypes.c_double), ("T", ctypes.c_int32), ("window", ctypes.c_int32),
-                ("k_max", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("k_max", ctypes.c_int32), ("flags", ctypes.c_uint32), ("w_dummy", ctypes.c_double)]
 
 
 _lib = None
@@ -172,10 +174,12 @@ def _points(p, keep: list) -> _Points:
 
 
 def _params(params, device: bool) -> _Params:
+    wd = getattr(params, "w_dummy", None)
     flags = ((STM_DEVICE_PTRS if device else 0) | (STM_K_DENSITY if params.k_density else 0)
-             | (STM_UNARY_BF16 if getattr(params, "unary_bf16", False) else 0))
+             | (STM_UNARY_BF16 if getattr(params, "unary_bf16", False) else 0)
+             | (STM_DUMMY if wd is not None else 0))
     return _Params(params.lambda1, params.lambda2, params.lambda3, params.T, params.window,
-                   params.k_max, flags)
+                   params.k_max, flags, 0.0 if wd is None else float(wd))
 
 
 def _stream():

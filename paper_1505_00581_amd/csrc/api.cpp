@@ -59,8 +59,10 @@ int check_shapes(const stm_points* m, const stm_points* s, const stm_params* p) 
   if (p->window < 0) return fail(STM_EINVAL, "window < 0");
   if (!finite_lambda(p->lambda1) || !finite_lambda(p->lambda2) || !finite_lambda(p->lambda3))
     return fail(STM_EINVAL, "lambdas must be finite and >= 0");
-  if (p->flags & ~(STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY))
+  if (p->flags & ~(STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY | STM_DUMMY))
     return fail(STM_EUNSUPPORTED, "unknown flag");
+  if ((p->flags & STM_DUMMY) && !finite_lambda(p->w_dummy))
+    return fail(STM_EINVAL, "w_dummy must be finite and >= 0");
   return STM_OK;
 }
 
@@ -273,7 +275,7 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
   if ((rc = unary_table(ctx, pr, static_cast<float*>(ctx->U.p)))) return rc;
 
   // the recursion, in chunks of offsets bounded by the value-table scratch
-  const size_t per_tau = (size_t)(M - 2) * K * K * sizeof(float);
+  const size_t per_tau = (size_t)(M - 2) * vt_side(params) * vt_side(params) * sizeof(float);
   int chunk = static_cast<int>(std::min<size_t>(n_tau, std::max<size_t>(1, ctx->vt_chunk_bytes / per_tau)));
   if ((rc = grow(ctx, ctx->vt, per_tau * chunk, st))) return rc;
   if ((rc = grow(ctx, ctx->last2, (size_t)chunk * sizeof(int2), st))) return rc;
@@ -289,6 +291,8 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
     a.lambda1 = static_cast<float>(params->lambda1);
     a.lambda2 = static_cast<float>(params->lambda2);
     a.w = static_cast<float>(params->lambda2 * params->lambda3);
+    a.dummy = dummy_on(params) ? 1 : 0;
+    a.cw = dummy_cost32(params);
     a.tau0 = tau_begin + c0;
     a.n_tau = nc;
     a.vt = static_cast<float*>(ctx->vt.p);
@@ -315,7 +319,7 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
     STM_HIP(stm::launch_dp_degenerate(a, st));
     STM_HIP(stm::launch_backtrack(a, d_as + (size_t)c0 * M, st));
     STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp.T, params->lambda1, params->lambda2,
-                                params->lambda3, d_as + (size_t)c0 * M, nc,
+                                params->lambda3, w_dummy_of(params), d_as + (size_t)c0 * M, nc,
                                 d_e64 ? d_e64 + c0 : nullptr, d_eu ? d_eu + c0 : nullptr, st));
   }
 

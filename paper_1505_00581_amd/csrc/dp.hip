@@ -45,6 +45,20 @@
 // detects coincident points on pairs that can be admissible and flags the
 // matching; the flagged matchings are recomputed by the variant that marks
 // coincident directions as NaN and substitutes the model angle.
+//
+// Dummy assignments (Eq. 2).  With dummies every point also has the state
+// epsilon at unary cost W^d; a Delta term needs both of its points matched,
+// D^g all three, and the constraints bind matched consecutive points only.
+// So a triangle holding epsilon adds no D^g, and the cells with epsilon follow
+// from the step before without the K^3 loop:
+//   V_i(r, c)     = l1 U_i(c) + Q_i(r, c) + min(V_{i-1}(eps, r), min_k [...])
+//   V_i(r, eps)   = l1 W^d + min(V_{i-1}(eps, r), min_{k admissible} V_{i-1}(k, r))
+//   V_i(eps, c)   = l1 U_i(c) + m_{i-1},   V_i(eps, eps) = l1 W^d + m_{i-1}
+// with m_{i-1} = min(V_{i-1}(eps, eps), min_k V_{i-1}(k, eps)).  Each step keeps
+// these as two K-vectors and a scalar beside the K x K cells; epsilon is index
+// 64 in the final argmin and in backtracking (after every candidate, so ties
+// go to candidates) and index K in the value tables, whose rows then have
+// K + 1 entries.
 #include <math.h>
 
 #include "stm_internal.h"
@@ -53,6 +67,8 @@ namespace stm {
 namespace {
 
 constexpr int kMaxList = 64;  // longest candidate list = wavefront lanes
+constexpr int kEps = kMaxList;  // index of the dummy state epsilon
+constexpr int32_t kDummyNode = -2;  // epsilon in assignments
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kTwoPi = 6.28318530717958647692f;
 constexpr float kInvTwoPi = 0.15915494309189533577f;
@@ -219,8 +235,19 @@ __device__ void build_schedule(const int32_t* trow, int nrow, const int32_t* tco
   if (lane == 0) *nout = total;
 }
 
-template <int NW, int KL>
-struct DPShared {
+// Per-step vectors of the dummy state, double-buffered by step parity:
+// de[b][c] = V(eps, c), df[b][r] = V(r, eps), dg[b] = V(eps, eps).
+template <int KL, bool DUMMY>
+struct DummyShared {};
+template <int KL>
+struct DummyShared<KL, true> {
+  float de[2][KL];
+  float df[2][KL];
+  float dg[2];
+};
+
+template <int NW, int KL, bool DUMMY = false>
+struct DPShared : DummyShared<KL, DUMMY> {
   float2 va[KL * KL];   // [a_{i-2}][a_{i-1}]: (V_{i-1}, -phi(z_{i-2} -> z_{i-1}))
   float ct[KL * KL];    // [a_{i-2}][a_i]: -phi(z_{i-2} -> z_i)
   float2 cxy[4][KL];    // candidate ring: coordinates,
@@ -245,6 +272,8 @@ struct MatchView {
   long long us;
   const float2* theta;  // model angles of the triangle ending at each point
   float lambda1, lambda2, w;
+  float cw;             // l1 * W^d, the unary cost of the dummy
+  int vs;               // value-table row length: K, or K + 1 with dummies
   int tau;
   // explicit candidate lists of this matching (null: the windowed rule):
   // point j's nodes are cand[j * cstride + a], a < ccount[j], ascending
@@ -277,25 +306,28 @@ __device__ __forceinline__ Cands cands_of(const MatchView& a, int j) {
 }
 
 // Value table of step i (cells V_i(a_{i-1}, a_i), i = 1..M-2) inside the
-// matching's scratch vt [M-2][K][K].
+// matching's scratch vt [M-2][vs][vs] (with dummies, row and column K hold
+// the epsilon cells).
 __device__ __forceinline__ float* vtable(float* vt, const MatchView& a, int i) {
-  return vt + (long long)(i - 1) * a.sp.K * a.sp.K;
+  return vt + (long long)(i - 1) * a.vs * a.vs;
 }
 __device__ __forceinline__ const float* vtable(const float* vt, const MatchView& a, int i) {
-  return vt + (long long)(i - 1) * a.sp.K * a.sp.K;
+  return vt + (long long)(i - 1) * a.vs * a.vs;
 }
 
 struct DPResult {
   float v;   // optimum (+inf if infeasible)
-  int idx;   // r * 64 + c of the first minimising final pair (a_{M-2}, a_{M-1})
+  int idx;   // r * KL + c of the first minimising final pair (a_{M-2}, a_{M-1});
+             // with dummies r * (KL + 1) + c, epsilon = KL
   int flag;  // coincident points seen (fast variant)
 };
 
 // Forward pass of one matching by the whole workgroup (NW waves): writes the
 // value tables of steps 1..M-2 to vtm and returns the optimum to every thread.
-template <int NW, bool DEGEN, int KL>
-__device__ DPResult dp_forward(DPShared<NW, KL>& sh, const MatchView& a, float* vtm) {
+template <int NW, bool DEGEN, int KL, bool DUMMY = false>
+__device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, float* vtm) {
   static_assert(KL == 16 || KL == 32 || KL == 64, "list capacity");
+  static_assert(!DUMMY || KL == kMaxList, "dummies use the 64-slot layout");
   constexpr int RPW = KL / NW;  // chunk slots per wave (a step has <= KL chunks)
   const int tau = a.tau;
   const int lane = threadIdx.x & 63;
@@ -303,6 +335,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL>& sh, const MatchView& a, float* 
   const int M = a.m.M;
   const int T = a.sp.T;
   const int Kc = a.sp.K;
+  const int VS = a.vs;
   const int tm0 = a.m.t[0];
   const float INF = __builtin_inff();
   constexpr int kBuilder = NW - 1;  // wave that builds the schedules
@@ -355,7 +388,26 @@ __device__ DPResult dp_forward(DPShared<NW, KL>& sh, const MatchView& a, float* 
         const float q = a.lambda2 * fabsf(static_cast<float>(dtm - (tp - tr)));
         vr[s] = (sh.cu[0][r] + sh.cu[1][col]) + q;
         ar[s] = neg_dir<DEGEN>(xr, xa);
-        if (valid) vt[r * Kc + col] = vr[s];
+        if (valid) vt[r * VS + col] = vr[s];
+      }
+    }
+    if constexpr (DUMMY) {
+      if (wv == 0) {
+        const float cw = a.cw;
+        if (lane < sh.ck[1]) {
+          const float e = cw + sh.cu[1][lane];
+          sh.de[1][lane] = e;
+          vt[Kc * VS + lane] = e;
+        }
+        if (lane < sh.ck[0]) {
+          const float f = sh.cu[0][lane] + cw;
+          sh.df[1][lane] = f;
+          vt[lane * VS + Kc] = f;
+        }
+        if (lane == 0) {
+          sh.dg[1] = cw + cw;
+          vt[Kc * VS + Kc] = cw + cw;
+        }
       }
     }
   }
@@ -424,6 +476,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL>& sh, const MatchView& a, float* 
         const float2* vcol = sh.va + r;
         const float* ccol = sh.ct + col;
         float best = INF;
+        if constexpr (DUMMY) best = sh.de[prv][r];  // predecessor epsilon: no D^g
         int k = c.lo;
         for (; k + 3 < c.hi; k += 4) {
           const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
@@ -440,16 +493,46 @@ __device__ DPResult dp_forward(DPShared<NW, KL>& sh, const MatchView& a, float* 
         }
         const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
         vnew = (sh.cu[s0][col] + q) + best;
-        if (valid && vt) vt[r * Kc + col] = vnew;
+        if (valid && vt) vt[r * VS + col] = vnew;
       }
       vr[s] = vnew;
       ar[s] = anew;
+    }
+    if constexpr (DUMMY) {
+      // the epsilon cells of step i, from step i-1's cells and epsilon cells
+      if (wv == kBuilder) {
+        const float cw = a.cw;
+        if (lane < Kp) {
+          // V_i(r, eps): over the admissible predecessors of row r, no D^g
+          const int f = sh.ctt[s1][lane];
+          const int hi = count_lt(sh.ctt[s2], Kq, f);
+          const int lo = T > 0 ? count_lt(sh.ctt[s2], Kq, f - T + 1) : 0;
+          float m = sh.de[prv][lane];
+          for (int k = lo; k < hi; ++k) m = fminf(m, sh.va[k * KL + lane].x);
+          const float v = cw + m;
+          sh.df[cur][lane] = v;
+          if (vt) vt[lane * VS + Kc] = v;
+        }
+        float m = lane < Kq ? sh.df[prv][lane] : INF;
+        for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
+        m = fminf(m, sh.dg[prv]);
+        if (lane < Kn) {
+          const float v = sh.cu[s0][lane] + m;
+          sh.de[cur][lane] = v;
+          if (vt) vt[Kc * VS + lane] = v;
+        }
+        if (lane == 0) {
+          sh.dg[cur] = cw + m;
+          if (vt) vt[Kc * VS + Kc] = cw + m;
+        }
+      }
     }
     __syncthreads();
   }
 
   // ---- optimum: first row-major minimum of V_{M-1}(a_{M-2}, a_{M-1}) ------------
   {
+    constexpr int RS = KL + (DUMMY ? 1 : 0);  // row stride of the result index
     const int last = (M - 1) & 1;
     const int nch = sh.nch[last];
     float bv = INF;
@@ -461,9 +544,19 @@ __device__ DPResult dp_forward(DPShared<NW, KL>& sh, const MatchView& a, float* 
         const Chunk c = unpack_chunk(sh.sched[last][ch]);
         int r, col;
         if (chunk_cell(c, lane, r, col)) {
-          const int idx = r * KL + col;
+          const int idx = r * RS + col;
           if (vr[s] < bv || (vr[s] == bv && idx < bi)) { bv = vr[s]; bi = idx; }
         }
+      }
+    }
+    if constexpr (DUMMY) {
+      if (wv == 0) {
+        auto take = [&](float v, int idx) {
+          if (v < bv || (v == bv && idx < bi)) { bv = v; bi = idx; }
+        };
+        if (lane < sh.ck[(M - 2) & 3]) take(sh.df[last][lane], lane * RS + kEps);
+        if (lane < sh.ck[(M - 1) & 3]) take(sh.de[last][lane], kEps * RS + lane);
+        if (lane == 0) take(sh.dg[last], kEps * RS + kEps);
       }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -495,34 +588,52 @@ __device__ DPResult dp_forward(DPShared<NW, KL>& sh, const MatchView& a, float* 
 // From the optimal final pair (r, c) = (a_{M-2}, a_{M-1}), each step recomputes
 // the terms of the optimal cell over its admissible predecessors (lanes) with
 // the forward pass's arithmetic and keeps the lowest index of the minimum.
-template <bool DEGEN>
+// With dummies r and c may be kEps; the epsilon predecessor comes last, so it
+// is taken only when its term is strictly smaller.
+template <bool DEGEN, bool DUMMY = false>
 __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int c, int lane,
                                int32_t* out) {
-  const int M = a.m.M, Kc = a.sp.K, tau = a.tau, tm0 = a.m.t[0];
+  const int M = a.m.M, Kc = a.sp.K, VS = a.vs;
   const float INF = __builtin_inff();
+  auto node_of = [&](const Cands& q, int idx) { return DUMMY && idx == kEps ? kDummyNode : q.node(idx); };
   Cands cc = cands_of(a, M - 1);
   Cands cr = cands_of(a, M - 2);
   if (lane == 0) {
-    out[M - 1] = cc.node(c);
-    out[M - 2] = cr.node(r);
+    out[M - 1] = node_of(cc, c);
+    out[M - 2] = node_of(cr, r);
   }
   for (int i = M - 1; i >= 2; --i) {
     const Cands ck = cands_of(a, i - 2);
     const int nk = ck.count();
-    const int nr = cr.node(r), nc = cc.node(c);
-    const float2 xr = a.s.xy[nr], xa = a.s.xy[nc];
-    const int tr = a.s.t[nr];
-    const float2 th = a.theta[i];
-    const bool same = xa.x == xr.x && xa.y == xr.y;
-    float bm, be;
-    cell_brackets(th, -neg_dir<DEGEN>(xr, xa), bm, be);
-    float tot = INF;
-    if (lane < nk) {
-      const int nkn = ck.node(lane);
-      if (admissible(a.s.t[nkn], tr, a.sp.T)) {
-        const float2 pk = a.s.xy[nkn];
-        const float v = vtable(vtm, a, i - 1)[lane * Kc + r];
-        tot = relax<DEGEN>(v, neg_dir<DEGEN>(pk, xr), neg_dir<DEGEN>(pk, xa), bm, be, th, same, a.w);
+    const float* vp = vtable(vtm, a, i - 1);
+    float tot = INF, teps = INF;
+    if (DUMMY && r == kEps) {
+      // V_i(eps, .) = ... + min(V_{i-1}(eps, eps), min_k V_{i-1}(k, eps))
+      if (lane < nk) tot = vp[lane * VS + Kc];
+      teps = vp[Kc * VS + Kc];
+    } else {
+      const int nr = cr.node(r);
+      const float2 xr = a.s.xy[nr];
+      const int tr = a.s.t[nr];
+      if (DUMMY) teps = vp[Kc * VS + r];
+      if (DUMMY && c == kEps) {
+        // V_i(r, eps) = l1 W^d + min(V_{i-1}(eps, r), min_k V_{i-1}(k, r))
+        if (lane < nk && admissible(a.s.t[ck.node(lane)], tr, a.sp.T)) tot = vp[lane * VS + r];
+      } else {
+        const int nc = cc.node(c);
+        const float2 xa = a.s.xy[nc];
+        const float2 th = a.theta[i];
+        const bool same = xa.x == xr.x && xa.y == xr.y;
+        float bm, be;
+        cell_brackets(th, -neg_dir<DEGEN>(xr, xa), bm, be);
+        if (lane < nk) {
+          const int nkn = ck.node(lane);
+          if (admissible(a.s.t[nkn], tr, a.sp.T)) {
+            const float2 pk = a.s.xy[nkn];
+            const float v = vp[lane * VS + r];
+            tot = relax<DEGEN>(v, neg_dir<DEGEN>(pk, xr), neg_dir<DEGEN>(pk, xa), bm, be, th, same, a.w);
+          }
+        }
       }
     }
     int bk = lane;
@@ -531,7 +642,8 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
       const int ok = __shfl_xor(bk, off);
       if (ot < tot || (ot == tot && ok < bk)) { tot = ot; bk = ok; }
     }
-    if (lane == 0) out[i - 2] = ck.node(bk);
+    if (DUMMY && teps < tot) bk = kEps;
+    if (lane == 0) out[i - 2] = node_of(ck, bk);
     c = r;
     r = bk;
     cc = cr;
@@ -551,6 +663,8 @@ __device__ __forceinline__ MatchView view_of(const DPLaunch& a, int tl) {
   v.lambda1 = a.lambda1;
   v.lambda2 = a.lambda2;
   v.w = a.w;
+  v.cw = a.cw;
+  v.vs = a.sp.K + (a.dummy ? 1 : 0);
   v.tau = a.taus ? a.taus[tl] : a.tau0 + tl;
   v.cand = a.cand ? a.cand + (long long)tl * a.m.M * a.cstride : nullptr;
   v.ccount = a.cand ? a.ccount + (long long)tl * a.m.M : nullptr;
@@ -559,18 +673,20 @@ __device__ __forceinline__ MatchView view_of(const DPLaunch& a, int tl) {
 }
 
 __device__ __forceinline__ float* scratch_of(const DPLaunch& a, int tl) {
-  return a.vt + (long long)tl * (a.m.M - 2) * a.sp.K * a.sp.K;
+  const long long vs = a.sp.K + (a.dummy ? 1 : 0);
+  return a.vt + (long long)tl * (a.m.M - 2) * vs * vs;
 }
 
-template <int NW, bool DEGEN, int KL>
+template <int NW, bool DEGEN, int KL, bool DUMMY = false>
 __global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
-  __shared__ DPShared<NW, KL> sh;
+  __shared__ DPShared<NW, KL, DUMMY> sh;
   const int tl = blockIdx.x;
   if (DEGEN && a.degen[tl] == 0) return;
-  const DPResult r = dp_forward<NW, DEGEN, KL>(sh, view_of(a, tl), scratch_of(a, tl));
+  const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY>(sh, view_of(a, tl), scratch_of(a, tl));
   if (threadIdx.x == 0) {
+    constexpr int RS = KL + (DUMMY ? 1 : 0);
     a.e32[tl] = r.v;
-    a.last2[tl] = make_int2(r.idx / KL, r.idx % KL);
+    a.last2[tl] = make_int2(r.idx / RS, r.idx % RS);
     if (!DEGEN) a.degen[tl] = r.flag;
   }
 }
@@ -585,8 +701,14 @@ __global__ __launch_bounds__(64) void k_backtrack(DPLaunch a, int32_t* __restric
   }
   const MatchView v = view_of(a, tl);
   const int2 l2 = a.last2[tl];
-  if (a.degen[tl]) backtrack_wave<true>(v, scratch_of(a, tl), l2.x, l2.y, lane, out);
-  else backtrack_wave<false>(v, scratch_of(a, tl), l2.x, l2.y, lane, out);
+  float* vt = scratch_of(a, tl);
+  if (a.dummy) {
+    if (a.degen[tl]) backtrack_wave<true, true>(v, vt, l2.x, l2.y, lane, out);
+    else backtrack_wave<false, true>(v, vt, l2.x, l2.y, lane, out);
+  } else {
+    if (a.degen[tl]) backtrack_wave<true>(v, vt, l2.x, l2.y, lane, out);
+    else backtrack_wave<false>(v, vt, l2.x, l2.y, lane, out);
+  }
 }
 
 // ---- batched persistent launch ------------------------------------------------------
@@ -605,6 +727,8 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
   v.lambda1 = b.lambda1;
   v.lambda2 = b.lambda2;
   v.w = b.w;
+  v.cw = b.cw;
+  v.vs = b.sp.K + (b.dummy ? 1 : 0);
   v.tau = tau;
   v.cand = pd.cand ? pd.cand + (long long)tau * pd.m.M * pd.cstride : nullptr;
   v.ccount = pd.cand ? pd.ccount + (long long)tau * pd.m.M : nullptr;
@@ -615,10 +739,10 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
 // The fast variant takes every item; an item whose matching has coincident
 // points is appended to the degenerate list instead of being backtracked, and
 // the degenerate variant (a second launch) takes the items of that list.
-template <int NW, bool DEGEN, int KL = kMaxList>
+template <int NW, bool DEGEN, int KL = kMaxList, bool DUMMY = false>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW >= 8 ? 6 : 3)))
 void k_dp_persistent(BatchLaunch b) {
-  __shared__ DPShared<NW, KL> sh;
+  __shared__ DPShared<NW, KL, DUMMY> sh;
   __shared__ int item_sh;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* vtm = b.vt + (long long)blockIdx.x * b.vt_stride;
@@ -635,15 +759,16 @@ void k_dp_persistent(BatchLaunch b) {
     const int2 it = b.items[item];
     const PairDev pd = b.pairs[it.x];
     const MatchView mv = view_of(b, pd, it.y);
-    const DPResult r = dp_forward<NW, DEGEN, KL>(sh, mv, vtm);
+    const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY>(sh, mv, vtm);
     if (!DEGEN && r.flag) {
       if (threadIdx.x == 0) b.degen_items[atomicAdd(b.degen_count, 1)] = item;
     } else if (wv == 0) {
+      constexpr int RS = KL + (DUMMY ? 1 : 0);
       const long long row = pd.row0 + it.y;
       int32_t* out = b.assign + pd.assign0 + (long long)it.y * pd.m.M;
       if (lane == 0) b.e32[row] = r.v;
       if (r.v < __builtin_inff()) {
-        backtrack_wave<DEGEN>(mv, vtm, r.idx / KL, r.idx % KL, lane, out);
+        backtrack_wave<DEGEN, DUMMY>(mv, vtm, r.idx / RS, r.idx % RS, lane, out);
       } else {
         for (int i = lane; i < pd.m.M; i += 64) out[i] = -1;
       }
@@ -701,13 +826,15 @@ __device__ __forceinline__ double wrap64(double x) {
 }
 
 // One wave re-scores the assignment z of one matching into e64[row], eu64[row].
+// A dummy (kDummyNode) costs wd; a Delta term needs both of its points
+// matched, D^g all three, and only matched consecutive points are checked.
 __device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, double l1, double l2,
-                             double l3, const int32_t* __restrict__ z, long long tl,
+                             double l3, double wd, const int32_t* __restrict__ z, long long tl,
                              double* __restrict__ e64, double* __restrict__ eu64) {
   const int lane = threadIdx.x & 63;
   const int M = m.M, dim = s.dim;
   const double inf = __builtin_inf();
-  if (z[0] < 0) {
+  if (z[0] == -1) {
     if (lane == 0) {
       if (e64) e64[tl] = inf;
       if (eu64) eu64[tl] = inf;
@@ -718,17 +845,32 @@ __device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, 
   int bad = 0;
   for (int i = lane; i < M; i += 64) {
     const int n = z[i];
-    const float* f = m.desc + (long long)i * dim;
-    const float* g = s.desc + (long long)n * dim;
-    double acc = 0.0;
-    for (int d = 0; d < dim; ++d) {
-      const double v = (double)f[d] - (double)g[d];
-      acc += v * v;
+    if (n == kDummyNode) {
+      su += wd;
+    } else {
+      const float* f = m.desc + (long long)i * dim;
+      const float* g = s.desc + (long long)n * dim;
+      double acc = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        const double v = (double)f[d] - (double)g[d];
+        acc += v * v;
+      }
+      su += sqrt(acc);
     }
-    su += sqrt(acc);
-    if (i >= 1 && !admissible(s.t[z[i - 1]], s.t[n], T)) bad = 1;
-    if (i >= 2) {
-      const int nj = z[i - 1], nk = z[i - 2];
+    const int nj = i >= 1 ? z[i - 1] : kDummyNode;
+    const int nk = i >= 2 ? z[i - 2] : kDummyNode;
+    if (n != kDummyNode && nj != kDummyNode && !admissible(s.t[nj], s.t[n], T)) bad = 1;
+    if (i >= 2 && (n == kDummyNode || nj == kDummyNode || nk == kDummyNode)) {
+      // the Delta terms whose points are both matched; no D^g
+      if (n != kDummyNode && nj != kDummyNode) {
+        const long d1 = (long)(m.t[i] - m.t[i - 1]) - (long)(s.t[n] - s.t[nj]);
+        sd += (double)(d1 < 0 ? -d1 : d1);
+      }
+      if (nj != kDummyNode && nk != kDummyNode) {
+        const long d2 = (long)(m.t[i - 1] - m.t[i - 2]) - (long)(s.t[nj] - s.t[nk]);
+        sd += (double)(d2 < 0 ? -d2 : d2);
+      }
+    } else if (i >= 2) {
       const long dt1 = (long)(m.t[i] - m.t[i - 1]) - (long)(s.t[n] - s.t[nj]);
       const long dt2 = (long)(m.t[i - 1] - m.t[i - 2]) - (long)(s.t[nj] - s.t[nk]);
       const float2 pi = m.xy[i], pj = m.xy[i - 1], pk = m.xy[i - 2];
@@ -754,22 +896,22 @@ __device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, 
 }
 
 __global__ __launch_bounds__(64) void k_rescore(ModelView m, SceneView s, int32_t T, double l1, double l2,
-                                               double l3, const int32_t* __restrict__ assign,
+                                               double l3, double wd, const int32_t* __restrict__ assign,
                                                double* __restrict__ e64, double* __restrict__ eu64) {
   const int tl = blockIdx.x;
-  rescore_wave(m, s, T, l1, l2, l3, assign + (long long)tl * m.M, tl, e64, eu64);
+  rescore_wave(m, s, T, l1, l2, l3, wd, assign + (long long)tl * m.M, tl, e64, eu64);
 }
 
 __global__ __launch_bounds__(64) void k_rescore_batch(const PairDev* __restrict__ pairs,
                                                      const int2* __restrict__ items, int n_items,
-                                                     int32_t T, double l1, double l2, double l3,
+                                                     int32_t T, double l1, double l2, double l3, double wd,
                                                      const int32_t* __restrict__ assign,
                                                      double* __restrict__ e64, double* __restrict__ eu64) {
   const int item = blockIdx.x;
   if (item >= n_items) return;
   const int2 it = items[item];
   const PairDev pd = pairs[it.x];
-  rescore_wave(pd.m, pd.s, T, l1, l2, l3, assign + pd.assign0 + (long long)it.y * pd.m.M,
+  rescore_wave(pd.m, pd.s, T, l1, l2, l3, wd, assign + pd.assign0 + (long long)it.y * pd.m.M,
                pd.row0 + it.y, e64, eu64);
 }
 
@@ -780,6 +922,10 @@ __global__ __launch_bounds__(64) void k_rescore_batch(const PairDev* __restrict_
 template <bool DEGEN>
 hipError_t launch_dp_waves(const DPLaunch& a, hipStream_t st) {
   if (a.n_tau <= 0) return hipSuccess;
+  if (a.dummy) {  // dummies: one variant, 8 waves and the 64-slot layout
+    hipLaunchKernelGGL((k_dp<8, DEGEN, 64, true>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.sp.K <= 16) {
     hipLaunchKernelGGL((k_dp<1, DEGEN, 16>), dim3(a.n_tau), dim3(64), 0, st, a);
     return hipGetLastError();
@@ -809,6 +955,10 @@ hipError_t launch_dp_degenerate(const DPLaunch& a, hipStream_t st) { return laun
 
 template <bool DEGEN>
 hipError_t launch_persistent_variant(const BatchLaunch& b, int n_wg, hipStream_t st) {
+  if (b.dummy) {  // dummies: 8 waves whatever the tuning says
+    hipLaunchKernelGGL((k_dp_persistent<8, DEGEN, kMaxList, true>), dim3(n_wg), dim3(8 * 64), 0, st, b);
+    return hipGetLastError();
+  }
   switch (b.waves) {
     case 4:
       hipLaunchKernelGGL((k_dp_persistent<4, DEGEN>), dim3(n_wg), dim3(4 * 64), 0, st, b);
@@ -850,11 +1000,11 @@ hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st) {
 }
 
 hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, int32_t T,
-                                double lambda1, double lambda2, double lambda3, const int32_t* assign,
-                                double* e64, double* eu64, hipStream_t st) {
+                                double lambda1, double lambda2, double lambda3, double w_dummy,
+                                const int32_t* assign, double* e64, double* eu64, hipStream_t st) {
   if (n_items <= 0 || (!e64 && !eu64)) return hipSuccess;
   hipLaunchKernelGGL(k_rescore_batch, dim3(n_items), dim3(64), 0, st, pairs, items, n_items, T,
-                     lambda1, lambda2, lambda3, assign, e64, eu64);
+                     lambda1, lambda2, lambda3, w_dummy, assign, e64, eu64);
   return hipGetLastError();
 }
 
@@ -865,11 +1015,11 @@ hipError_t launch_backtrack(const DPLaunch& a, int32_t* assign, hipStream_t st) 
 }
 
 hipError_t launch_rescore(const ModelView& m, const SceneView& s, int32_t T, double lambda1,
-                          double lambda2, double lambda3, const int32_t* assign, int32_t n_tau,
-                          double* e64, double* eu64, hipStream_t st) {
+                          double lambda2, double lambda3, double w_dummy, const int32_t* assign,
+                          int32_t n_tau, double* e64, double* eu64, hipStream_t st) {
   if (n_tau <= 0 || (!e64 && !eu64)) return hipSuccess;
   hipLaunchKernelGGL(k_rescore, dim3(n_tau), dim3(64), 0, st, m, s, T, lambda1, lambda2, lambda3,
-                     assign, e64, eu64);
+                     w_dummy, assign, e64, eu64);
   return hipGetLastError();
 }
 

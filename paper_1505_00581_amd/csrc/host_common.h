@@ -103,4 +103,14 @@ int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_pa
 int unary_table(stm_ctx* ctx, const Prepared& pr, float* U);
 int check_range(const Prepared& pr, int32_t tau_begin, int32_t tau_end);
 
+// Dummy assignments (STM_DUMMY): W^d for the FP64 re-score (0 when off), and
+// the value-table side K (+1 for the dummy state).
+inline bool dummy_on(const stm_params* p) { return (p->flags & STM_DUMMY) != 0; }
+inline double w_dummy_of(const stm_params* p) { return dummy_on(p) ? p->w_dummy : 0.0; }
+inline long long vt_side(const stm_params* p) { return (long long)p->k_max + (dummy_on(p) ? 1 : 0); }
+// lambda1 * W^d in FP32, the dummy's unary term in the recursion.
+inline float dummy_cost32(const stm_params* p) {
+  return dummy_on(p) ? static_cast<float>(p->lambda1 * p->w_dummy) : 0.f;
+}
+
 }  // namespace stmh

@@ -137,6 +137,8 @@ stm::BatchLaunch plan_launch(stm_plan* p, const stm::PairDev* pairs, const int2*
   b.w = static_cast<float>(p->params.lambda2 * p->params.lambda3);
   b.vt = p->vt;
   b.vt_stride = p->vt_stride;
+  b.dummy = dummy_on(&p->params) ? 1 : 0;
+  b.cw = dummy_cost32(&p->params);
   b.e32 = e32;
   b.assign = assign;
   b.waves = p->waves;
@@ -178,8 +180,8 @@ int plan_enqueue_run(stm_plan* p, float* e32, double* e64, double* eu, int32_t* 
   STM_HIP(stm::launch_dp_persistent(b, p->n_cu * p->wgs_per_cu, st));
   if (timed) STM_HIP(hipEventRecord(p->ev_k1, st));
   STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, p->params.T,
-                                    p->params.lambda1, p->params.lambda2, p->params.lambda3, assign,
-                                    e64, eu, st));
+                                    p->params.lambda1, p->params.lambda2, p->params.lambda3,
+                                    w_dummy_of(&p->params), assign, e64, eu, st));
   return STM_OK;
 }
 
@@ -386,7 +388,7 @@ int stm_plan_create(stm_ctx* ctx, const stm_points* models, int32_t n_models, co
       for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[order[k]];
       STM_HIP(hipMemcpyAsync(p->items_dev, sorted.data(), sorted.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     }
-    p->vt_stride = (long long)std::max(1, p->m_max - 2) * params->k_max * params->k_max;
+    p->vt_stride = (long long)std::max(1, p->m_max - 2) * vt_side(params) * vt_side(params);
     if ((rc2 = plan_scratch(p))) return rc2;
     if (!p->device) {
       const int64_t nr = p->row_off.back(), na = p->asg_off.back();
@@ -627,7 +629,8 @@ int plan_enqueue_pruned(stm_plan* p, stm_pruner* P, int kp, float* e32, double* 
   x.list_count = inf_count;
   STM_HIP(stm::launch_dp_persistent(x, p->n_cu * p->wgs_per_cu, st));
   STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, p->params.T, p->params.lambda1,
-                                    p->params.lambda2, p->params.lambda3, asg, e64, eu, st));
+                                    p->params.lambda2, p->params.lambda3, w_dummy_of(&p->params), asg, e64,
+                                    eu, st));
   return STM_OK;
 }
 
@@ -643,6 +646,7 @@ int stm_plan_run_pruned(stm_plan* p, stm_pruner* P, int32_t topk, float* energy3
   if (P->dim != p->dim) return fail(STM_EINVAL, "descriptor dimension differs from the pruner's");
   if (topk < 1 || topk > 64) return fail(STM_EINVAL, "topk must be in [1, 64]");
   if (p->bf16) return fail(STM_EUNSUPPORTED, "pruned runs of plans with the BF16 unary table are not built");
+  if (dummy_on(&p->params)) return fail(STM_EUNSUPPORTED, "pruned runs of plans with dummy assignments are not built");
   if (p->row_off.back() > 0 && (!energy32 || !assign)) return fail(STM_EINVAL, "energy32 and assign are required");
   STM_HIP(hipSetDevice(p->ctx->device));
   const int kp = std::min<int>(topk, p->params.k_max);

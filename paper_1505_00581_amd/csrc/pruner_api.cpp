@@ -263,6 +263,8 @@ stm::DPLaunch dp_base(stm_ctx* ctx, const Prepared& pr, const stm_params* params
   a.lambda1 = static_cast<float>(params->lambda1);
   a.lambda2 = static_cast<float>(params->lambda2);
   a.w = static_cast<float>(params->lambda2 * params->lambda3);
+  a.dummy = dummy_on(params) ? 1 : 0;
+  a.cw = dummy_cost32(params);
   a.waves = ctx->dp_waves;
   a.vt = static_cast<float*>(ctx->vt.p);
   a.last2 = static_cast<int2*>(ctx->last2.p);
@@ -270,14 +272,17 @@ stm::DPLaunch dp_base(stm_ctx* ctx, const Prepared& pr, const stm_params* params
   return a;
 }
 
-// Largest number of offsets whose value tables (K x K per step) fit the scratch budget.
-int dp_chunk(stm_ctx* ctx, const Prepared& pr, int n, int K, size_t cap_rows) {
-  const size_t per_tau = (size_t)std::max(pr.m.M - 2, 1) * K * K * sizeof(float);
+// Largest number of offsets whose value tables (K x K per step, (K + 1)^2 with
+// dummies) fit the scratch budget.
+int dp_chunk(stm_ctx* ctx, const Prepared& pr, const stm_params* params, int n, int K, size_t cap_rows) {
+  const size_t side = (size_t)K + (dummy_on(params) ? 1 : 0);
+  const size_t per_tau = (size_t)std::max(pr.m.M - 2, 1) * side * side * sizeof(float);
   return static_cast<int>(std::min<size_t>({(size_t)n, cap_rows, std::max<size_t>(1, ctx->vt_chunk_bytes / per_tau)}));
 }
 
-int dp_scratch(stm_ctx* ctx, const Prepared& pr, int chunk, int K) {
-  const size_t per_tau = (size_t)std::max(pr.m.M - 2, 1) * K * K * sizeof(float);
+int dp_scratch(stm_ctx* ctx, const Prepared& pr, const stm_params* params, int chunk, int K) {
+  const size_t side = (size_t)K + (dummy_on(params) ? 1 : 0);
+  const size_t per_tau = (size_t)std::max(pr.m.M - 2, 1) * side * side * sizeof(float);
   int rc;
   if ((rc = grow(ctx, ctx->vt, per_tau * chunk, pr.st))) return rc;
   if ((rc = grow(ctx, ctx->last2, (size_t)chunk * sizeof(int2), pr.st))) return rc;
@@ -292,7 +297,8 @@ int dp_rows(const Prepared& pr, const stm_params* params, stm::DPLaunch b, float
   STM_HIP(stm::launch_dp_fast(b, pr.st));
   STM_HIP(stm::launch_dp_degenerate(b, pr.st));
   STM_HIP(stm::launch_backtrack(b, as, pr.st));
-  STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp.T, params->lambda1, params->lambda2, params->lambda3, as, b.n_tau,
+  STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp.T, params->lambda1, params->lambda2, params->lambda3,
+                              w_dummy_of(params), as, b.n_tau,
                               e64, eu, pr.st));
   return STM_OK;
 }
@@ -309,9 +315,9 @@ int exact_fallback(stm_ctx* ctx, const FallbackBufs& fb, const Prepared& pr, con
     if (!(e[j] < std::numeric_limits<float>::infinity())) redo.push_back(tau_begin + j);
   if (redo.empty()) return STM_OK;
   const int nr = static_cast<int>(redo.size()), M = pr.m.M;
-  const int chunk = dp_chunk(ctx, pr, nr, pr.sp.K, (size_t)nr);
+  const int chunk = dp_chunk(ctx, pr, params, nr, pr.sp.K, (size_t)nr);
   int rc;
-  if ((rc = dp_scratch(ctx, pr, chunk, pr.sp.K))) return rc;
+  if ((rc = dp_scratch(ctx, pr, params, chunk, pr.sp.K))) return rc;
   if ((rc = grow(ctx, *fb.taus, (size_t)nr * sizeof(int32_t), pr.st))) return rc;
   if ((rc = grow(ctx, *fb.f32, (size_t)chunk * sizeof(float), pr.st))) return rc;
   if ((rc = grow(ctx, *fb.f64, (size_t)chunk * sizeof(double), pr.st))) return rc;
@@ -548,6 +554,7 @@ int stm_match_pruned(stm_ctx* ctx, stm_pruner* P, const stm_points* model, const
   if (rc) return rc;
   if (P->ctx != ctx) return fail(STM_EINVAL, "the pruner belongs to another context");
   if (topk < 1 || topk > kSlots) return fail(STM_EINVAL, "topk must be in [1, 64]");
+  if (params && dummy_on(params)) return fail(STM_EUNSUPPORTED, "pruned matching with dummy assignments is not built");
   Prepared pr;
   if ((rc = pair_inputs(P, model, scene, params, hip_stream, pr))) return rc;
   if ((rc = check_range(pr, tau_begin, tau_end))) return rc;
@@ -564,8 +571,8 @@ int stm_match_pruned(stm_ctx* ctx, stm_pruner* P, const stm_points* model, const
 
   // pruned lists and the recursion on them, in chunks of offsets
   const int kp = std::min(topk, pr.sp.K);
-  const int chunk = dp_chunk(ctx, pr, n_tau, kp, (size_t)std::max(1, (1 << 20) / M));
-  if ((rc = dp_scratch(ctx, pr, chunk, kp))) return rc;
+  const int chunk = dp_chunk(ctx, pr, params, n_tau, kp, (size_t)std::max(1, (1 << 20) / M));
+  if ((rc = dp_scratch(ctx, pr, params, chunk, kp))) return rc;
   if ((rc = grow(ctx, P->cand, (size_t)chunk * M * kp * sizeof(int32_t), pr.st))) return rc;
   if ((rc = grow(ctx, P->count, (size_t)chunk * M * sizeof(int32_t), pr.st))) return rc;
   if ((rc = grow(ctx, P->node, (size_t)chunk * M * kSlots * sizeof(int32_t), pr.st))) return rc;
@@ -643,8 +650,8 @@ int stm_match_lists(stm_ctx* ctx, const stm_points* model, const stm_points* sce
   STM_HIP(stm::launch_model_angles(pr.m, static_cast<float2*>(ctx->theta.p), pr.st));
   if ((rc = grow(ctx, ctx->U, (size_t)M * S * sizeof(float), pr.st))) return rc;
   if ((rc = unary_table(ctx, pr, static_cast<float*>(ctx->U.p)))) return rc;
-  const int chunk = dp_chunk(ctx, pr, n_tau, kc, (size_t)n_tau);
-  if ((rc = dp_scratch(ctx, pr, chunk, kc))) return rc;
+  const int chunk = dp_chunk(ctx, pr, params, n_tau, kc, (size_t)n_tau);
+  if ((rc = dp_scratch(ctx, pr, params, chunk, kc))) return rc;
   stm::DPLaunch b = dp_base(ctx, pr, params);
   b.sp.K = kc;
   b.cstride = kc;

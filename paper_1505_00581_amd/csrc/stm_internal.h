@@ -143,7 +143,7 @@ struct DPLaunch {
   const float2* theta;  // [M] model angles (mid, end) of the triangle ending at i
   float lambda1, lambda2, w;  // w = lambda2 * lambda3
   int32_t tau0, n_tau;
-  float* vt;            // [n_tau][M-2][K][K] cell values V_i, i = 1..M-2
+  float* vt;            // [n_tau][M-2][V][V] cell values V_i, i = 1..M-2; V = K (+1 with dummies)
   float* e32;           // [n_tau]
   int2* last2;          // [n_tau]
   int32_t* degen;       // [n_tau], written by the fast variant
@@ -155,6 +155,9 @@ struct DPLaunch {
   int32_t cstride = 0;
   // explicit offsets (null: tau0 + tl): matching tl of the launch is offset taus[tl]
   const int32_t* taus = nullptr;
+  // dummy assignments (Eq. 2): enabled flag and lambda1 * W^d in FP32
+  int32_t dummy = 0;
+  float cw = 0.f;
 };
 // The fast variant over every matching of the launch, then the variant for
 // degenerate triangles, which only recomputes the matchings flagged by the first.
@@ -163,9 +166,11 @@ hipError_t launch_dp_degenerate(const DPLaunch& a, hipStream_t st);
 
 hipError_t launch_backtrack(const DPLaunch& a, int32_t* assign, hipStream_t st);
 
+// FP64 energy of each assignment row; w_dummy is W^d, the unary cost of a
+// dummy (node id -2 in assign; never present when dummies are off).
 hipError_t launch_rescore(const ModelView& m, const SceneView& s, int32_t T, double lambda1,
-                          double lambda2, double lambda3, const int32_t* assign, int32_t n_tau,
-                          double* e64, double* eu64, hipStream_t st);
+                          double lambda2, double lambda3, double w_dummy, const int32_t* assign,
+                          int32_t n_tau, double* e64, double* eu64, hipStream_t st);
 
 // ---- batched persistent launch ---------------------------------------------------
 
@@ -201,6 +206,8 @@ struct BatchLaunch {
   float lambda1, lambda2, w;
   float* vt;            // value-table scratch, vt_stride floats per workgroup
   long long vt_stride;
+  int32_t dummy = 0;    // dummy assignments (Eq. 2) enabled
+  float cw = 0.f;       // lambda1 * W^d in FP32
   float* e32;           // [rows]
   int32_t* assign;      // [sum over pairs of n_tau * M]
   int32_t waves;        // 4, 8 or 16 waves per workgroup
@@ -218,8 +225,8 @@ hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st);
 hipError_t launch_collect_infeasible(const PairDev* pairs, const int2* items, int n_items, const float* e32,
                                      int32_t* list, int32_t* count, int32_t* fell, hipStream_t st);
 hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, int32_t T,
-                                double lambda1, double lambda2, double lambda3, const int32_t* assign,
-                                double* e64, double* eu64, hipStream_t st);
+                                double lambda1, double lambda2, double lambda3, double w_dummy,
+                                const int32_t* assign, double* e64, double* eu64, hipStream_t st);
 
 // ---- learned candidate pruner -------------------------------------------------------
 

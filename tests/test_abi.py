@@ -69,6 +69,8 @@ def test_null_context_is_einval_after_argument_checks():
     (lambda m, s, p: s.t.__setitem__(s.t.shape[0] - 1, s.n_frames), "outside"),
     (lambda m, s, p: m.desc.__setitem__((0, 0), np.nan), "non-finite model"),
     (lambda m, s, p: s.xy.__setitem__((7, 1), np.inf), "non-finite scene"),
+    (lambda m, s, p: setattr(p, "w_dummy", -0.5), "w_dummy"),
+    (lambda m, s, p: setattr(p, "w_dummy", float("inf")), "w_dummy"),
 ])
 def test_invalid_inputs_rejected_on_host(mutate, needle):
     m, s, p = _good()
@@ -162,3 +164,21 @@ def test_plan_run_pruned_rejects_null_arguments():
     lib = stm.load()
     assert lib.stm_plan_run_pruned(None, None, 16, None, None, None, None, None, None) == stm.STM_EINVAL
     assert "null" in lib.stm_last_error().decode()
+
+
+def test_params_struct_and_dummy_constants_match_the_header():
+    src = open(os.path.join(ROOT, "include", "stm.h")).read()
+    body = dict((n, b) for b, n in re.findall(r"typedef struct \{(.*?)\} (\w+);", src, flags=re.S))["stm_params"]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(\w+)\s*;", body)
+    assert fields == [f[0] for f in B._Params._fields_]
+    assert ctypes.sizeof(B._Params) == 48
+    assert int(re.search(r"#define STM_DUMMY\s+(0x[0-9a-f]+)u", src).group(1), 16) == B.STM_DUMMY
+    assert int(re.search(r"#define STM_DUMMY_NODE \((-?\d+)\)", src).group(1)) == B.STM_DUMMY_NODE
+
+
+def test_dummy_params_pass_the_argument_checks():
+    m, s, p = _good()
+    p.w_dummy = 0.4
+    rc, msg = _call_match(m, s, p)
+    assert rc == stm.STM_EINVAL and "context" in msg

@@ -1,0 +1,180 @@
+"""Dummy assignments (Eq. 2, STM_DUMMY) on MI355X against the FP64 oracle.
+
+The oracle restates the reading independently: U(epsilon) = W^d, a Delta term
+needs both of its points matched, D^g all three, constraints bind matched
+consecutive points.  Same tolerances as the exact path: energies 1e-5
+relative with a 1e-4 absolute floor; assignments identical, or the oracle's
+FP64 energy of the GPU assignment equal to the optimum within that
+tolerance; the GPU's FP64 re-score equal to the oracle's literal energy of
+the same assignment to 1e-9.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1505_00581_amd as stm
+from paper_1505_00581_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-5, 1e-4
+EPS = -2
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = stm.Context(0)
+    yield c
+    c.close()
+
+
+def _np(x):
+    return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+
+
+def check(m, s, p, res, ora, rows=None):
+    e32 = _np(res["energy32"]).astype(np.float64)
+    e64, eu64, A = _np(res["energy64"]), _np(res["energy_u64"]), _np(res["assign"])
+    if rows is not None:
+        e32, e64, eu64, A = e32[rows], e64[rows], eu64[rows], A[rows]
+    E, Z = ora["energy"], ora["assign"]
+    assert np.isfinite(E).all() and np.isfinite(e32).all()  # the all-dummy assignment is allowed
+    tol = np.maximum(RTOL * np.abs(E), ATOL)
+    err = np.abs(e32 - E)
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, f"energy mismatch at {bad[:5]}: gpu {e32[bad[:5]]} oracle {E[bad[:5]]}"
+    same = (A == Z).all(1)
+    eg, eu = oracle.energies(m, s, p, A)
+    if not same.all():
+        d = np.abs(eg[~same] - E[~same])
+        assert (d <= tol[~same]).all(), f"different assignment with energy gap {d.max()}"
+    assert np.allclose(e64, eg, rtol=1e-9, atol=1e-9), np.abs(e64 - eg).max()
+    assert np.allclose(eu64, eu, rtol=1e-9, atol=1e-9)
+    return dict(n=len(E), agree=float(same.mean()), dummies=int((A == EPS).sum()),
+                max_rel=float((err / np.maximum(np.abs(E), 1e-30)).max()))
+
+
+def test_tiny_random_against_oracle(ctx):
+    n = d = 0
+    for seed in range(60):
+        w = synth.tiny(seed, k_max=[3, 5][seed % 2], T=[4, 2, 0][seed % 3])
+        w.params.w_dummy = [0.05, 0.2, 0.5, 2.0][seed % 4]
+        m, s, p = w.models[0], w.scenes[0], w.params
+        if len(oracle.offsets(m, s)) == 0:
+            continue
+        st = check(m, s, p, ctx.match(m, s, p), oracle.match(m, s, p))
+        n += st["n"]
+        d += st["dummies"]
+    say(f"  {n} tiny matchings, {d} dummy assignments")
+    assert n > 150 and d > 50
+
+
+@pytest.mark.parametrize("seed,wd", [(0, 0.12), (1, 0.2), (2, 0.35)])
+def test_config1_all_offsets(ctx, seed, wd):
+    w = synth.config1(seed)
+    m, s, p = w.models[0], w.scenes[0], dataclasses.replace(w.params, w_dummy=wd)
+    say(f"[config1 dummy seed={seed} W^d={wd}] M={m.n} S={s.n}")
+    st = check(m, s, p, ctx.match(m, s, p), oracle.match(m, s, p))
+    say(f"  {st}")
+    assert st["dummies"] > 0
+
+
+def test_realistic_scene_sampled_offsets(ctx):
+    """A model of the realistic workload (K = 64, the 64-slot layout and all
+    its chunking) against its 1500-frame scene; rows sampled for the oracle."""
+    w = synth.config2(0)
+    m, s = w.models[0], w.scenes[0]
+    p = dataclasses.replace(w.params, w_dummy=0.16)
+    res = ctx.match(m, s, p)
+    n = int(_np(res["energy32"]).shape[0])
+    rows = np.sort(np.random.default_rng(3).choice(n, 40, replace=False))
+    say(f"[realistic dummy] M={m.n} S={s.n} offsets={n} sampled={len(rows)}")
+    st = check(m, s, p, res, oracle.match(m, s, p, taus=rows.astype(np.int32)), rows=rows)
+    say(f"  {st}")
+    assert st["dummies"] > 0
+    # dummies only lower the optimum: never above the matching without them
+    ex = _np(ctx.match(m, s, w.params)["energy32"])
+    assert (_np(res["energy32"]) <= ex).all()
+
+
+def test_zero_cost_gives_zero_energy(ctx):
+    w = synth.config1(4)
+    m, s, p = w.models[0], w.scenes[0], dataclasses.replace(w.params, w_dummy=0.0)
+    r = ctx.match(m, s, p)
+    assert (_np(r["energy32"]) == 0).all() and (_np(r["energy64"]) == 0).all()
+
+
+def test_empty_windows_become_feasible(ctx):
+    """Frames without scene points make offsets infeasible without dummies;
+    with them every offset is solved and agrees with the oracle."""
+    w = synth.tiny(77, m=6, max_per_frame=1, n_frames=40, k_max=4, T=3)
+    m, s = w.models[0], w.scenes[0]
+    ex = ctx.match(m, s, w.params)
+    assert (~np.isfinite(_np(ex["energy32"]))).any()
+    p = dataclasses.replace(w.params, w_dummy=0.3)
+    check(m, s, p, ctx.match(m, s, p), oracle.match(m, s, p))
+
+
+def test_given_lists_against_oracle(ctx):
+    rng = np.random.default_rng(5)
+    for seed in range(12):
+        w = synth.tiny(300 + seed, k_max=5)
+        m, s = w.models[0], w.scenes[0]
+        p = dataclasses.replace(w.params, w_dummy=[0.1, 0.4][seed % 2])
+        n = len(oracle.offsets(m, s))
+        if n == 0:
+            continue
+        lists = np.full((n, m.n, p.k_max), -1, np.int32)
+        counts = np.zeros((n, m.n), np.int32)
+        for t in range(n):
+            for i in range(m.n):
+                c = [int(x) for x in oracle.candidate_list(m, s, p, t, i) if rng.random() < 0.7]
+                lists[t, i, :len(c)] = c
+                counts[t, i] = len(c)
+        got = ctx.match_lists(m, s, p, lists, counts)
+        check(m, s, p, got, oracle.match_lists(m, s, p, lists, counts))
+
+
+def test_plan_equals_per_model_matching(ctx):
+    w = synth.config3(2, n_models=6, n_scenes=2)
+    scenes = []
+    for s in w.scenes:
+        keep = s.t < 240
+        scenes.append(synth.Points(np.ascontiguousarray(s.xy[keep]), np.ascontiguousarray(s.t[keep]),
+                                   np.ascontiguousarray(s.desc[keep]), 240))
+    models = [m for m in w.models if int(m.t[-1]) < 180]
+    p = dataclasses.replace(w.params, w_dummy=0.2)
+    pairs = np.array([(i, j) for i in range(len(models)) for j in range(len(scenes))], np.int32)
+    plan = stm.Plan(ctx, models, scenes, pairs, p)
+    plan.set_tuning(4, 3)  # dummies run one variant whatever the shape asks
+    out = plan.run()
+    n = d = 0
+    for q, (i, j) in enumerate(pairs):
+        e32, e64, eu, A = [_np(x) for x in plan.pair_rows(out, q)]
+        ref = ctx.match(models[i], scenes[j], p)
+        np.testing.assert_array_equal(e32, ref["energy32"])
+        np.testing.assert_array_equal(A, ref["assign"])
+        np.testing.assert_array_equal(e64, ref["energy64"])
+        n += e32.size
+        d += int((A == EPS).sum())
+    out2 = plan.run()
+    np.testing.assert_array_equal(_np(out2["energy32"]), _np(out["energy32"]))
+    say(f"  {len(pairs)} pairs, {n} matchings, {d} dummies: plan identical to per-model launches")
+    plan.close()
+    assert n > 0 and d > 0
+
+
+def test_pruned_matching_rejects_dummies(ctx):
+    w = synth.config1(0)
+    m, s = w.models[0], w.scenes[0]
+    pr = stm.Pruner(ctx, m.dim)
+    pr.set_params(synth.pruner_init(m.dim, 0))
+    with pytest.raises(stm.StmError, match="dummy"):
+        pr.match(m, s, dataclasses.replace(w.params, w_dummy=0.2), topk=8)
