@@ -64,6 +64,7 @@ class Workload:
     params: Params
     planted: list  # (model index, scene index, tau) of every planted copy
     name: str = ""
+    saliency: list = dataclasses.field(default_factory=list)  # per model: detector confidence per point
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -245,6 +246,32 @@ def paper_blocks(seed: int = 0, n_models: int = 50, block: int = 60) -> Workload
         planted.append((mi, 0, tau))
     scene = assemble_scene(*parts, n_frames)
     return Workload(models, [scene], p, planted, f"paper_blocks_m30_s{n_points}_b{block}")
+
+
+def multipoint(seed: int = 0, n_models: int = 2, frames: tuple = (50, 100), per_frame: int = 3,
+               n_frames: int = 1500, clutter_per_frame: int = 20, window: int = 3, k_max: int = 64,
+               width: float = 320.0, height: float = 240.0, planted_per_model: int = 5) -> Workload:
+    """Models with 1..per_frame interest points in each model frame (the
+    multiple-points models of Table 4) against one scene with planted copies.
+    Model frames: distinct, drawn from {0..1.5 F_m} with gaps < T; each point
+    gets a detector confidence U(0, 1) (Workload.saliency).  Points are stored
+    by frame, then by draw order."""
+    rng = _rng(seed)
+    p = Params(window=window, k_max=k_max)
+    models, sal = [], []
+    for _ in range(n_models):
+        nf = int(rng.integers(frames[0], frames[1] + 1))
+        ft = model_frames(rng, nf, int(math.ceil(1.5 * nf)), p.T)
+        per = rng.integers(1, per_frame + 1, size=nf)
+        t = np.repeat(ft, per).astype(np.int32)
+        m = int(t.shape[0])
+        xy = np.stack([rng.uniform(0, width, m), rng.uniform(0, height, m)], 1).astype(np.float32)
+        models.append(Points(xy, t, dirichlet_desc(rng, m)))
+        sal.append(rng.uniform(0.0, 1.0, m).astype(np.float32))
+    scene, planted = make_scene(rng, models, n_frames, np.full(n_frames, clutter_per_frame), width, height,
+                                planted_per_model)
+    return Workload(models, [scene], p, planted, f"multipoint_{n_models}models_{per_frame}perframe",
+                    saliency=sal)
 
 
 def block_lists(model: Points, scene: Points, n_blocks: int, block: int = 60):
