@@ -405,6 +405,42 @@ def bench_dummy(ctx, dms, ds, p, wd: float, steps: int, warmup: int, exact_ms: f
     return res
 
 
+def bench_chains(ctx, seed: int, steps: int, warmup: int, n_chains: int = 3):
+    """The multiple-points variant 2 (Table 4): two models with 1..3 points
+    per frame (204 and 151 points) against a 1500-frame scene of 20 clutter
+    points per frame, each split into single-point chains matched at every
+    offset, the distance averaged over the chains."""
+    import torch
+
+    import paper_1505_00581_amd as stm
+    from paper_1505_00581_amd import synth
+    w = synth.multipoint(seed, n_models=2)
+    ds = stm.DevicePoints.from_host(w.scenes[0])
+    dms = [stm.DevicePoints.from_host(m) for m in w.models]
+    sal = [torch.as_tensor(x, device="cuda") for x in w.saliency]
+
+    def step():
+        return [ctx.match_chains(dm, ds, w.params, sv, n_chains) for dm, sv in zip(dms, sal)]
+
+    for _ in range(warmup + 1):
+        outs = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs = step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    offsets = sum(int(o["energy32"].shape[0]) for o in outs)
+    chains = [int(o["chains_used"]) for o in outs]
+    res = dict(models=[int(m.n) for m in w.models], chains=chains, offsets=offsets, ms_per_step=round(ms, 3),
+               value=round(offsets / ms * 1e3, 2), unit="model offsets/s",
+               chain_matchings_per_s=round(sum(c * int(o["energy32"].shape[0]) for c, o in zip(chains, outs))
+                                           / ms * 1e3, 2),
+               feasible=round(float(np.mean([np.isfinite(o["energy32"].cpu().numpy()).mean() for o in outs])), 4))
+    log(f"multiple points, independent chains: {res}")
+    return res
+
+
 def bench_t_sweep(ctx, w, dms, ds, steps: int, values):
     """Run time of the exact step against the closeness limit T (the run-time
     half of the paper's Fig. 7; T <= 0 means no limit), on the same workload."""
@@ -445,6 +481,7 @@ def main():
     ap.add_argument("--batched-runs", type=int, default=3)
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "stm_tuning_cache.json"))
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruner section")
+    ap.add_argument("--no-chains", action="store_true", help="skip the multiple-points (chains) section")
     ap.add_argument("--dummy-cost", default="0.16,0.5,1.0",
                     help="comma-separated W^d values of the dummy-assignment section (Eq. 2); empty: skip it")
     ap.add_argument("--t-sweep", default="", help="comma-separated closeness limits T to time "
@@ -586,6 +623,8 @@ def main():
                  unary="BF16 MFMA dot products (D padded 162->192), FP32 norms and accumulation")
     log(f"split precision: {ms_bf:.2f} ms/step")
 
+    chains = None if args.no_chains else bench_chains(ctx, args.seed, args.steps, args.warmup)
+
     dummy = None
     if args.dummy_cost:
         dummy = [bench_dummy(ctx, dms, ds, p, float(x), args.steps, args.warmup, ms_per_step, outs)
@@ -649,6 +688,7 @@ def main():
         "cpu_baseline": cpu,
         "split_precision": split,
         "dummy_assignments": dummy,
+        "multipoint_chains": chains,
         "parity_on_cpu_sample": parity,
     }
     if pruned is not None:

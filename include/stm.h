@@ -179,6 +179,37 @@ STM_API int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* s
               float* energy32, double* energy64, double* energy_u64, int32_t* assign,
               void* hip_stream);
 
+/* ---- several points per model frame ------------------------------------------
+ *
+ * The multiple-points model, variant 2 of Section 4 (Table 4): the model is
+ * split into single-point models (second-order chains), each matched
+ * independently by stm_match, and the matching distance is the mean of the
+ * chains' energies.  The paper leaves the split to another publication; here
+ * chain c (c < n_chains) holds the c-th most salient point of every model
+ * frame with more than c points (saliency: the detector's confidence, higher
+ * first, equal values in point order; NULL: point order), and chains of fewer
+ * than 3 points are dropped.
+ *
+ * model: frames non-decreasing (several points may share a frame), n >= 3;
+ * saliency [n] in the same memory as the other pointers (nullable).  Offsets
+ * are those of the whole model (stm_offsets): tau puts its first frame at
+ * scene frame tau, and chain c is matched at tau + (first frame of c - first
+ * frame of the model).  Outputs as stm_match, per offset:
+ *   energy32, energy64, energy_u64  the mean over the kept chains (+inf if one
+ *                                   of them is infeasible);
+ *   assign [n_tau][n]               each point's node in its chain's optimum,
+ *                                   STM_UNCHAINED_NODE for points of no kept
+ *                                   chain (-1 for the points of an infeasible
+ *                                   chain);
+ *   chains_used                     the number of kept chains (nullable).
+ * Errors as stm_match, plus STM_EINVAL for decreasing model frames, a
+ * non-finite saliency, n_chains outside 1..64, or no chain of 3 points. */
+#define STM_UNCHAINED_NODE (-3)
+STM_API int stm_match_chains(stm_ctx* ctx, const stm_points* model, const float* saliency, int32_t n_chains,
+                             const stm_points* scene, const stm_params* params, int32_t tau_begin,
+                             int32_t tau_end, float* energy32, double* energy64, double* energy_u64,
+                             int32_t* assign, int32_t* chains_used, void* hip_stream);
+
 /* ---- many matchings in one launch ------------------------------------------
  *
  * A plan matches every offset of every (model, scene) pair of a batch.  At

@@ -24,6 +24,7 @@ STM_UNARY_BF16 = 0x2
 STM_K_DENSITY = 0x4
 STM_DUMMY = 0x8
 STM_DUMMY_NODE = -2  # assignment value of a dummy (unmatched model point)
+STM_UNCHAINED_NODE = -3  # assignment value of a point in no kept chain (stm_match_chains)
 
 EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_match",
            "stm_candidates", "stm_unary", "stm_count_work", "stm_set_dp_waves",
@@ -32,7 +33,8 @@ EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_ma
            "stm_match_batch", "stm_pruner_num_params", "stm_pruner_create", "stm_pruner_destroy",
            "stm_pruner_set_params", "stm_pruner_get_params", "stm_pruner_save", "stm_pruner_load",
            "stm_pruner_features", "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
-           "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned")
+           "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned",
+           "stm_match_chains")
 
 
 class StmError(RuntimeError):
@@ -114,6 +116,7 @@ def load() -> ctypes.CDLL:
         lib.stm_match_lists.argtypes = [P, PP, PP, PS, i32, i32, P, P, i32, P, P, P, P, P]
         lib.stm_pruner_set_rule.argtypes = [P, i32]
         lib.stm_plan_run_pruned.argtypes = [P, P, i32, P, P, P, P, P, P]
+        lib.stm_match_chains.argtypes = [P, PP, P, i32, PP, PS, i32, i32, P, P, P, P, P, P]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
                      "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
@@ -121,7 +124,8 @@ def load() -> ctypes.CDLL:
                      "stm_pruner_create", "stm_pruner_set_params", "stm_pruner_get_params",
                      "stm_pruner_save", "stm_pruner_load", "stm_pruner_features",
                      "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
-                     "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned"):
+                     "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned",
+                     "stm_match_chains"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -292,6 +296,41 @@ class Context:
                                          _ptr(out["energy64"]), _ptr(out["energy_u64"]),
                                          _ptr(out["assign"]), stream))
         out["tau_begin"], out["tau_end"] = b, e
+        return out
+
+    def match_chains(self, model, scene, params, saliency=None, n_chains: int = 3, tau_begin=None,
+                     tau_end=None):
+        """The multiple-points variant 2 (stm_match_chains): the mean energy of
+        the model's single-point chains at every offset of the whole model.
+        Returns the stm_match outputs (assign [n, M] in model point order) plus
+        chains_used."""
+        b, e = self._range(model, scene, tau_begin, tau_end)
+        n, M = e - b, int(model.t.shape[0])
+        keep = []
+        pm, ps = _points(model, keep), _points(scene, keep)
+        dev = _is_device(model)
+        if dev:
+            import torch
+            d = model.xy.device
+            sal = None if saliency is None else torch.as_tensor(saliency, device=d).to(torch.float32).contiguous()
+            out = dict(energy32=torch.empty(n, dtype=torch.float32, device=d),
+                       energy64=torch.empty(n, dtype=torch.float64, device=d),
+                       energy_u64=torch.empty(n, dtype=torch.float64, device=d),
+                       assign=torch.empty((n, M), dtype=torch.int32, device=d))
+            stream = _stream()
+        else:
+            sal = None if saliency is None else np.ascontiguousarray(saliency, np.float32)
+            out = dict(energy32=np.empty(n, np.float32), energy64=np.empty(n, np.float64),
+                       energy_u64=np.empty(n, np.float64), assign=np.empty((n, M), np.int32))
+            stream = None
+        used = ctypes.c_int32(0)
+        pp = _params(params, dev)
+        _check(self._lib.stm_match_chains(self.handle, ctypes.byref(pm), None if sal is None else _ptr(sal),
+                                          int(n_chains), ctypes.byref(ps), ctypes.byref(pp), b, e,
+                                          _ptr(out["energy32"]), _ptr(out["energy64"]),
+                                          _ptr(out["energy_u64"]), _ptr(out["assign"]), ctypes.byref(used),
+                                          stream))
+        out["tau_begin"], out["tau_end"], out["chains_used"] = b, e, used.value
         return out
 
     def candidates(self, model, scene, params, tau_begin=None, tau_end=None):

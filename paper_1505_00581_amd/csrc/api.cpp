@@ -205,7 +205,9 @@ void stm_destroy(stm_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->fstart, &ctx->theta, &ctx->U,     &ctx->vt,    &ctx->last2, &ctx->degen,
                     &ctx->val,    &ctx->counts, &ctx->mxy,  &ctx->mt,    &ctx->mdesc, &ctx->sxy,
                     &ctx->st,     &ctx->sdesc,  &ctx->o_e32, &ctx->o_e64, &ctx->o_eu, &ctx->o_assign,
-                    &ctx->o_cand, &ctx->o_cnt, &ctx->fb,   &ctx->fn,    &ctx->gb,    &ctx->gn};
+                    &ctx->o_cand, &ctx->o_cnt, &ctx->fb,   &ctx->fn,    &ctx->gb,    &ctx->gn,
+                    &ctx->ch_xy,  &ctx->ch_t,  &ctx->ch_desc, &ctx->ch_idx, &ctx->ch_off, &ctx->ch_e32, &ctx->ch_e64,
+                    &ctx->ch_eu,  &ctx->ch_as};
   for (DevBuf* b : bufs) release(*b);
   for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
   delete ctx;

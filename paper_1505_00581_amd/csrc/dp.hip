@@ -739,8 +739,10 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
 // The fast variant takes every item; an item whose matching has coincident
 // points is appended to the degenerate list instead of being backtracked, and
 // the degenerate variant (a second launch) takes the items of that list.
+// Occupancy targets: the LDS of one matching allows three 8-wave workgroups
+// per CU (two with the dummy vectors).
 template <int NW, bool DEGEN, int KL = kMaxList, bool DUMMY = false>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW >= 8 ? 6 : 3)))
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(DUMMY ? 4 : (NW >= 8 ? 6 : 3))))
 void k_dp_persistent(BatchLaunch b) {
   __shared__ DPShared<NW, KL, DUMMY> sh;
   __shared__ int item_sh;

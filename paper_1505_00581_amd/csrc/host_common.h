@@ -46,6 +46,8 @@ struct stm_ctx {
   stmh::DevBuf mxy, mt, mdesc, sxy, st, sdesc;
   stmh::DevBuf o_e32, o_e64, o_eu, o_assign, o_cand, o_cnt;
   stmh::DevBuf fb, fn, gb, gn;  // BF16 descriptors and squared norms
+  // multiple-points chains: gathered chain points and per-chain results
+  stmh::DevBuf ch_xy, ch_t, ch_desc, ch_idx, ch_off, ch_e32, ch_e64, ch_eu, ch_as;
   size_t vt_chunk_bytes = size_t(4) << 30;  // value-table scratch per chunk of offsets
   // kernel timing
   bool prof = false;

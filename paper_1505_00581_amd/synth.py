@@ -253,9 +253,10 @@ def multipoint(seed: int = 0, n_models: int = 2, frames: tuple = (50, 100), per_
                width: float = 320.0, height: float = 240.0, planted_per_model: int = 5) -> Workload:
     """Models with 1..per_frame interest points in each model frame (the
     multiple-points models of Table 4) against one scene with planted copies.
-    Model frames: distinct, drawn from {0..1.5 F_m} with gaps < T; each point
-    gets a detector confidence U(0, 1) (Workload.saliency).  Points are stored
-    by frame, then by draw order."""
+    Model frames: distinct, drawn from {0..1.5 F_m} with gaps < T; points per
+    frame U{1..per_frame}, raised so that no chain level skips more than 3
+    frames; each point gets a detector confidence U(0, 1) (Workload.saliency).
+    Points are stored by frame, then by draw order."""
     rng = _rng(seed)
     p = Params(window=window, k_max=k_max)
     models, sal = [], []
@@ -263,6 +264,16 @@ def multipoint(seed: int = 0, n_models: int = 2, frames: tuple = (50, 100), per_
         nf = int(rng.integers(frames[0], frames[1] + 1))
         ft = model_frames(rng, nf, int(math.ceil(1.5 * nf)), p.T)
         per = rng.integers(1, per_frame + 1, size=nf)
+        # keep every chain level dense: a frame more than 3 frames after the
+        # last one holding a (c+1)-th point gets one
+        for c in range(1, per_frame):
+            last = None
+            for k in range(nf):
+                if per[k] > c:
+                    last = ft[k]
+                elif last is not None and ft[k] - last > 3:
+                    per[k] = c + 1
+                    last = ft[k]
         t = np.repeat(ft, per).astype(np.int32)
         m = int(t.shape[0])
         xy = np.stack([rng.uniform(0, width, m), rng.uniform(0, height, m)], 1).astype(np.float32)
