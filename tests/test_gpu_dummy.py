@@ -178,3 +178,30 @@ def test_pruned_matching_rejects_dummies(ctx):
     pr.set_params(synth.pruner_init(m.dim, 0))
     with pytest.raises(stm.StmError, match="dummy"):
         pr.match(m, s, dataclasses.replace(w.params, w_dummy=0.2), topk=8)
+
+
+def test_coincident_points_with_dummies(ctx):
+    """Integer coordinates on an 8-pixel grid make zero-length sides common, so
+    the degenerate variant (with dummies) redoes many matchings."""
+    n = 0
+    for seed in range(40):
+        w = synth.tiny(1000 + seed, int_coords=True, max_per_frame=3)
+        w.scenes[0].xy[:] = np.round(w.scenes[0].xy / 8.0) * 8.0
+        w.models[0].xy[:] = np.round(w.models[0].xy / 8.0) * 8.0
+        m, s = w.models[0], w.scenes[0]
+        p = dataclasses.replace(w.params, w_dummy=[0.1, 0.5][seed % 2])
+        if len(oracle.offsets(m, s)) == 0:
+            continue
+        n += check(m, s, p, ctx.match(m, s, p), oracle.match(m, s, p))["n"]
+    assert n > 100
+
+
+def test_all_points_coincide_with_dummies(ctx):
+    rng = np.random.Generator(np.random.PCG64(4))
+    m = synth.make_model(rng, 6, 40, 40, 10, frame_hi=8)
+    counts = rng.integers(1, 4, size=14)
+    xy, t, d = synth.clutter(rng, counts, 40, 40, m.dim)
+    xy[:] = 17.0
+    s = synth.assemble_scene([xy], [t], [d], 14)
+    p = synth.Params(window=1, k_max=8, T=6, w_dummy=0.3)
+    check(m, s, p, ctx.match(m, s, p), oracle.match(m, s, p))
