@@ -117,11 +117,27 @@ def cpu_baseline(workload, target_s: float, seed: int):
         # grow the next batch towards the time target
         per = dt / max(len(sel), 1)
         batch = int(max(threads, min(8 * batch, (target_s - elapsed) / max(per, 1e-6))))
+    # one core, on the first few matchings of the same sample
+    one = [pairs[j] for j in order[:max(1, min(6, done))]]
+    t0 = time.perf_counter()
+    for mi, t in one:
+        oracle.match(workload.models[mi], s, p, taus=np.array([t], np.int32), n_threads=1)
+    one_s = time.perf_counter() - t0
+    log(f"  cpu oracle, one core: {len(one)} matchings in {one_s:.1f}s")
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return solved, dict(value=done / elapsed if elapsed > 0 else None, unit="matchings/s", cores=threads,
                 kind="oracle",
                 sample=(f"{done} (model, offset) matchings drawn uniformly (seed {seed + 77}) from "
                         f"the same workload, FP64 C oracle (literal backward recursion), "
-                        f"OpenMP over offsets, {elapsed:.1f}s"))
+                        f"OpenMP over offsets, {elapsed:.1f}s"),
+                one_core_value=round(len(one) / one_s, 4) if one_s > 0 else None,
+                one_core_sample=f"the first {len(one)} matchings of that sample, {one_s:.1f}s",
+                cpu_model=model, nproc=os.cpu_count())
 
 
 def sample_parity(solved, outs, outs_bf):
@@ -571,7 +587,8 @@ def main():
         ach = counts["feasible_relax"] * OPS_PER_RELAX / launches_per_step / avg_s / 1e12
         return dict(bound="alu", achieved=round(ach, 3), peak=round(peak, 3), unit="TOP/s",
                     frac=round(ach / peak, 4), traffic=traffic, kernel=kernel,
-                    avg_launch_ms=round(1e3 * avg_s, 4), ops_per_relax=OPS_PER_RELAX)
+                    avg_launch_ms=round(1e3 * avg_s, 4), ops_per_relax=OPS_PER_RELAX,
+                    hbm_gb_per_s=None if traffic is None else round(traffic / avg_s / 1e9, 1))
 
     per_model = dict(ms_per_step=round(loop_ms, 3), value=round(n_match / loop_ms * 1e3, 2),
                      unit="matchings/s", launches="one stm_match call per model (10 recursion launches "
