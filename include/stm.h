@@ -64,7 +64,7 @@ extern "C" {
 #define STM_EINVAL       -1  /* invalid argument or input data (see stm_last_error) */
 #define STM_ENOMEM       -2  /* device or host allocation failed; nothing written   */
 #define STM_EHIP         -3  /* a HIP runtime call failed (message has its string)  */
-#define STM_EUNSUPPORTED -4  /* flag combination or size not supported by this build */
+#define STM_EUNSUPPORTED -4  /* flag combination or size this library does not support  */
 
 /* ---- limits ------------------------------------------------------------- */
 /* Candidate cap: one 64-lane wavefront covers the candidates of one model
