@@ -434,16 +434,22 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
     }
     if (wv == kBuilder)
       build_schedule(sh.ctt[s1], Kp, sh.ctt[s0], Kn, sh.ctt[s2], Kq, T, sh.sched[cur], &sh.nch[cur], lane);
-    for (int e = threadIdx.x; e < Kq * KL; e += NW * 64) {
-      const int k = e / KL, c = e & (KL - 1);
+    {
+      // each thread keeps one column c and walks the rows k
+      constexpr int kRowsPerPass = NW * 64 / KL;
+      const int c = threadIdx.x & (KL - 1);
       if (c < Kn) {
-        // a pair is used only if some z_{i-1} fits strictly between its frames
-        // and within T of both: 2 <= t_i - t_{i-2} <= 2T - 2
-        const int gap = sh.ctt[s0][c] - sh.ctt[s2][k];
-        if (gap >= 2 && (T <= 0 || gap <= 2 * T - 2)) {
-          const float2 pk = sh.cxy[s2][k], pc = sh.cxy[s0][c];
-          if (!DEGEN && pk.x == pc.x && pk.y == pc.y) sh.flag = 1;
-          sh.ct[e] = neg_dir<DEGEN>(pk, pc);
+        const int tc = sh.ctt[s0][c];
+        const float2 pc = sh.cxy[s0][c];
+        for (int k = threadIdx.x / KL; k < Kq; k += kRowsPerPass) {
+          // a pair is used only if some z_{i-1} fits strictly between its
+          // frames and within T of both: 2 <= t_i - t_{i-2} <= 2T - 2
+          const int gap = tc - sh.ctt[s2][k];
+          if (gap >= 2 && (T <= 0 || gap <= 2 * T - 2)) {
+            const float2 pk = sh.cxy[s2][k];
+            if (!DEGEN && pk.x == pc.x && pk.y == pc.y) sh.flag = 1;
+            sh.ct[k * KL + c] = neg_dir<DEGEN>(pk, pc);
+          }
         }
       }
     }
@@ -477,8 +483,12 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
         const float* ccol = sh.ct + col;
         float best = INF;
         if constexpr (DUMMY) best = sh.de[prv][r];  // predecessor epsilon: no D^g
+        // eight predecessors per trip (one address step per table; the wide
+        // layouts only, where few chunk slots leave registers for it), then
+        // four, then one at a time
         int k = c.lo;
-        for (; k + 3 < c.hi; k += 4) {
+        constexpr bool kEight = NW >= 8 && KL == kMaxList;
+        for (; kEight && k + 7 < c.hi; k += 8) {
           const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
           const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
           const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
@@ -486,6 +496,23 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
           const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
           const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
           best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
+          const float2 v4 = vcol[(k + 4) * KL], v5 = vcol[(k + 5) * KL];
+          const float2 v6 = vcol[(k + 6) * KL], v7 = vcol[(k + 7) * KL];
+          const float t4 = relax<DEGEN>(v4.x, v4.y, ccol[(k + 4) * KL], bm, be, th, same, w);
+          const float t5 = relax<DEGEN>(v5.x, v5.y, ccol[(k + 5) * KL], bm, be, th, same, w);
+          const float t6 = relax<DEGEN>(v6.x, v6.y, ccol[(k + 6) * KL], bm, be, th, same, w);
+          const float t7 = relax<DEGEN>(v7.x, v7.y, ccol[(k + 7) * KL], bm, be, th, same, w);
+          best = fminf(fminf(best, fminf(fminf(t4, t5), t6)), t7);
+        }
+        if (k + 3 < c.hi) {
+          const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
+          const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
+          const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
+          const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
+          const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
+          const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
+          best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
+          k += 4;
         }
         for (; k < c.hi; ++k) {
           const float2 v0 = vcol[k * KL];
@@ -678,7 +705,9 @@ __device__ __forceinline__ float* scratch_of(const DPLaunch& a, int tl) {
 }
 
 template <int NW, bool DEGEN, int KL, bool DUMMY = false>
-__global__ __launch_bounds__(NW * 64) void k_dp(DPLaunch a) {
+__global__ __launch_bounds__(NW * 64)
+__attribute__((amdgpu_waves_per_eu(KL == kMaxList && NW == 8 ? (DUMMY ? 4 : 6) : 1)))
+void k_dp(DPLaunch a) {
   __shared__ DPShared<NW, KL, DUMMY> sh;
   const int tl = blockIdx.x;
   if (DEGEN && a.degen[tl] == 0) return;
