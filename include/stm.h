@@ -29,8 +29,9 @@
  *    never throws and never aborts.  stm_last_error() describes the last
  *    failure of the calling thread.
  *  - The caller owns every input and output buffer.  The context owns its
- *    device scratch (frame index, unary table, back-pointers), grows it on
- *    demand and frees it in stm_destroy.  On STM_ENOMEM nothing was written.
+ *    device scratch (frame index, unary table, the recursion's value tables),
+ *    grows it on demand and frees it in stm_destroy.  On STM_ENOMEM nothing
+ *    was written.
  *  - Pointers are host pointers unless params->flags has STM_DEVICE_PTRS;
  *    then every input and output pointer of the call is a device pointer on
  *    the context's device, the work is queued on `hip_stream` (NULL: the HIP
@@ -68,7 +69,7 @@ extern "C" {
 
 /* ---- limits ------------------------------------------------------------- */
 /* Candidate cap: one 64-lane wavefront covers the candidates of one model
- * point, and back-pointers are stored in one byte. */
+ * point. */
 #define STM_K_LIMIT 64
 
 /* ---- flags (stm_params.flags) ------------------------------------------- */
@@ -254,6 +255,20 @@ STM_API int stm_plan_rows(const stm_plan* plan, int64_t* row_offsets, int64_t* a
  * tie rules as stm_match. */
 STM_API int stm_plan_run(stm_plan* plan, float* energy32, double* energy64, double* energy_u64,
                  int32_t* assign, void* hip_stream);
+
+/* One run over the whole batch on caller-given candidate lists: the recursion
+ * of stm_match_lists for every pair in one persistent launch (for instance
+ * many models against the paper's streaming scene blocks, Table 2).  cand[q]
+ * [n_tau_q][M_q][kc] and count[q] [n_tau_q][M_q] are device pointers for pair
+ * q, n_tau_q its row count (stm_plan_rows); point j of offset tau has the
+ * nodes cand[q][(tau * M_q + j) * kc + a], a < count, ascending.  kc <= the
+ * plan's k_max.  The offsets matter only through the lists.  Outputs as
+ * stm_plan_run.  Errors: STM_EINVAL for null arguments, kc outside
+ * [1, k_max], or lists that fail the device check (count outside [0, kc], a
+ * node outside the pair's scene, not ascending; one read-back). */
+STM_API int stm_plan_run_lists(stm_plan* plan, const int32_t* const* cand, const int32_t* const* count,
+                               int32_t kc, float* energy32, double* energy64, double* energy_u64,
+                               int32_t* assign, void* hip_stream);
 
 /* Launch shape of the persistent recursion kernel: waves per workgroup (4, 8
  * or 16) and workgroups per compute unit (1..3; 16-wave workgroups at most 2).

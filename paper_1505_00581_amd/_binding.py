@@ -34,7 +34,7 @@ EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_ma
            "stm_pruner_set_params", "stm_pruner_get_params", "stm_pruner_save", "stm_pruner_load",
            "stm_pruner_features", "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
            "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned",
-           "stm_match_chains")
+           "stm_match_chains", "stm_plan_run_lists")
 
 
 class StmError(RuntimeError):
@@ -117,6 +117,7 @@ def load() -> ctypes.CDLL:
         lib.stm_pruner_set_rule.argtypes = [P, i32]
         lib.stm_plan_run_pruned.argtypes = [P, P, i32, P, P, P, P, P, P]
         lib.stm_match_chains.argtypes = [P, PP, P, i32, PP, PS, i32, i32, P, P, P, P, P, P]
+        lib.stm_plan_run_lists.argtypes = [P, P, P, i32, P, P, P, P, P]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
                      "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
@@ -125,7 +126,7 @@ def load() -> ctypes.CDLL:
                      "stm_pruner_save", "stm_pruner_load", "stm_pruner_features",
                      "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
                      "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned",
-                     "stm_match_chains"):
+                     "stm_match_chains", "stm_plan_run_lists"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -457,6 +458,20 @@ class Plan:
         _check(self._lib.stm_plan_run(self.handle, _ptr(out["energy32"]), _ptr(out["energy64"]),
                                       _ptr(out["energy_u64"]), _ptr(out["assign"]),
                                       _stream() if self.device else None))
+        return out
+
+    def run_lists(self, cands, counts, kc: int, out=None):
+        """A run on given candidate lists (stm_plan_run_lists): cands[q] [n_q, M_q,
+        kc] and counts[q] [n_q, M_q] int32 CUDA tensors for every pair q."""
+        assert len(cands) == len(counts) == self.pairs.shape[0]
+        out = out if out is not None else self.outputs()
+        P = ctypes.c_void_p
+        cp = (P * len(cands))(*[c.data_ptr() for c in cands])
+        np_ = (P * len(counts))(*[c.data_ptr() for c in counts])
+        _check(self._lib.stm_plan_run_lists(self.handle, ctypes.addressof(cp), ctypes.addressof(np_), int(kc),
+                                            _ptr(out["energy32"]), _ptr(out["energy64"]),
+                                            _ptr(out["energy_u64"]), _ptr(out["assign"]),
+                                            _stream() if self.device else None))
         return out
 
     def run_pruned(self, pruner, topk: int = 48, out=None):

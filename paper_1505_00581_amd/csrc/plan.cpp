@@ -66,6 +66,9 @@ struct stm_plan {
   hipGraph_t graph_pr = nullptr;
   hipGraphExec_t exec_pr = nullptr;
   const void* cap_pr[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // runs on caller-given lists: the pair table with the lists, a check flag
+  stm::PairDev* ls_pairs_dev = nullptr;
+  int32_t* ls_bad = nullptr;
 };
 
 namespace {
@@ -824,6 +827,84 @@ int stm_match_batch(stm_ctx* ctx, const stm_points* models, int32_t n_models, co
   plan_free(p);
   err() = msg;
   return rc;
+}
+
+}  // extern "C"
+
+// ---- plan runs on caller-given candidate lists ---------------------------------
+
+extern "C" {
+
+int stm_plan_run_lists(stm_plan* p, const int32_t* const* cand, const int32_t* const* count, int32_t kc,
+                       float* energy32, double* energy64, double* energy_u64, int32_t* assign, void* hip_stream) {
+  err().clear();
+  if (!p || !cand || !count) return fail(STM_EINVAL, "null plan or lists");
+  if (kc < 1 || kc > p->params.k_max) return fail(STM_EINVAL, "list stride kc must be in [1, k_max]");
+  if (p->row_off.back() > 0 && (!energy32 || !assign)) return fail(STM_EINVAL, "energy32 and assign are required");
+  STM_HIP(hipSetDevice(p->ctx->device));
+  int rc = STM_OK;
+  if (!p->ls_pairs_dev) {
+    p->ls_pairs_dev = static_cast<stm::PairDev*>(
+        plan_alloc(p, std::max<size_t>(1, p->pairs_host.size()) * sizeof(stm::PairDev), &rc));
+    p->ls_bad = static_cast<int32_t*>(plan_alloc(p, sizeof(int32_t), &rc));
+    if (rc) return rc;
+  }
+  const hipStream_t user = static_cast<hipStream_t>(hip_stream);
+  STM_HIP(hipEventRecord(p->ev_in, user));
+  STM_HIP(hipStreamWaitEvent(p->stream, p->ev_in, 0));
+  const hipStream_t st = p->stream;
+  // the lists: counts in [0, kc], ascending nodes of the pair's scene
+  std::vector<stm::PairDev> ph = p->pairs_host;
+  STM_HIP(stm::launch_fill_i32(p->ls_bad, 1, 0, st));
+  for (size_t q = 0; q < ph.size(); ++q) {
+    if (ph[q].n_tau > 0 && (!cand[q] || !count[q])) return fail(STM_EINVAL, "null list of a pair with offsets");
+    STM_HIP(stm::launch_check_lists(cand[q], count[q], (long long)ph[q].n_tau * ph[q].m.M, kc, ph[q].s.S, p->ls_bad,
+                                    st));
+    ph[q].cand = cand[q];
+    ph[q].ccount = count[q];
+    ph[q].cstride = kc;
+  }
+  int32_t bad = 0;
+  STM_HIP(hipMemcpyAsync(&bad, p->ls_bad, sizeof(bad), hipMemcpyDeviceToHost, st));
+  if (!ph.empty())
+    STM_HIP(hipMemcpyAsync(p->ls_pairs_dev, ph.data(), ph.size() * sizeof(stm::PairDev), hipMemcpyHostToDevice, st));
+  STM_HIP(hipStreamSynchronize(st));
+  if (bad) return fail(STM_EINVAL, "candidate lists: count outside [0, kc], node outside the scene or not ascending");
+
+  float* e32 = p->device ? energy32 : p->o_e32;
+  double* e64 = p->device ? energy64 : (energy64 ? p->o_e64 : nullptr);
+  double* eu = p->device ? energy_u64 : (energy_u64 ? p->o_eu : nullptr);
+  int32_t* asg = p->device ? assign : p->o_asg;
+  if ((rc = plan_enqueue_tables(p, st))) return rc;
+  STM_HIP(stm::launch_fill_i32(p->counters, 3, 0, st));
+  stm::BatchLaunch b = plan_launch(p, p->ls_pairs_dev, p->items_dev, p->n_items, e32, asg);
+  b.sp.K = kc;
+  const bool timed = p->ctx->prof;
+  if (timed) STM_HIP(hipEventRecord(p->ev_k0, st));
+  STM_HIP(stm::launch_dp_persistent(b, p->n_cu * p->wgs_per_cu, st));
+  if (timed) STM_HIP(hipEventRecord(p->ev_k1, st));
+  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, p->params.T, p->params.lambda1,
+                                    p->params.lambda2, p->params.lambda3, w_dummy_of(&p->params), asg, e64, eu,
+                                    st));
+  STM_HIP(hipEventRecord(p->ev_out, st));
+  STM_HIP(hipStreamWaitEvent(user, p->ev_out, 0));
+  if (timed) {
+    STM_HIP(hipEventSynchronize(p->ev_k1));
+    float ms = 0.f;
+    STM_HIP(hipEventElapsedTime(&ms, p->ev_k0, p->ev_k1));
+    p->ctx->prof_plan_ms += ms;
+    p->ctx->prof_plan_launches += 1;
+    p->ctx->prof_matchings += p->row_off.back();
+  }
+  if (!p->device) {
+    const int64_t nr = p->row_off.back(), na = p->asg_off.back();
+    STM_HIP(hipMemcpyAsync(energy32, e32, (size_t)nr * sizeof(float), hipMemcpyDeviceToHost, st));
+    STM_HIP(hipMemcpyAsync(assign, asg, (size_t)na * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (energy64) STM_HIP(hipMemcpyAsync(energy64, e64, (size_t)nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (energy_u64) STM_HIP(hipMemcpyAsync(energy_u64, eu, (size_t)nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    STM_HIP(hipStreamSynchronize(st));
+  }
+  return STM_OK;
 }
 
 }  // extern "C"

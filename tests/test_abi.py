@@ -182,3 +182,8 @@ def test_dummy_params_pass_the_argument_checks():
     p.w_dummy = 0.4
     rc, msg = _call_match(m, s, p)
     assert rc == stm.STM_EINVAL and "context" in msg
+
+
+def test_plan_run_lists_rejects_null_arguments():
+    lib = stm.load()
+    assert lib.stm_plan_run_lists(None, None, None, 8, None, None, None, None, None) == stm.STM_EINVAL
