@@ -205,3 +205,40 @@ def test_all_points_coincide_with_dummies(ctx):
     s = synth.assemble_scene([xy], [t], [d], 14)
     p = synth.Params(window=1, k_max=8, T=6, w_dummy=0.3)
     check(m, s, p, ctx.match(m, s, p), oracle.match(m, s, p))
+
+
+def test_plan_on_lists_with_dummies(ctx):
+    """Dummies on caller-given lists in one persistent launch equal the
+    per-model list runs with dummies (host-pointer plan, host outputs)."""
+    import torch
+    w = synth.config1(6)
+    models = [w.models[0], synth.config1(7).models[0]]
+    s = w.scenes[0]
+    p = dataclasses.replace(w.params, w_dummy=0.25)
+    plan = stm.Plan(ctx, models, [s], np.array([[0, 0], [1, 0]], np.int32), p)
+    rng = np.random.default_rng(9)
+    cands, counts, host = [], [], []
+    for q, m in enumerate(models):
+        n = int(plan.row_offsets[q + 1] - plan.row_offsets[q])
+        full, cnt = ctx.candidates(m, s, p)
+        full, cnt = _np(full), _np(cnt)
+        keep = rng.random(full.shape) < 0.7
+        lists = np.full_like(full, 0)
+        c2 = np.zeros_like(cnt)
+        for t in range(n):
+            for i in range(m.n):
+                sel = [int(v) for a, v in enumerate(full[t, i, :cnt[t, i]]) if keep[t, i, a]]
+                lists[t, i, :len(sel)] = sel
+                c2[t, i] = len(sel)
+        host.append((lists, c2))
+        cands.append(torch.as_tensor(lists, device="cuda"))
+        counts.append(torch.as_tensor(c2, device="cuda"))
+    out = plan.run_lists(cands, counts, p.k_max)
+    for q, m in enumerate(models):
+        e32, e64, eu, A = [_np(x) for x in plan.pair_rows(out, q)]
+        ref = ctx.match_lists(m, s, p, host[q][0], host[q][1], 0, e32.shape[0])
+        np.testing.assert_array_equal(e32, ref["energy32"])
+        np.testing.assert_array_equal(A, ref["assign"])
+        np.testing.assert_array_equal(e64, ref["energy64"])
+        assert np.isfinite(e32).all() and (A == EPS).any()
+    plan.close()
