@@ -295,6 +295,7 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
     a.w = static_cast<float>(params->lambda2 * params->lambda3);
     a.dummy = dummy_on(params) ? 1 : 0;
     a.cw = dummy_cost32(params);
+    a.packed = !a.dummy && sparse_scene(pr.s.S, pr.s.F) ? 1 : 0;
     a.tau0 = tau_begin + c0;
     a.n_tau = nc;
     a.vt = static_cast<float*>(ctx->vt.p);

@@ -35,7 +35,11 @@
 // Section 3.4).  Each step builds a schedule of 64-cell chunks over the
 // admissible cells only, frame group by frame group; a lane takes one cell of
 // a chunk, the waves take chunks round-robin, and every lane of a chunk shares
-// the predecessor loop bounds.  Per step the LDS holds the previous V cells
+// the predecessor loop bounds.  For explicit lists on sparse scenes (about
+// one point per frame, lists spanning many frames) a group has only a few
+// cells, so the packed variant numbers all cells of a step across the chunks
+// and gives lane l of packed chunk p cell 64 p + l, each lane with its own
+// predecessor range; the minima, and so every result, are the same.  Per step the LDS holds the previous V cells
 // with their directions and the (a_{i-2}, a_i) direction table; the new cells
 // stay in registers until every wave has finished reading, then replace the
 // old ones.  Only admissible cells are ever read back.
@@ -204,9 +208,12 @@ __device__ __forceinline__ bool chunk_cell(const Chunk& c, int lane, int& r, int
 // first pair).  The rows of one frame f share the admissible columns (frames in
 // (f, f + T)) and predecessors (frames in (f - T, f)).  Each group gives
 // ceil(rows * columns / 64) <= rows chunks, so a step has at most K chunks.
+// With pstart (packed variant): pstart[j] = number of the first cell of chunk
+// j when the step's cells are numbered chunk after chunk, pstart[n] = the
+// step's cell count, also stored in *ptot.
 __device__ void build_schedule(const int32_t* trow, int nrow, const int32_t* tcol, int ncol,
                                const int32_t* tprev, int nprev, int T, uint2* out, int32_t* nout,
-                               int lane) {
+                               int lane, int16_t* pstart = nullptr, int32_t* ptot = nullptr) {
   const int f = lane < nrow ? trow[lane] : 0;
   const bool start = lane < nrow && (lane == 0 || trow[lane - 1] != f);
   const unsigned long long starts = __ballot(start);
@@ -233,6 +240,43 @@ __device__ void build_schedule(const int32_t* trow, int nrow, const int32_t* tco
     for (int c = 0; c < nchunk; ++c) out[incl - nchunk + c] = pack_chunk(lane, clo, nc, c * 64, lo, hi, nr * nc);
   const int total = __shfl(incl, 63);
   if (lane == 0) *nout = total;
+  if (pstart) {
+    int cells = nr * nc;  // inclusive scan of the groups' cell counts
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(cells, off);
+      if (lane >= off) cells += v;
+    }
+    if (start)
+      for (int c = 0; c < nchunk; ++c) pstart[incl - nchunk + c] = static_cast<int16_t>(cells - nr * nc + c * 64);
+    const int ncells = __shfl(cells, 63);
+    if (lane == 0) {
+      pstart[total] = static_cast<int16_t>(ncells);
+      *ptot = ncells;
+    }
+  }
+}
+
+// Cell 64 p + lane of a packed schedule: its chunk j (the last with pstart[j]
+// <= the number), row r, column a and predecessor range [lo, hi).  A number
+// past the step's cells decodes cell 0 (in-range reads) and returns false.
+__device__ __forceinline__ bool packed_cell(const uint2* sched, const int16_t* pstart, int n_chunks, int n_cells,
+                                            int num, int& r, int& a, int& lo, int& hi) {
+  const bool valid = num < n_cells;
+  const int e_all = valid ? num : 0;
+  int j = 0, j1 = n_chunks;  // pstart[j] <= e_all < pstart[j1]
+  while (j1 - j > 1) {
+    const int mid = (j + j1) >> 1;
+    if (pstart[mid] <= e_all) j = mid; else j1 = mid;
+  }
+  const uint2 d = sched[j];
+  const int r0 = d.x & 63, clo = (d.x >> 6) & 63, nc = (d.x >> 12) & 127, e0 = d.x >> 19;
+  lo = d.y & 127;
+  hi = (d.y >> 7) & 127;
+  const int e = e0 + (e_all - pstart[j]);
+  const int q = static_cast<int>((static_cast<float>(e) + 0.5f) * __builtin_amdgcn_rcpf(static_cast<float>(nc)));
+  r = r0 + q;
+  a = clo + (e - q * nc);
+  return valid;
 }
 
 // Per-step vectors of the dummy state, double-buffered by step parity:
@@ -246,8 +290,17 @@ struct DummyShared<KL, true> {
   float dg[2];
 };
 
-template <int NW, int KL, bool DUMMY = false>
-struct DPShared : DummyShared<KL, DUMMY> {
+// Packed schedules: first cell number of every chunk, and the step's cell count.
+template <int KL, bool PACKED>
+struct PackedShared {};
+template <int KL>
+struct PackedShared<KL, true> {
+  int16_t pstart[2][KL + 1];
+  int32_t ptot[2];
+};
+
+template <int NW, int KL, bool DUMMY = false, bool PACKED = false>
+struct DPShared : DummyShared<KL, DUMMY>, PackedShared<KL, PACKED> {
   float2 va[KL * KL];   // [a_{i-2}][a_{i-1}]: (V_{i-1}, -phi(z_{i-2} -> z_{i-1}))
   float ct[KL * KL];    // [a_{i-2}][a_i]: -phi(z_{i-2} -> z_i)
   float2 cxy[4][KL];    // candidate ring: coordinates,
@@ -324,10 +377,11 @@ struct DPResult {
 
 // Forward pass of one matching by the whole workgroup (NW waves): writes the
 // value tables of steps 1..M-2 to vtm and returns the optimum to every thread.
-template <int NW, bool DEGEN, int KL, bool DUMMY = false>
-__device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, float* vtm) {
+template <int NW, bool DEGEN, int KL, bool DUMMY = false, bool PACKED = false>
+__device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchView& a, float* vtm) {
   static_assert(KL == 16 || KL == 32 || KL == 64, "list capacity");
   static_assert(!DUMMY || KL == kMaxList, "dummies use the 64-slot layout");
+  static_assert(!PACKED || (KL == kMaxList && !DUMMY), "packed schedules: 64-slot layout, no dummies");
   constexpr int RPW = KL / NW;  // chunk slots per wave (a step has <= KL chunks)
   const int tau = a.tau;
   const int lane = threadIdx.x & 63;
@@ -339,6 +393,40 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
   const int tm0 = a.m.t[0];
   const float INF = __builtin_inff();
   constexpr int kBuilder = NW - 1;  // wave that builds the schedules
+
+  // chunk slots of schedule b, and the cell of this lane in slot ch (packed
+  // schedules: cell number 64 ch + lane; lo/hi only set there)
+  auto n_slots = [&](int b) {
+    if constexpr (PACKED) return (sh.ptot[b] + 63) >> 6;
+    else return sh.nch[b];
+  };
+  auto slot_cell = [&](int b, int ch, int& r, int& col) {
+    if constexpr (PACKED) {
+      int lo, hi;
+      return packed_cell(sh.sched[b], sh.pstart[b], sh.nch[b], sh.ptot[b], ch * 64 + lane, r, col, lo, hi);
+    } else {
+      return chunk_cell(unpack_chunk(sh.sched[b][ch]), lane, r, col);
+    }
+  };
+  // the same, with an in-range cell for lanes past the last one (their reads)
+  auto slot_cell_safe = [&](int b, int ch, int& r, int& col) {
+    if constexpr (PACKED) {
+      return slot_cell(b, ch, r, col);
+    } else {
+      const Chunk c = unpack_chunk(sh.sched[b][ch]);
+      const bool valid = chunk_cell(c, lane, r, col);
+      if (!valid) { r = c.r0; col = c.clo; }  // in-range reads; results unused
+      return valid;
+    }
+  };
+  auto schedule = [&](const int32_t* trow, int nrow, const int32_t* tcol, int ncol, const int32_t* tprev, int nprev,
+                      int b) {
+    if constexpr (PACKED)
+      build_schedule(trow, nrow, tcol, ncol, tprev, nprev, T, sh.sched[b], &sh.nch[b], lane, sh.pstart[b],
+                     &sh.ptot[b]);
+    else
+      build_schedule(trow, nrow, tcol, ncol, tprev, nprev, T, sh.sched[b], &sh.nch[b], lane);
+  };
 
   auto load_slot = [&](int j) {
     if (wv == 0) {
@@ -360,8 +448,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
   load_slot(1);
   load_slot(2);
   __syncthreads();
-  if (wv == kBuilder)
-    build_schedule(sh.ctt[0], sh.ck[0], sh.ctt[1], sh.ck[1], nullptr, 0, T, sh.sched[1], &sh.nch[1], lane);
+  if (wv == kBuilder) schedule(sh.ctt[0], sh.ck[0], sh.ctt[1], sh.ck[1], nullptr, 0, 1);
   __syncthreads();
 
   float vr[RPW], ar[RPW];
@@ -371,16 +458,14 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
   // ---- the first pair (points 0, 1) ------------------------------------------
   {
     const int dtm = a.m.t[1] - a.m.t[0];
-    const int nch = sh.nch[1];
+    const int nch = n_slots(1);
     float* vt = vtable(vtm, a, 1);
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
       const int ch = wv + NW * s;
       if (ch < nch) {
-        const Chunk c = unpack_chunk(sh.sched[1][ch]);
         int r, col;
-        const bool valid = chunk_cell(c, lane, r, col);
-        if (!valid) { r = c.r0; col = c.clo; }
+        const bool valid = slot_cell_safe(1, ch, r, col);
         const int tr = sh.ctt[0][r], tp = sh.ctt[1][col];
         const float2 xr = sh.cxy[0][r], xa = sh.cxy[1][col];
         const bool same = xa.x == xr.x && xa.y == xr.y;
@@ -421,19 +506,17 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
     // Phase 1: publish the previous step's cells, build this step's schedule and
     // (a_{i-2}, a_i) direction table, prefetch the next candidate list.
     {
-      const int nprev = sh.nch[prv];
+      const int nprev = n_slots(prv);
 #pragma unroll
       for (int s = 0; s < RPW; ++s) {
         const int ch = wv + NW * s;
         if (ch < nprev) {
-          const Chunk c = unpack_chunk(sh.sched[prv][ch]);
           int r, col;
-          if (chunk_cell(c, lane, r, col)) sh.va[r * KL + col] = make_float2(vr[s], ar[s]);
+          if (slot_cell(prv, ch, r, col)) sh.va[r * KL + col] = make_float2(vr[s], ar[s]);
         }
       }
     }
-    if (wv == kBuilder)
-      build_schedule(sh.ctt[s1], Kp, sh.ctt[s0], Kn, sh.ctt[s2], Kq, T, sh.sched[cur], &sh.nch[cur], lane);
+    if (wv == kBuilder) schedule(sh.ctt[s1], Kp, sh.ctt[s0], Kn, sh.ctt[s2], Kq, cur);
     {
       // each thread keeps one column c and walks the rows k
       constexpr int kRowsPerPass = NW * 64 / KL;
@@ -462,65 +545,99 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
     const float qw = a.lambda2 * (i <= M - 2 ? 2.f : 1.f);
     float* vt = i <= M - 2 ? vtable(vtm, a, i) : nullptr;
     const float w = a.w;
-    const int nch = sh.nch[cur];
+    const int nch = n_slots(cur);
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
       const int ch = wv + NW * s;
       float vnew = INF, anew = 0.f;
-      if (ch < nch) {
-        const Chunk c = unpack_chunk(sh.sched[cur][ch]);
-        int r, col;
-        const bool valid = chunk_cell(c, lane, r, col);
-        if (!valid) { r = c.r0; col = c.clo; }  // in-range reads; results unused
-        const int tr = sh.ctt[s1][r], tp = sh.ctt[s0][col];
-        const float2 xr = sh.cxy[s1][r], xa = sh.cxy[s0][col];
-        const bool same = xa.x == xr.x && xa.y == xr.y;
-        if (!DEGEN && same && valid) sh.flag = 1;
-        anew = neg_dir<DEGEN>(xr, xa);
-        float bm, be;
-        cell_brackets(th, -anew, bm, be);
-        const float2* vcol = sh.va + r;
-        const float* ccol = sh.ct + col;
-        float best = INF;
-        if constexpr (DUMMY) best = sh.de[prv][r];  // predecessor epsilon: no D^g
-        // eight predecessors per trip (one address step per table; the wide
-        // layouts only, where few chunk slots leave registers for it), then
-        // four, then one at a time
-        int k = c.lo;
-        constexpr bool kEight = NW >= 8 && KL == kMaxList;
-        for (; kEight && k + 7 < c.hi; k += 8) {
-          const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
-          const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
-          const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
-          const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
-          const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
-          const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
-          best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
-          const float2 v4 = vcol[(k + 4) * KL], v5 = vcol[(k + 5) * KL];
-          const float2 v6 = vcol[(k + 6) * KL], v7 = vcol[(k + 7) * KL];
-          const float t4 = relax<DEGEN>(v4.x, v4.y, ccol[(k + 4) * KL], bm, be, th, same, w);
-          const float t5 = relax<DEGEN>(v5.x, v5.y, ccol[(k + 5) * KL], bm, be, th, same, w);
-          const float t6 = relax<DEGEN>(v6.x, v6.y, ccol[(k + 6) * KL], bm, be, th, same, w);
-          const float t7 = relax<DEGEN>(v7.x, v7.y, ccol[(k + 7) * KL], bm, be, th, same, w);
-          best = fminf(fminf(best, fminf(fminf(t4, t5), t6)), t7);
+      if constexpr (PACKED) {
+        if (ch < nch) {
+          // lane-own cell and predecessor range; the wave runs to the longest
+          // range, a lane past its own repeats its last predecessor, masked
+          int r, col, lo, hi;
+          const bool valid = packed_cell(sh.sched[cur], sh.pstart[cur], sh.nch[cur], sh.ptot[cur], ch * 64 + lane, r,
+                                         col, lo, hi);
+          const int tr = sh.ctt[s1][r], tp = sh.ctt[s0][col];
+          const float2 xr = sh.cxy[s1][r], xa = sh.cxy[s0][col];
+          const bool same = xa.x == xr.x && xa.y == xr.y;
+          if (!DEGEN && same && valid) sh.flag = 1;
+          anew = neg_dir<DEGEN>(xr, xa);
+          float bm, be;
+          cell_brackets(th, -anew, bm, be);
+          const float2* vcol = sh.va + r;
+          const float* ccol = sh.ct + col;
+          const int len = hi - lo;
+          int longest = len;
+          for (int off = 32; off > 0; off >>= 1) longest = max(longest, __shfl_xor(longest, off));
+          longest = __builtin_amdgcn_readfirstlane(longest);
+          const int last = max(len - 1, 0);
+          float best = INF;
+          for (int j = 0; j < longest; ++j) {
+            const int kk = min(lo + min(j, last), KL - 1);
+            const float2 v0 = vcol[kk * KL];
+            const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[kk * KL], bm, be, th, same, w);
+            best = fminf(best, j < len ? t0 : INF);
+          }
+          const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
+          vnew = (sh.cu[s0][col] + q) + best;
+          if (valid && vt) vt[r * VS + col] = vnew;
         }
-        if (k + 3 < c.hi) {
-          const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
-          const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
-          const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
-          const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
-          const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
-          const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
-          best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
-          k += 4;
+      } else {
+        if (ch < nch) {
+          const Chunk c = unpack_chunk(sh.sched[cur][ch]);
+          int r, col;
+          const bool valid = chunk_cell(c, lane, r, col);
+          if (!valid) { r = c.r0; col = c.clo; }  // in-range reads; results unused
+          const int tr = sh.ctt[s1][r], tp = sh.ctt[s0][col];
+          const float2 xr = sh.cxy[s1][r], xa = sh.cxy[s0][col];
+          const bool same = xa.x == xr.x && xa.y == xr.y;
+          if (!DEGEN && same && valid) sh.flag = 1;
+          anew = neg_dir<DEGEN>(xr, xa);
+          float bm, be;
+          cell_brackets(th, -anew, bm, be);
+          const float2* vcol = sh.va + r;
+          const float* ccol = sh.ct + col;
+          float best = INF;
+          if constexpr (DUMMY) best = sh.de[prv][r];  // predecessor epsilon: no D^g
+          // eight predecessors per trip (one address step per table; the wide
+          // layouts only, where few chunk slots leave registers for it), then
+          // four, then one at a time
+          int k = c.lo;
+          constexpr bool kEight = NW >= 8 && KL == kMaxList;
+          for (; kEight && k + 7 < c.hi; k += 8) {
+            const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
+            const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
+            const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
+            const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
+            const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
+            const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
+            best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
+            const float2 v4 = vcol[(k + 4) * KL], v5 = vcol[(k + 5) * KL];
+            const float2 v6 = vcol[(k + 6) * KL], v7 = vcol[(k + 7) * KL];
+            const float t4 = relax<DEGEN>(v4.x, v4.y, ccol[(k + 4) * KL], bm, be, th, same, w);
+            const float t5 = relax<DEGEN>(v5.x, v5.y, ccol[(k + 5) * KL], bm, be, th, same, w);
+            const float t6 = relax<DEGEN>(v6.x, v6.y, ccol[(k + 6) * KL], bm, be, th, same, w);
+            const float t7 = relax<DEGEN>(v7.x, v7.y, ccol[(k + 7) * KL], bm, be, th, same, w);
+            best = fminf(fminf(best, fminf(fminf(t4, t5), t6)), t7);
+          }
+          if (k + 3 < c.hi) {
+            const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
+            const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
+            const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
+            const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
+            const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
+            const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
+            best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
+            k += 4;
+          }
+          for (; k < c.hi; ++k) {
+            const float2 v0 = vcol[k * KL];
+            best = fminf(best, relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w));
+          }
+          const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
+          vnew = (sh.cu[s0][col] + q) + best;
+          if (valid && vt) vt[r * VS + col] = vnew;
         }
-        for (; k < c.hi; ++k) {
-          const float2 v0 = vcol[k * KL];
-          best = fminf(best, relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w));
-        }
-        const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
-        vnew = (sh.cu[s0][col] + q) + best;
-        if (valid && vt) vt[r * VS + col] = vnew;
       }
       vr[s] = vnew;
       ar[s] = anew;
@@ -561,16 +678,15 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY>& sh, const MatchView& a, 
   {
     constexpr int RS = KL + (DUMMY ? 1 : 0);  // row stride of the result index
     const int last = (M - 1) & 1;
-    const int nch = sh.nch[last];
+    const int nch = n_slots(last);
     float bv = INF;
     int bi = 0x7fffffff;
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
       const int ch = wv + NW * s;
       if (ch < nch) {
-        const Chunk c = unpack_chunk(sh.sched[last][ch]);
         int r, col;
-        if (chunk_cell(c, lane, r, col)) {
+        if (slot_cell(last, ch, r, col)) {
           const int idx = r * RS + col;
           if (vr[s] < bv || (vr[s] == bv && idx < bi)) { bv = vr[s]; bi = idx; }
         }
@@ -704,14 +820,14 @@ __device__ __forceinline__ float* scratch_of(const DPLaunch& a, int tl) {
   return a.vt + (long long)tl * (a.m.M - 2) * vs * vs;
 }
 
-template <int NW, bool DEGEN, int KL, bool DUMMY = false>
+template <int NW, bool DEGEN, int KL, bool DUMMY = false, bool PACKED = false>
 __global__ __launch_bounds__(NW * 64)
-__attribute__((amdgpu_waves_per_eu(KL == kMaxList && NW == 8 ? (DUMMY ? 4 : 6) : 1)))
+__attribute__((amdgpu_waves_per_eu(KL == kMaxList && NW == 8 ? (DUMMY || PACKED ? 4 : 6) : 1)))
 void k_dp(DPLaunch a) {
-  __shared__ DPShared<NW, KL, DUMMY> sh;
+  __shared__ DPShared<NW, KL, DUMMY, PACKED> sh;
   const int tl = blockIdx.x;
   if (DEGEN && a.degen[tl] == 0) return;
-  const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY>(sh, view_of(a, tl), scratch_of(a, tl));
+  const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY, PACKED>(sh, view_of(a, tl), scratch_of(a, tl));
   if (threadIdx.x == 0) {
     constexpr int RS = KL + (DUMMY ? 1 : 0);
     a.e32[tl] = r.v;
@@ -769,11 +885,12 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
 // points is appended to the degenerate list instead of being backtracked, and
 // the degenerate variant (a second launch) takes the items of that list.
 // Occupancy targets: the LDS of one matching allows three 8-wave workgroups
-// per CU (two with the dummy vectors).
-template <int NW, bool DEGEN, int KL = kMaxList, bool DUMMY = false>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(DUMMY ? 4 : (NW >= 8 ? 6 : 3))))
+// per CU (two with the dummy vectors or the packed schedule).
+template <int NW, bool DEGEN, int KL = kMaxList, bool DUMMY = false, bool PACKED = false>
+__global__ __launch_bounds__(NW * 64)
+__attribute__((amdgpu_waves_per_eu(DUMMY || PACKED ? 4 : (NW >= 8 ? 6 : 3))))
 void k_dp_persistent(BatchLaunch b) {
-  __shared__ DPShared<NW, KL, DUMMY> sh;
+  __shared__ DPShared<NW, KL, DUMMY, PACKED> sh;
   __shared__ int item_sh;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* vtm = b.vt + (long long)blockIdx.x * b.vt_stride;
@@ -790,7 +907,7 @@ void k_dp_persistent(BatchLaunch b) {
     const int2 it = b.items[item];
     const PairDev pd = b.pairs[it.x];
     const MatchView mv = view_of(b, pd, it.y);
-    const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY>(sh, mv, vtm);
+    const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY, PACKED>(sh, mv, vtm);
     if (!DEGEN && r.flag) {
       if (threadIdx.x == 0) b.degen_items[atomicAdd(b.degen_count, 1)] = item;
     } else if (wv == 0) {
@@ -957,6 +1074,10 @@ hipError_t launch_dp_waves(const DPLaunch& a, hipStream_t st) {
     hipLaunchKernelGGL((k_dp<8, DEGEN, 64, true>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
     return hipGetLastError();
   }
+  if (a.packed && a.sp.K > 32) {  // sparse scenes, long lists: packed schedules
+    hipLaunchKernelGGL((k_dp<8, DEGEN, 64, false, true>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.sp.K <= 16) {
     hipLaunchKernelGGL((k_dp<1, DEGEN, 16>), dim3(a.n_tau), dim3(64), 0, st, a);
     return hipGetLastError();
@@ -988,6 +1109,10 @@ template <bool DEGEN>
 hipError_t launch_persistent_variant(const BatchLaunch& b, int n_wg, hipStream_t st) {
   if (b.dummy) {  // dummies: 8 waves whatever the tuning says
     hipLaunchKernelGGL((k_dp_persistent<8, DEGEN, kMaxList, true>), dim3(n_wg), dim3(8 * 64), 0, st, b);
+    return hipGetLastError();
+  }
+  if (b.packed) {  // sparse scenes: packed schedules, 8 waves
+    hipLaunchKernelGGL((k_dp_persistent<8, DEGEN, kMaxList, false, true>), dim3(n_wg), dim3(8 * 64), 0, st, b);
     return hipGetLastError();
   }
   switch (b.waves) {

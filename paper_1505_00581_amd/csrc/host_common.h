@@ -110,6 +110,9 @@ int check_range(const Prepared& pr, int32_t tau_begin, int32_t tau_end);
 inline bool dummy_on(const stm_params* p) { return (p->flags & STM_DUMMY) != 0; }
 inline double w_dummy_of(const stm_params* p) { return dummy_on(p) ? p->w_dummy : 0.0; }
 inline long long vt_side(const stm_params* p) { return (long long)p->k_max + (dummy_on(p) ? 1 : 0); }
+// Packed schedules for sparse scenes (at most 3 points per frame on average,
+// as interest points usually are), where a frame group holds a few cells.
+inline bool sparse_scene(int32_t S, int32_t F) { return (long long)S <= 3LL * F; }
 // lambda1 * W^d in FP32, the dummy's unary term in the recursion.
 inline float dummy_cost32(const stm_params* p) {
   return dummy_on(p) ? static_cast<float>(p->lambda1 * p->w_dummy) : 0.f;

@@ -142,6 +142,11 @@ stm::BatchLaunch plan_launch(stm_plan* p, const stm::PairDev* pairs, const int2*
   b.vt_stride = p->vt_stride;
   b.dummy = dummy_on(&p->params) ? 1 : 0;
   b.cw = dummy_cost32(&p->params);
+  b.packed = 0;
+  if (!b.dummy) {
+    b.packed = 1;
+    for (const auto& sv : p->sv) b.packed &= sparse_scene(sv.S, sv.F) ? 1 : 0;
+  }
   b.e32 = e32;
   b.assign = assign;
   b.waves = p->waves;

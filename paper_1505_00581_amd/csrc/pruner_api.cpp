@@ -265,6 +265,7 @@ stm::DPLaunch dp_base(stm_ctx* ctx, const Prepared& pr, const stm_params* params
   a.w = static_cast<float>(params->lambda2 * params->lambda3);
   a.dummy = dummy_on(params) ? 1 : 0;
   a.cw = dummy_cost32(params);
+  a.packed = !a.dummy && sparse_scene(pr.s.S, pr.s.F) ? 1 : 0;
   a.waves = ctx->dp_waves;
   a.vt = static_cast<float*>(ctx->vt.p);
   a.last2 = static_cast<int2*>(ctx->last2.p);

@@ -158,6 +158,9 @@ struct DPLaunch {
   // dummy assignments (Eq. 2): enabled flag and lambda1 * W^d in FP32
   int32_t dummy = 0;
   float cw = 0.f;
+  // packed schedules (sparse scenes, long lists; no dummies): every cell of a
+  // step on its own lane, chunk after chunk
+  int32_t packed = 0;
 };
 // The fast variant over every matching of the launch, then the variant for
 // degenerate triangles, which only recomputes the matchings flagged by the first.
@@ -208,6 +211,7 @@ struct BatchLaunch {
   long long vt_stride;
   int32_t dummy = 0;    // dummy assignments (Eq. 2) enabled
   float cw = 0.f;       // lambda1 * W^d in FP32
+  int32_t packed = 0;   // packed schedules (sparse scenes; no dummies)
   float* e32;           // [rows]
   int32_t* assign;      // [sum over pairs of n_tau * M]
   int32_t waves;        // 4, 8 or 16 waves per workgroup
