@@ -341,19 +341,19 @@ struct Cands {
   const int32_t* list;
   int n;
   __device__ __forceinline__ int count() const { return list ? n : r.k1 + r.k2; }
-  __device__ __forceinline__ int node(int a) const { return list ? list[a] : cand_node(r, a); }
+  __device__ __forceinline__ int node(int a) const { return list ? ro(list + a) : cand_node(r, a); }
 };
 
 __device__ __forceinline__ Cands cands_of(const MatchView& a, int j) {
   Cands c;
   if (a.cand) {
     c.list = a.cand + (long long)j * a.cstride;
-    c.n = a.ccount[j];
+    c.n = ro(a.ccount + j);
     c.r = CandRange{0, 0, 0, 0};
   } else {
     c.list = nullptr;
     c.n = 0;
-    c.r = point_candidates(a.s.fstart, a.s.F, a.tau + a.m.t[j] - a.m.t[0], a.sp);
+    c.r = point_candidates(a.s.fstart, a.s.F, a.tau + ro(a.m.t + j) - ro(a.m.t), a.sp);
   }
   return c;
 }
@@ -390,7 +390,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
   const int T = a.sp.T;
   const int Kc = a.sp.K;
   const int VS = a.vs;
-  const int tm0 = a.m.t[0];
+  const int tm0 = ro(a.m.t);
   const float INF = __builtin_inff();
   constexpr int kBuilder = NW - 1;  // wave that builds the schedules
 
@@ -435,9 +435,9 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
       const int sl = j & 3;
       if (lane < k) {
         const int n = c.node(lane);
-        sh.cxy[sl][lane] = a.s.xy[n];
-        sh.ctt[sl][lane] = a.s.t[n];
-        sh.cu[sl][lane] = a.lambda1 * a.U[(long long)j * a.us + n];
+        sh.cxy[sl][lane] = ro(a.s.xy + n);
+        sh.ctt[sl][lane] = ro(a.s.t + n);
+        sh.cu[sl][lane] = a.lambda1 * ro(a.U + (long long)j * a.us + n);
       }
       if (lane == 0) sh.ck[sl] = k;
     }
@@ -457,7 +457,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
 
   // ---- the first pair (points 0, 1) ------------------------------------------
   {
-    const int dtm = a.m.t[1] - a.m.t[0];
+    const int dtm = ro(a.m.t + 1) - ro(a.m.t);
     const int nch = n_slots(1);
     float* vt = vtable(vtm, a, 1);
 #pragma unroll
@@ -540,8 +540,8 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
     __syncthreads();
 
     // Phase 2: the minima over a_{i-2} of every admissible cell, chunk by chunk.
-    const float2 th = a.theta[i];
-    const int dtm = a.m.t[i] - a.m.t[i - 1];
+    const float2 th = ro(a.theta + i);
+    const int dtm = ro(a.m.t + i) - ro(a.m.t + (i - 1));
     const float qw = a.lambda2 * (i <= M - 2 ? 2.f : 1.f);
     float* vt = i <= M - 2 ? vtable(vtm, a, i) : nullptr;
     const float w = a.w;
@@ -756,23 +756,23 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
       teps = vp[Kc * VS + Kc];
     } else {
       const int nr = cr.node(r);
-      const float2 xr = a.s.xy[nr];
-      const int tr = a.s.t[nr];
+      const float2 xr = ro(a.s.xy + nr);
+      const int tr = ro(a.s.t + nr);
       if (DUMMY) teps = vp[Kc * VS + r];
       if (DUMMY && c == kEps) {
         // V_i(r, eps) = l1 W^d + min(V_{i-1}(eps, r), min_k V_{i-1}(k, r))
-        if (lane < nk && admissible(a.s.t[ck.node(lane)], tr, a.sp.T)) tot = vp[lane * VS + r];
+        if (lane < nk && admissible(ro(a.s.t + ck.node(lane)), tr, a.sp.T)) tot = vp[lane * VS + r];
       } else {
         const int nc = cc.node(c);
-        const float2 xa = a.s.xy[nc];
-        const float2 th = a.theta[i];
+        const float2 xa = ro(a.s.xy + nc);
+        const float2 th = ro(a.theta + i);
         const bool same = xa.x == xr.x && xa.y == xr.y;
         float bm, be;
         cell_brackets(th, -neg_dir<DEGEN>(xr, xa), bm, be);
         if (lane < nk) {
           const int nkn = ck.node(lane);
-          if (admissible(a.s.t[nkn], tr, a.sp.T)) {
-            const float2 pk = a.s.xy[nkn];
+          if (admissible(ro(a.s.t + nkn), tr, a.sp.T)) {
+            const float2 pk = ro(a.s.xy + nkn);
             const float v = vp[lane * VS + r];
             tot = relax<DEGEN>(v, neg_dir<DEGEN>(pk, xr), neg_dir<DEGEN>(pk, xa), bm, be, th, same, a.w);
           }
@@ -976,13 +976,16 @@ __device__ __forceinline__ double wrap64(double x) {
 // One wave re-scores the assignment z of one matching into e64[row], eu64[row].
 // A dummy (kDummyNode) costs wd; a Delta term needs both of its points
 // matched, D^g all three, and only matched consecutive points are checked.
+// The descriptor distances are taken four points at a time, 16 lanes per
+// point striding its descriptor (coalesced reads; partial sums joined by a
+// 16-lane tree); the triangle terms one point per lane.
 __device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, double l1, double l2,
                              double l3, double wd, const int32_t* __restrict__ z, long long tl,
                              double* __restrict__ e64, double* __restrict__ eu64) {
   const int lane = threadIdx.x & 63;
   const int M = m.M, dim = s.dim;
   const double inf = __builtin_inf();
-  if (z[0] == -1) {
+  if (ro(z) == -1) {
     if (lane == 0) {
       if (e64) e64[tl] = inf;
       if (eu64) eu64[tl] = inf;
@@ -991,38 +994,42 @@ __device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, 
   }
   double su = 0.0, sd = 0.0;
   int bad = 0;
-  for (int i = lane; i < M; i += 64) {
-    const int n = z[i];
-    if (n == kDummyNode) {
-      su += wd;
-    } else {
+  const int grp = lane >> 4, gl = lane & 15;
+  for (int i0 = 0; i0 < M; i0 += 4) {
+    const int i = i0 + grp;
+    const int n = i < M ? ro(z + i) : kDummyNode;
+    double acc = 0.0;
+    if (n != kDummyNode) {
       const float* f = m.desc + (long long)i * dim;
       const float* g = s.desc + (long long)n * dim;
-      double acc = 0.0;
-      for (int d = 0; d < dim; ++d) {
-        const double v = (double)f[d] - (double)g[d];
-        acc += v * v;
+      for (int d = gl; d < dim; d += 16) {
+        const double v = (double)ro(f + d) - (double)ro(g + d);
+        acc = fma(v, v, acc);
       }
-      su += sqrt(acc);
     }
-    const int nj = i >= 1 ? z[i - 1] : kDummyNode;
-    const int nk = i >= 2 ? z[i - 2] : kDummyNode;
-    if (n != kDummyNode && nj != kDummyNode && !admissible(s.t[nj], s.t[n], T)) bad = 1;
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (gl == 0 && i < M) su += n == kDummyNode ? wd : sqrt(acc);
+  }
+  for (int i = lane; i < M; i += 64) {
+    const int n = ro(z + i);
+    const int nj = i >= 1 ? ro(z + (i - 1)) : kDummyNode;
+    const int nk = i >= 2 ? ro(z + (i - 2)) : kDummyNode;
+    if (n != kDummyNode && nj != kDummyNode && !admissible(ro(s.t + nj), ro(s.t + n), T)) bad = 1;
     if (i >= 2 && (n == kDummyNode || nj == kDummyNode || nk == kDummyNode)) {
       // the Delta terms whose points are both matched; no D^g
       if (n != kDummyNode && nj != kDummyNode) {
-        const long d1 = (long)(m.t[i] - m.t[i - 1]) - (long)(s.t[n] - s.t[nj]);
+        const long d1 = (long)(ro(m.t + i) - ro(m.t + (i - 1))) - (long)(ro(s.t + n) - ro(s.t + nj));
         sd += (double)(d1 < 0 ? -d1 : d1);
       }
       if (nj != kDummyNode && nk != kDummyNode) {
-        const long d2 = (long)(m.t[i - 1] - m.t[i - 2]) - (long)(s.t[nj] - s.t[nk]);
+        const long d2 = (long)(ro(m.t + (i - 1)) - ro(m.t + (i - 2))) - (long)(ro(s.t + nj) - ro(s.t + nk));
         sd += (double)(d2 < 0 ? -d2 : d2);
       }
     } else if (i >= 2) {
-      const long dt1 = (long)(m.t[i] - m.t[i - 1]) - (long)(s.t[n] - s.t[nj]);
-      const long dt2 = (long)(m.t[i - 1] - m.t[i - 2]) - (long)(s.t[nj] - s.t[nk]);
-      const float2 pi = m.xy[i], pj = m.xy[i - 1], pk = m.xy[i - 2];
-      const float2 qi = s.xy[n], qj = s.xy[nj], qk = s.xy[nk];
+      const long dt1 = (long)(ro(m.t + i) - ro(m.t + (i - 1))) - (long)(ro(s.t + n) - ro(s.t + nj));
+      const long dt2 = (long)(ro(m.t + (i - 1)) - ro(m.t + (i - 2))) - (long)(ro(s.t + nj) - ro(s.t + nk));
+      const float2 pi = ro(m.xy + i), pj = ro(m.xy + (i - 1)), pk = ro(m.xy + (i - 2));
+      const float2 qi = ro(s.xy + n), qj = ro(s.xy + nj), qk = ro(s.xy + nk);
       const double mid_m = ang64(pi.x, pi.y, pj.x, pj.y, pk.x, pk.y);
       const double mid_s = ang64(qi.x, qi.y, qj.x, qj.y, qk.x, qk.y);
       const double end_m = ang64(pj.x, pj.y, pi.x, pi.y, pk.x, pk.y);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace stm {
 
 // Device view of one model and one scene.  Scene nodes are sorted by frame;
@@ -34,17 +36,30 @@ struct CandRange {
   int32_t s1, k1, s2, k2;
 };
 
+// Reads an input that no kernel writes while the reader runs (points, frame
+// starts, unary tables, model angles, given lists) through the constant address
+// space: a wave-uniform address becomes a scalar load and a divergent one a
+// global load, where a pointer fetched from memory would otherwise be read with
+// flat loads, which also hold up the wave's LDS waits.
+template <class T>
+__device__ __forceinline__ T ro(const T* p) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte elements");
+  using Word = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+  return __builtin_bit_cast(T, *(const __attribute__((address_space(4))) Word*)p);
+}
+
 __device__ __forceinline__ int32_t fs_at(const int32_t* __restrict__ fstart, int32_t F, int32_t f) {
   f = f < 0 ? 0 : (f > F ? F : f);
-  return fstart[f];
+  return ro(fstart + f);
 }
 
 // Per-point cap from the local density: rho = nodes in frames f0-1..f0+1,
 // K = clamp(floor((56 rho - 1170) / 60), 8, 64) (8 + 56 (rho - 30) / 60 rounded
-// half up), never above k_max.
-__device__ __forceinline__ int32_t density_cap(const int32_t* __restrict__ fstart, int32_t F,
-                                               int32_t f0, int32_t kmax) {
-  int32_t rho = fs_at(fstart, F, f0 + 2) - fs_at(fstart, F, f0 - 1);
+// half up), never above k_max.  bnd(f) is the first node of frame f, clamped
+// (fstart[0] below frame 0, fstart[F] above frame F).
+template <class Bnd>
+__device__ __forceinline__ int32_t density_cap_by(const Bnd& bnd, int32_t f0, int32_t kmax) {
+  int32_t rho = bnd(f0 + 2) - bnd(f0 - 1);
   int32_t num = 56 * rho - 1170;
   int32_t k = num >= 0 ? num / 60 : -((-num + 59) / 60);
   k = k < 8 ? 8 : (k > 64 ? 64 : k);
@@ -56,23 +71,24 @@ __device__ __forceinline__ int32_t density_cap(const int32_t* __restrict__ fstar
 // order f0, f0-1, f0+1, f0-2, f0+2, ...: whole frames are taken while they fit,
 // the first frame that does not fit contributes its lowest node ids.  The
 // whole frames form one contiguous frame interval, so the kept set is at most
-// two contiguous node ranges.
-__device__ __forceinline__ CandRange cand_range(const int32_t* __restrict__ fstart, int32_t F,
-                                                int32_t f0, int32_t W, int32_t K) {
+// two contiguous node ranges.  A frame outside the scene has bnd(f + 1) =
+// bnd(f), no nodes.
+template <class Bnd>
+__device__ __forceinline__ CandRange cand_range_by(const Bnd& bnd, int32_t f0, int32_t W, int32_t K) {
   int32_t taken = 0, lo_f = f0, hi_f = f0 - 1;
   CandRange r;
   for (int32_t step = 0; step <= 2 * W; ++step) {
     const int32_t d = step == 0 ? 0 : ((step & 1) ? -((step + 1) >> 1) : (step >> 1));
     const int32_t f = f0 + d;
-    const int32_t cnt = (f >= 0 && f < F) ? fstart[f + 1] - fstart[f] : 0;
+    const int32_t s = bnd(f);
+    const int32_t cnt = bnd(f + 1) - s;
     if (taken + cnt <= K) {
       taken += cnt;
       if (d <= 0) lo_f = f;
       if (d >= 0) hi_f = f;
     } else {
       const int32_t kp = K - taken;
-      const int32_t s = fstart[f];
-      const int32_t a = fs_at(fstart, F, lo_f), b = fs_at(fstart, F, hi_f + 1);
+      const int32_t a = bnd(lo_f), b = bnd(hi_f + 1);
       if (d < 0) {
         r.s1 = s; r.k1 = kp; r.s2 = a; r.k2 = b - a;
       } else {
@@ -81,15 +97,16 @@ __device__ __forceinline__ CandRange cand_range(const int32_t* __restrict__ fsta
       return r;
     }
   }
-  const int32_t a = fs_at(fstart, F, lo_f), b = fs_at(fstart, F, hi_f + 1);
+  const int32_t a = bnd(lo_f), b = bnd(hi_f + 1);
   r.s1 = a; r.k1 = b - a; r.s2 = b; r.k2 = 0;
   return r;
 }
 
 __device__ __forceinline__ CandRange point_candidates(const int32_t* __restrict__ fstart, int32_t F,
                                                       int32_t f0, const SearchParams& sp) {
-  const int32_t K = sp.kdensity ? density_cap(fstart, F, f0, sp.K) : sp.K;
-  return cand_range(fstart, F, f0, sp.W, K);
+  const auto bnd = [&](int32_t f) { return fs_at(fstart, F, f); };
+  const int32_t K = sp.kdensity ? density_cap_by(bnd, f0, sp.K) : sp.K;
+  return cand_range_by(bnd, f0, sp.W, K);
 }
 
 __device__ __forceinline__ int32_t cand_node(const CandRange& c, int32_t a) {
