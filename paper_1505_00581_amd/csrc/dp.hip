@@ -881,46 +881,70 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
   return v;
 }
 
-// The fast variant takes every item; an item whose matching has coincident
-// points is appended to the degenerate list instead of being backtracked, and
-// the degenerate variant (a second launch) takes the items of that list.
-// Occupancy targets: the LDS of one matching allows three 8-wave workgroups
-// per CU (two with the dummy vectors or the packed schedule).
+// A workgroup runs the forward passes of up to b.batch items (at most one per
+// wave) one after the other, each into its own value tables, then wave q
+// backtracks the q-th of them.  A backtracking walk is a
+// chain of dependent memory reads, so the batch's walks overlap instead of
+// each leaving the other waves idle.  The fast variant takes every item; an
+// item whose matching has coincident points is appended to the degenerate
+// list instead of being backtracked, and the degenerate variant (a second
+// launch) takes the items of that list.  Occupancy targets: the LDS of one
+// matching allows three 8-wave workgroups per CU (two with the dummy vectors
+// or the packed schedule).
 template <int NW, bool DEGEN, int KL = kMaxList, bool DUMMY = false, bool PACKED = false>
 __global__ __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu(DUMMY || PACKED ? 4 : (NW >= 8 ? 6 : 3))))
 void k_dp_persistent(BatchLaunch b) {
   __shared__ DPShared<NW, KL, DUMMY, PACKED> sh;
   __shared__ int item_sh;
+  __shared__ int bt_item[NW];  // item of each batch slot, -1: not backtracked here
+  __shared__ int bt_idx[NW];   // its first minimising final pair, -1: infeasible
+  constexpr int RS = KL + (DUMMY ? 1 : 0);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  float* vtm = b.vt + (long long)blockIdx.x * b.vt_stride;
+  const int nb_max = b.batch < 1 ? 1 : (b.batch < NW ? b.batch : NW);
+  float* vwg = b.vt + (long long)blockIdx.x * b.batch * b.vt_stride;
   const int n_items = DEGEN ? *b.degen_count : (b.list ? *b.list_count : b.n_items);
   int32_t* counter = DEGEN ? b.counter + 1 : b.counter;
+  int slot = 0;  // forward passes waiting for their backtracking
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
     __syncthreads();
-    const int item = item_sh >= n_items ? -1
-                     : DEGEN           ? b.degen_items[item_sh]
-                     : b.list          ? b.list[item_sh]
-                                       : item_sh;
-    if (item_sh >= n_items) break;
-    const int2 it = b.items[item];
-    const PairDev pd = b.pairs[it.x];
-    const MatchView mv = view_of(b, pd, it.y);
-    const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY, PACKED>(sh, mv, vtm);
-    if (!DEGEN && r.flag) {
-      if (threadIdx.x == 0) b.degen_items[atomicAdd(b.degen_count, 1)] = item;
-    } else if (wv == 0) {
-      constexpr int RS = KL + (DUMMY ? 1 : 0);
-      const long long row = pd.row0 + it.y;
-      int32_t* out = b.assign + pd.assign0 + (long long)it.y * pd.m.M;
-      if (lane == 0) b.e32[row] = r.v;
-      if (r.v < __builtin_inff()) {
-        backtrack_wave<DEGEN, DUMMY>(mv, vtm, r.idx / RS, r.idx % RS, lane, out);
-      } else {
-        for (int i = lane; i < pd.m.M; i += 64) out[i] = -1;
+    const bool done = item_sh >= n_items;
+    if (!done) {
+      const int item = DEGEN ? b.degen_items[item_sh] : b.list ? b.list[item_sh] : item_sh;
+      const int2 it = b.items[item];
+      const PairDev pd = b.pairs[it.x];
+      const MatchView mv = view_of(b, pd, it.y);
+      const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY, PACKED>(sh, mv, vwg + slot * b.vt_stride);
+      if (threadIdx.x == 0) {
+        if (!DEGEN && r.flag) {
+          b.degen_items[atomicAdd(b.degen_count, 1)] = item;
+          bt_item[slot] = -1;
+        } else {
+          b.e32[pd.row0 + it.y] = r.v;
+          bt_item[slot] = item;
+          bt_idx[slot] = r.v < __builtin_inff() ? r.idx : -1;
+        }
       }
+      ++slot;
     }
+    if (slot == nb_max || (done && slot > 0)) {
+      __syncthreads();
+      if (wv < slot && bt_item[wv] >= 0) {
+        const int2 it = b.items[bt_item[wv]];
+        const PairDev pd = b.pairs[it.x];
+        int32_t* out = b.assign + pd.assign0 + (long long)it.y * pd.m.M;
+        const int idx = bt_idx[wv];
+        if (idx >= 0) {
+          backtrack_wave<DEGEN, DUMMY>(view_of(b, pd, it.y), vwg + wv * b.vt_stride, idx / RS, idx % RS, lane,
+                                       out);
+        } else {
+          for (int i = lane; i < pd.m.M; i += 64) out[i] = -1;
+        }
+      }
+      slot = 0;
+    }
+    if (done) break;
     __syncthreads();
   }
 }

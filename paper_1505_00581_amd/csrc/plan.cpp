@@ -36,6 +36,7 @@ struct stm_plan {
   float* vt = nullptr;
   long long vt_stride = 0;
   size_t vt_cap = 0;                    // floats allocated in vt
+  int batch = 1;                        // items a workgroup takes at a time
   std::vector<int64_t> row_off, asg_off;
   int n_cu = 0;
   int waves = 8, wgs_per_cu = 3;
@@ -113,16 +114,37 @@ void plan_free(stm_plan* p) {
   delete p;
 }
 
-// Scratch of the persistent kernel for the current launch shape.
+// Scratch of the persistent kernel for the current launch shape: value tables
+// for batch items per workgroup, the largest batch (at most kMaxBatch) whose
+// tables fit an eighth of the free device memory and at most 16 GiB, halved
+// while the allocation fails, down to one.
 int plan_scratch(stm_plan* p) {
-  const size_t need = (size_t)p->n_cu * p->wgs_per_cu * (size_t)p->vt_stride;
-  if (need <= p->vt_cap) return STM_OK;
-  int rc = STM_OK;
-  float* q = static_cast<float*>(plan_alloc(p, need * sizeof(float), &rc));
-  if (!q) return rc;
-  p->vt = q;  // the older, smaller buffer stays owned until the plan is freed
-  p->vt_cap = need;
-  return STM_OK;
+  const size_t per_batch = (size_t)p->n_cu * p->wgs_per_cu * (size_t)p->vt_stride;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    free_b = 0;
+  }
+  const size_t budget = std::min<size_t>(size_t(16) << 30, free_b / 8);
+  int batch = stm::kMaxBatch;
+  while (batch > 1 && per_batch * batch * sizeof(float) > budget) --batch;
+  for (;; batch = batch > 1 ? batch / 2 : 0) {
+    const size_t need = per_batch * batch;
+    if (need <= p->vt_cap) {
+      p->batch = batch;
+      return STM_OK;
+    }
+    int rc = STM_OK;
+    float* q = static_cast<float*>(plan_alloc(p, need * sizeof(float), &rc));
+    if (q) {
+      p->vt = q;  // an older, smaller buffer stays owned until the plan is freed
+      p->vt_cap = need;
+      p->batch = batch;
+      err().clear();
+      return STM_OK;
+    }
+    if (batch == 1) return rc;
+  }
 }
 
 stm::BatchLaunch plan_launch(stm_plan* p, const stm::PairDev* pairs, const int2* items, int n_items,
@@ -140,6 +162,7 @@ stm::BatchLaunch plan_launch(stm_plan* p, const stm::PairDev* pairs, const int2*
   b.w = static_cast<float>(p->params.lambda2 * p->params.lambda3);
   b.vt = p->vt;
   b.vt_stride = p->vt_stride;
+  b.batch = p->batch;
   b.dummy = dummy_on(&p->params) ? 1 : 0;
   b.cw = dummy_cost32(&p->params);
   b.packed = 0;

@@ -224,8 +224,9 @@ struct BatchLaunch {
   const int32_t* list_count = nullptr;
   SearchParams sp;
   float lambda1, lambda2, w;
-  float* vt;            // value-table scratch, vt_stride floats per workgroup
+  float* vt;            // value-table scratch: batch slots of vt_stride floats per workgroup
   long long vt_stride;
+  int32_t batch = 1;    // items a workgroup takes at a time (1..kMaxBatch)
   int32_t dummy = 0;    // dummy assignments (Eq. 2) enabled
   float cw = 0.f;       // lambda1 * W^d in FP32
   int32_t packed = 0;   // packed schedules (sparse scenes; no dummies)
@@ -233,6 +234,9 @@ struct BatchLaunch {
   int32_t* assign;      // [sum over pairs of n_tau * M]
   int32_t waves;        // 4, 8 or 16 waves per workgroup
 };
+
+// Most items a persistent workgroup takes at a time.
+constexpr int kMaxBatch = 8;
 
 // The fast variant over all items, then the degenerate variant over the items
 // the first one flagged; n_wg workgroups each.
