@@ -217,18 +217,42 @@ __device__ void build_schedule(const int32_t* trow, int nrow, const int32_t* tco
   const int f = lane < nrow ? trow[lane] : 0;
   const bool start = lane < nrow && (lane == 0 || trow[lane - 1] != f);
   const unsigned long long starts = __ballot(start);
-  int nchunk = 0, nr = 0, nc = 0, clo = 0, lo = 0, hi = 0;
-  if (start) {
-    const unsigned long long later = starts & ~((2ull << lane) - 1ull);
-    const int next = later ? __ffsll(static_cast<long long>(later)) - 1 : nrow;
-    nr = next - lane;
+  int nchunk = 0, nr = 0, nc = 0, clo = 0, chi = 0, lo = 0, hi = 0;
+  if (__popcll(starts) <= 16) {
+    // few frame groups: each lane holds one column and one predecessor frame,
+    // and every count is a ballot, one group after the other
+    const int32_t tc = lane < ncol ? tcol[lane] : 0x7fffffff;  // frames are < 0x7fffffff
+    const int32_t tp = tprev && lane < nprev ? tprev[lane] : 0x7fffffff;
+    unsigned long long rem = starts;
+    while (rem) {
+      const int g = __ffsll(static_cast<long long>(rem)) - 1;
+      rem &= rem - 1;
+      const int fg = __builtin_amdgcn_readlane(f, g);
+      const int c0 = __popcll(__ballot(tc < fg + 1));
+      const int c1 = T > 0 ? __popcll(__ballot(tc < (fg > 0x7fffffff - T ? 0x7fffffff : fg + T))) : ncol;
+      const int p1 = __popcll(__ballot(tp < fg));
+      const int p0 = T > 0 ? __popcll(__ballot(tp < fg - T + 1)) : 0;
+      if (lane == g) {
+        clo = c0;
+        chi = c1;
+        hi = p1;
+        lo = p0;
+      }
+    }
+  } else if (start) {
+    // many groups (sparse scenes): binary searches, one group per lane
     clo = count_lt(tcol, ncol, f + 1);
-    const int chi = T > 0 ? count_lt(tcol, ncol, f > 0x7fffffff - T ? 0x7fffffff : f + T) : ncol;
-    nc = chi > clo ? chi - clo : 0;
+    chi = T > 0 ? count_lt(tcol, ncol, f > 0x7fffffff - T ? 0x7fffffff : f + T) : ncol;
     if (tprev) {
       hi = count_lt(tprev, nprev, f);
       lo = T > 0 ? count_lt(tprev, nprev, f - T + 1) : 0;
     }
+  }
+  if (start) {
+    const unsigned long long later = starts & ~((2ull << lane) - 1ull);
+    const int next = later ? __ffsll(static_cast<long long>(later)) - 1 : nrow;
+    nr = next - lane;
+    nc = chi > clo ? chi - clo : 0;
     nchunk = (nr * nc + 63) >> 6;
   }
   int incl = nchunk;
