@@ -55,11 +55,11 @@ __device__ __forceinline__ int32_t fs_at(const int32_t* __restrict__ fstart, int
 
 // Per-point cap from the local density: rho = nodes in frames f0-1..f0+1,
 // K = clamp(floor((56 rho - 1170) / 60), 8, 64) (8 + 56 (rho - 30) / 60 rounded
-// half up), never above k_max.  bnd(f) is the first node of frame f, clamped
-// (fstart[0] below frame 0, fstart[F] above frame F).
+// half up), never above k_max.  bnd(d) is the first node of frame f0 + d,
+// clamped (fstart[0] below frame 0, fstart[F] above frame F).
 template <class Bnd>
-__device__ __forceinline__ int32_t density_cap_by(const Bnd& bnd, int32_t f0, int32_t kmax) {
-  int32_t rho = bnd(f0 + 2) - bnd(f0 - 1);
+__device__ __forceinline__ int32_t density_cap_by(const Bnd& bnd, int32_t kmax) {
+  int32_t rho = bnd(2) - bnd(-1);
   int32_t num = 56 * rho - 1170;
   int32_t k = num >= 0 ? num / 60 : -((-num + 59) / 60);
   k = k < 8 ? 8 : (k > 64 ? 64 : k);
@@ -71,42 +71,62 @@ __device__ __forceinline__ int32_t density_cap_by(const Bnd& bnd, int32_t f0, in
 // order f0, f0-1, f0+1, f0-2, f0+2, ...: whole frames are taken while they fit,
 // the first frame that does not fit contributes its lowest node ids.  The
 // whole frames form one contiguous frame interval, so the kept set is at most
-// two contiguous node ranges.  A frame outside the scene has bnd(f + 1) =
-// bnd(f), no nodes.
-template <class Bnd>
-__device__ __forceinline__ CandRange cand_range_by(const Bnd& bnd, int32_t f0, int32_t W, int32_t K) {
-  int32_t taken = 0, lo_f = f0, hi_f = f0 - 1;
+// two contiguous node ranges.  A frame outside the scene has bnd(d + 1) =
+// bnd(d), no nodes.  kW > 0 unrolls the visiting loop for windows W <= kW,
+// so that bnd sees compile-time offsets only.
+template <int kW, class Bnd>
+__device__ __forceinline__ CandRange cand_range_by(const Bnd& bnd, int32_t W, int32_t K) {
+  int32_t taken = 0;
+  int32_t a = bnd(0), b = a;  // nodes [a, b) of the whole frames taken so far
   CandRange r;
-  for (int32_t step = 0; step <= 2 * W; ++step) {
+  // one visited frame; true once the range is complete
+  const auto visit = [&](int32_t step) {
     const int32_t d = step == 0 ? 0 : ((step & 1) ? -((step + 1) >> 1) : (step >> 1));
-    const int32_t f = f0 + d;
-    const int32_t s = bnd(f);
-    const int32_t cnt = bnd(f + 1) - s;
-    if (taken + cnt <= K) {
-      taken += cnt;
-      if (d <= 0) lo_f = f;
-      if (d >= 0) hi_f = f;
-    } else {
-      const int32_t kp = K - taken;
-      const int32_t a = bnd(lo_f), b = bnd(hi_f + 1);
-      if (d < 0) {
-        r.s1 = s; r.k1 = kp; r.s2 = a; r.k2 = b - a;
-      } else {
-        r.s1 = a; r.k1 = b - a; r.s2 = s; r.k2 = kp;
-      }
-      return r;
+    const int32_t s = bnd(d), e = bnd(d + 1);
+    if (taken + (e - s) <= K) {
+      taken += e - s;
+      if (d <= 0) a = s;
+      if (d >= 0) b = e;
+      return false;
     }
+    const int32_t kp = K - taken;
+    if (d < 0) {
+      r.s1 = s; r.k1 = kp; r.s2 = a; r.k2 = b - a;
+    } else {
+      r.s1 = a; r.k1 = b - a; r.s2 = s; r.k2 = kp;
+    }
+    return true;
+  };
+  if constexpr (kW > 0) {
+#pragma unroll
+    for (int32_t step = 0; step <= 2 * kW; ++step)
+      if (step > 2 * W || visit(step)) return step > 2 * W ? CandRange{a, b - a, b, 0} : r;
+  } else {
+    for (int32_t step = 0; step <= 2 * W; ++step)
+      if (visit(step)) return r;
   }
-  const int32_t a = bnd(lo_f), b = bnd(hi_f + 1);
-  r.s1 = a; r.k1 = b - a; r.s2 = b; r.k2 = 0;
-  return r;
+  return CandRange{a, b - a, b, 0};
 }
+
+// Windows up to this half-width read all their frame boundaries in one round
+// of independent loads before the rule runs, instead of one load per visited
+// frame.
+constexpr int32_t kWindowPreload = 3;
 
 __device__ __forceinline__ CandRange point_candidates(const int32_t* __restrict__ fstart, int32_t F,
                                                       int32_t f0, const SearchParams& sp) {
-  const auto bnd = [&](int32_t f) { return fs_at(fstart, F, f); };
-  const int32_t K = sp.kdensity ? density_cap_by(bnd, f0, sp.K) : sp.K;
-  return cand_range_by(bnd, f0, sp.W, K);
+  if (sp.W <= kWindowPreload) {
+    constexpr int kW = kWindowPreload;
+    int32_t bd[2 * kW + 4];  // first nodes of frames f0 - kW - 1 .. f0 + kW + 2
+#pragma unroll
+    for (int l = 0; l < 2 * kW + 4; ++l) bd[l] = fs_at(fstart, F, f0 - kW - 1 + l);
+    const auto bnd = [&](int32_t d) { return bd[d + kW + 1]; };
+    const int32_t K = sp.kdensity ? density_cap_by(bnd, sp.K) : sp.K;
+    return cand_range_by<kW>(bnd, sp.W, K);
+  }
+  const auto bnd = [&](int32_t d) { return fs_at(fstart, F, f0 + d); };
+  const int32_t K = sp.kdensity ? density_cap_by(bnd, sp.K) : sp.K;
+  return cand_range_by<0>(bnd, sp.W, K);
 }
 
 __device__ __forceinline__ int32_t cand_node(const CandRange& c, int32_t a) {
