@@ -182,13 +182,19 @@ __device__ __forceinline__ Chunk unpack_chunk(uint2 d) {
 }
 
 // Number of entries < x in the ascending list a[0..n).
+// Lists hold at most 64 entries, so seven probes at fixed strides suffice; the
+// probes do not branch on the data, and independent searches interleave their
+// reads.
 __device__ __forceinline__ int count_lt(const int32_t* a, int n, int x) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  if (n <= 0) return 0;
+  int pos = 0;
+#pragma unroll
+  for (int step = 64; step > 0; step >>= 1) {
+    const int probe = pos + step;
+    const int32_t v = a[(probe <= n ? probe : n) - 1];
+    if (probe <= n && v < x) pos = probe;
   }
-  return lo;
+  return pos;
 }
 
 // Cell of lane `lane` in chunk c: row r and column a; false past the last cell.

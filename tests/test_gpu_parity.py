@@ -211,6 +211,24 @@ def test_ragged_caps(ctx, K):
     check(m, s, p, res, oracle.match(m, s, p, taus=taus), rows=taus)
 
 
+@pytest.mark.parametrize("W,K,density", [(4, 16, False), (5, 64, False), (7, 37, False), (4, 64, True)])
+def test_wide_windows(ctx, W, K, density):
+    # windows wider than 3 frames take the candidate rule's general loop (the
+    # narrow ones read their frame boundaries up front); the batched and the
+    # per-model paths must both match the oracle
+    w = synth.config1(7)
+    m, s = w.models[0], w.scenes[0]
+    p = dataclasses.replace(w.params, k_max=K, window=W, k_density=density)
+    taus = np.arange(0, 71, 5)
+    res = ctx.match(m, s, p)
+    check(m, s, p, res, oracle.match(m, s, p, taus=taus), rows=taus)
+    plan = stm.Plan(ctx, [m], [s], np.array([[0, 0]], np.int32), p)
+    out = plan.run()
+    np.testing.assert_array_equal(out["energy32"], res["energy32"])
+    np.testing.assert_array_equal(out["assign"].reshape(res["assign"].shape), res["assign"])
+    plan.close()
+
+
 @pytest.mark.parametrize("T", [0, -5, 1, 2, 3])
 def test_closeness_variants(ctx, T):
     w = synth.config1(5)
