@@ -484,9 +484,13 @@ def bench_chains(ctx, seed: int, steps: int, warmup: int, n_chains: int = 3):
 
 def bench_t_sweep(ctx, w, dms, ds, steps: int, values):
     """Run time of the exact step against the closeness limit T (the run-time
-    half of the paper's Fig. 7; T <= 0 means no limit), on the same workload."""
+    half of the paper's Fig. 7; T <= 0 means no limit), on the same workload:
+    one plan over the 10 (model, scene) pairs per T, as the measured step."""
     import torch
+
+    import paper_1505_00581_amd as stm
     out = []
+    pairs = np.array([(i, 0) for i in range(len(dms))], np.int32)
     for T in values:
         pt = dataclasses.replace(w.params, T=int(T))
         work = dict(feasible_relax=0, feasible_cells=0)
@@ -494,14 +498,16 @@ def bench_t_sweep(ctx, w, dms, ds, steps: int, values):
             c = ctx.count_work(dm, ds, pt)
             for k in work:
                 work[k] += c[k]
-        outs = [ctx.match(dm, ds, pt) for dm in dms]
+        plan = stm.Plan(ctx, dms, [ds], pairs, pt)
+        res = plan.run()
+        plan.run(res)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            for dm, o in zip(dms, outs):
-                ctx.match(dm, ds, pt, out=o)
+            plan.run(res)
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / steps
+        plan.close()
         out.append(dict(T=int(T), ms_per_step=round(ms, 3), feasible_relax=work["feasible_relax"],
                         feasible_relax_per_s=round(work["feasible_relax"] / ms * 1e3, 1)))
         log(f"  T={T}: {ms:.2f} ms/step, {work['feasible_relax']:.3e} feasible relaxations")
