@@ -72,13 +72,18 @@ __global__ void k_candidates(ModelView m, SceneView s, SearchParams sp, int32_t 
 }
 
 // ---- unary table U[i][n] = ||f_i - g_n|| in FP32 (Eq. 2) -----------------------
-// One thread per scene point, 16 model rows per block staged in LDS; the
-// scene row is streamed from global memory two floats at a time.
+// One thread per scene point, 16 model rows per block staged in LDS.  The
+// scene rows of the block's 256 points are staged too, 32 dimensions at a
+// time and read from global memory in 128-byte row segments (a thread
+// streaming its own row would touch 64 lines per load across the wave).  Each
+// distance is accumulated over the dimensions in ascending order.
 constexpr int kUnaryRows = 16;
 constexpr int kUnaryMaxDim = 256;
+constexpr int kUnaryTile = 32;
 
 __global__ __launch_bounds__(kBlock) void k_unary_f32(ModelView m, SceneView s, float* __restrict__ U) {
   __shared__ float fm[kUnaryRows][kUnaryMaxDim];
+  __shared__ float gt[kBlock][kUnaryTile + 1];  // +1: lanes of one column hit distinct banks
   const int32_t dim = s.dim;
   const int32_t i0 = blockIdx.y * kUnaryRows;
   const int32_t rows = min(kUnaryRows, m.M - i0);
@@ -86,35 +91,32 @@ __global__ __launch_bounds__(kBlock) void k_unary_f32(ModelView m, SceneView s, 
     const int32_t r = e / dim, d = e - r * dim;
     fm[r][d] = r < rows ? m.desc[(long long)(i0 + r) * dim + d] : 0.0f;
   }
-  __syncthreads();
-  const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= s.S) return;
+  const int32_t n0 = blockIdx.x * kBlock;
+  const int32_t n = n0 + threadIdx.x;
   float acc[kUnaryRows];
 #pragma unroll
   for (int r = 0; r < kUnaryRows; ++r) acc[r] = 0.0f;
-  const float* g = s.desc + (long long)n * dim;
-  int32_t d = 0;
-  if ((dim & 1) == 0) {
-    const float2* g2 = reinterpret_cast<const float2*>(g);
-    for (; d < dim; d += 2) {
-      const float2 v = g2[d >> 1];
-#pragma unroll
-      for (int r = 0; r < kUnaryRows; ++r) {
-        const float a0 = fm[r][d] - v.x, a1 = fm[r][d + 1] - v.y;
-        acc[r] = fmaf(a0, a0, acc[r]);
-        acc[r] = fmaf(a1, a1, acc[r]);
-      }
+  for (int32_t d0 = 0; d0 < dim; d0 += kUnaryTile) {
+    const int32_t w = min(kUnaryTile, dim - d0);
+    __syncthreads();  // the previous tile is consumed (and fm is written, first time)
+#pragma unroll 4
+    for (int32_t j = 0; j < kUnaryTile; ++j) {
+      const int32_t e = threadIdx.x + kBlock * j;  // point e / 32, dimension e % 32 of the tile
+      const int32_t p = e / kUnaryTile, dd = e % kUnaryTile;
+      const int32_t np = n0 + p;
+      gt[p][dd] = np < s.S && dd < w ? s.desc[(long long)np * dim + d0 + dd] : 0.0f;
     }
-  } else {
-    for (; d < dim; ++d) {
-      const float v = g[d];
+    __syncthreads();
+    for (int32_t dd = 0; dd < w; ++dd) {
+      const float v = gt[threadIdx.x][dd];
 #pragma unroll
       for (int r = 0; r < kUnaryRows; ++r) {
-        const float a0 = fm[r][d] - v;
+        const float a0 = fm[r][d0 + dd] - v;
         acc[r] = fmaf(a0, a0, acc[r]);
       }
     }
   }
+  if (n >= s.S) return;
 #pragma unroll
   for (int r = 0; r < kUnaryRows; ++r)
     if (r < rows) U[(long long)(i0 + r) * s.S + n] = sqrtf(acc[r]);
