@@ -548,21 +548,35 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
     }
     if (wv == kBuilder) schedule(sh.ctt[s1], Kp, sh.ctt[s0], Kn, sh.ctt[s2], Kq, cur);
     {
-      // each thread keeps one column c and walks the rows k
-      constexpr int kRowsPerPass = NW * 64 / KL;
-      const int c = threadIdx.x & (KL - 1);
-      if (c < Kn) {
-        const int tc = sh.ctt[s0][c];
-        const float2 pc = sh.cxy[s0][c];
-        for (int k = threadIdx.x / KL; k < Kq; k += kRowsPerPass) {
-          // a pair is used only if some z_{i-1} fits strictly between its
-          // frames and within T of both: 2 <= t_i - t_{i-2} <= 2T - 2
-          const int gap = tc - sh.ctt[s2][k];
-          if (gap >= 2 && (T <= 0 || gap <= 2 * T - 2)) {
-            const float2 pk = sh.cxy[s2][k];
-            if (!DEGEN && pk.x == pc.x && pk.y == pc.y) sh.flag = 1;
-            sh.ct[k * KL + c] = neg_dir<DEGEN>(pk, pc);
-          }
+      // the (a_{i-2}, a_i) direction of row k, column c; a pair is used only
+      // if some z_{i-1} fits strictly between its frames and within T of
+      // both: 2 <= t_i - t_{i-2} <= 2T - 2
+      const auto direction = [&](int k, int c, int tc, float2 pc) {
+        const int gap = tc - sh.ctt[s2][k];
+        if (gap >= 2 && (T <= 0 || gap <= 2 * T - 2)) {
+          const float2 pk = sh.cxy[s2][k];
+          if (!DEGEN && pk.x == pc.x && pk.y == pc.y) sh.flag = 1;
+          sh.ct[k * KL + c] = neg_dir<DEGEN>(pk, pc);
+        }
+      };
+      if (KL == kMaxList && !PACKED && Kn <= 48) {
+        // short lists (density caps): the Kq x Kn pairs spread over all
+        // threads; p < 4096 and Kn <= 64 keep (p + 1/2) / Kn at least 1/128
+        // from an integer, so the truncated float quotient is exact
+        const float rn = __builtin_amdgcn_rcpf(static_cast<float>(Kn));
+        for (int p = threadIdx.x; p < Kq * Kn; p += NW * 64) {
+          const int k = static_cast<int>((static_cast<float>(p) + 0.5f) * rn);
+          const int c = p - k * Kn;
+          direction(k, c, sh.ctt[s0][c], sh.cxy[s0][c]);
+        }
+      } else {
+        // each thread keeps one column c and walks the rows k
+        constexpr int kRowsPerPass = NW * 64 / KL;
+        const int c = threadIdx.x & (KL - 1);
+        if (c < Kn) {
+          const int tc = sh.ctt[s0][c];
+          const float2 pc = sh.cxy[s0][c];
+          for (int k = threadIdx.x / KL; k < Kq; k += kRowsPerPass) direction(k, c, tc, pc);
         }
       }
     }
