@@ -225,6 +225,11 @@ STM_API int stm_match_chains(stm_ctx* ctx, const stm_points* model, const float*
  * and the FP64 re-score.  This is the paper's suggestion of matching several
  * models and spreading several trellises over the GPU at once (Section 5),
  * for the under-used GPU it measures on small scene blocks (Section 3.9).
+ * The largest scratch is the recursion's value tables: each resident
+ * workgroup keeps those of up to 8 items ((M_max - 2) x K^2 floats each, K + 1
+ * per side with dummies) and backtracks them together, as many items as fit
+ * an eighth of the free device memory and at most 16 GiB in all (at least
+ * one; STM_ENOMEM if one does not fit).
  *
  * Output rows: pair p owns the energy rows [row_offsets[p], row_offsets[p+1])
  * (one per offset, in offset order) and the assignment elements
