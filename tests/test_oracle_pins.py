@@ -337,12 +337,37 @@ def test_candidate_lists_hand_derived():
         assert list(got_c) == c["expected"], c
 
 
-def test_density_rule_matches_formula():
-    st = np.repeat(np.arange(10), [10, 20, 30, 10, 25, 30, 30, 15, 5, 0]).astype(np.int32)
-    for f in range(10):
-        rho = int(np.count_nonzero(np.abs(st - f) <= 1))
-        want = int(min(max(math.floor(8 + 56 * (rho - 30) / 60 + 0.5), 8), 64))
-        assert E.density_k(st, f, 64) == want
+def _ranges(rs):
+    return [n for lo, hi in rs for n in range(lo, hi + 1)]
+
+
+def test_density_capped_lists_hand_derived():
+    """The density cap (rho over frames f-1..f+1, rounding, the clamp to [8, 64]
+    and k_max, scene edges) against hand-derived lists, through the C oracle,
+    its Python twin and the Python cap alone."""
+    g = json.load(open(os.path.join(GOLD, "candidates.json")))["density"]
+    counts = np.array(g["scene_frame_counts"])
+    st = np.repeat(np.arange(counts.size), counts).astype(np.int32)
+    scene = synth.Points(np.zeros((st.size, 2), np.float32), st,
+                         np.zeros((st.size, 2), np.float32), counts.size)
+    model = synth.Points(np.zeros((2, 2), np.float32), np.array(g["model_t"], np.int32),
+                         np.zeros((2, 2), np.float32))
+    W = g["W"]
+    for c in g["cases"]:
+        want = _ranges(c["expected_ranges"])
+        assert len(want) == c["K"], c
+        assert int(np.count_nonzero(np.abs(st - c["frame"]) <= 1)) == c["rho"], c
+        assert E.density_k(st, c["frame"], c["k_max"]) == c["K"], c
+        p = synth.Params(window=W, k_max=c["k_max"], k_density=True)
+        got_py = E.candidates(model.t, scene.t, c["tau"], c["point"], W, c["k_max"], True)
+        got_c = oracle.candidate_list(model, scene, p, c["tau"], c["point"])
+        assert list(got_py) == want, c
+        assert list(got_c) == want, c
+    c = g["no_density_case"]
+    p = synth.Params(window=W, k_max=c["k_max"], k_density=False)
+    want = _ranges(c["expected_ranges"])
+    assert list(oracle.candidate_list(model, scene, p, c["tau"], c["point"])) == want
+    assert list(E.candidates(model.t, scene.t, c["tau"], c["point"], W, c["k_max"], False)) == want
 
 
 def test_work_counts_by_enumeration():
