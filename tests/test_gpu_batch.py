@@ -5,7 +5,10 @@
 * sampled items agree with the FP64 oracle (density caps, uneven models);
 * graph replays are identical, a new output buffer re-captures, host-pointer
   plans work, degenerate matchings inside a batch are redone exactly;
-* the autotuner picks a valid shape, writes its cache and reads it back.
+* the autotuner picks a valid shape, writes its cache and reads it back;
+* every launch shape (waves, workgroups per CU, batch, dense or packed
+  schedule) gives the same results, and a shape whose scratch cannot be
+  allocated is refused with the plan left as it was.
 """
 import json
 import os
@@ -16,11 +19,11 @@ import pytest
 
 import oracle
 import paper_1505_00581_amd as stm
+from tolerances import energy_tol
 from paper_1505_00581_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-RTOL, ATOL = 1e-5, 1e-4
 
 
 def say(*a):
@@ -106,7 +109,7 @@ def test_batch_against_oracle_and_replay(ctx):
         E = ora["energy"]
         fin = np.isfinite(E)
         assert (np.isfinite(e32[taus]) == fin).all()
-        tol = np.maximum(RTOL * np.abs(E[fin]), ATOL)
+        tol = energy_tol(E[fin])
         assert (np.abs(e32[taus][fin] - E[fin]) <= tol).all()
         eg, _ = oracle.energies(models[i], scenes[j], p, A[taus][fin])
         assert (np.abs(eg - E[fin]) <= tol).all()
@@ -137,7 +140,7 @@ def test_degenerate_matchings_inside_a_batch(ctx):
         ora = oracle.match(models[i], scenes[j], p)
         fin = np.isfinite(ora["energy"])
         assert (np.isfinite(e32) == fin).all()
-        assert (np.abs(e32[fin] - ora["energy"][fin]) <= np.maximum(RTOL * ora["energy"][fin], ATOL)).all()
+        assert (np.abs(e32[fin] - ora["energy"][fin]) <= energy_tol(ora["energy"][fin])).all()
     plan.close()
 
 
@@ -150,13 +153,68 @@ def test_autotune_and_cache(ctx, tmp_path):
     cache = str(tmp_path / "tune.json")
     ch = plan.autotune(cache, n_sample=64)
     assert ch["waves"] in (4, 8, 16) and 1 <= ch["wgs_per_cu"] <= 3 and not ch["cached"]
+    assert 1 <= ch["batch"] <= min(8, ch["waves"]) and ch["packed"] in (0, 1)
     data = json.load(open(cache))
     assert len(data) == 1 and list(data.values())[0]["waves"] == ch["waves"]
     ch2 = plan.autotune(cache)
-    assert ch2["cached"] and ch2["waves"] == ch["waves"]
+    assert ch2["cached"] and all(ch2[k] == ch[k] for k in ("waves", "wgs_per_cu", "batch", "packed"))
+    out = plan.run()
+    for k in ("energy32", "energy64", "assign"):
+        np.testing.assert_array_equal(out[k], ref[k])
     # results do not depend on the launch shape
     for w_, g in [(4, 3), (16, 2), (8, 1)]:
         plan.set_tuning(w_, g)
+        out = plan.run()
+        for k in ("energy32", "energy64", "assign"):
+            np.testing.assert_array_equal(out[k], ref[k])
+    plan.close()
+
+
+def test_shapes_and_refused_scratch(ctx):
+    """Batches of 1..8 items per workgroup and both schedule variants give the
+    same rows; with plan allocations refused (the library's failure injection)
+    a shape that needs more value-table scratch fails with STM_ENOMEM and the
+    plan keeps its shape, scratch and results."""
+    import torch
+    models, scenes, p = _small_batch(6, n_models=4, n_scenes=1)
+    pairs = _all_pairs(len(models), len(scenes))
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    stride = (max(m.n for m in models) - 2) * p.k_max * p.k_max
+    one = n_cu * 3 * stride * 4   # bytes of the value tables at 3 workgroups per CU, batch 1
+    say(f"n_cu {n_cu}, scratch of one item per workgroup at 3 per CU: {one} bytes")
+    os.environ["STM_FAILPOINT_PLAN_ALLOC"] = str(one)
+    try:
+        plan = stm.Plan(ctx, models, scenes, pairs, p)   # the scratch of larger batches is refused
+    finally:
+        del os.environ["STM_FAILPOINT_PLAN_ALLOC"]
+    assert plan.shape()["batch"] == 1
+    ref = {k: v.copy() for k, v in plan.run().items()}
+    for w_, g, b, sc in [(8, 3, 1, 0), (8, 1, 2, 1), (4, 3, 1, 1), (16, 1, 1, 0)]:
+        plan.set_shape(w_, g, b, sc)
+        eff = plan.shape()
+        assert eff["batch"] == b and eff["packed"] == sc and eff["wgs_per_cu"] == g
+        out = plan.run()
+        for k in ("energy32", "energy64", "assign"):
+            np.testing.assert_array_equal(out[k], ref[k])
+    plan.set_shape(8, 3, 1, 0)
+    before = plan.shape()
+    os.environ["STM_FAILPOINT_PLAN_ALLOC"] = "0"
+    try:
+        with pytest.raises(stm.StmError) as ei:
+            plan.set_shape(8, 3, 4, 0)   # four times the scratch it has
+        assert ei.value.code == stm.STM_ENOMEM
+        assert plan.shape() == before
+        plan.set_tuning(8, 2)            # keeps the batch request; fits the scratch it has
+        assert plan.shape()["wgs_per_cu"] == 2
+    finally:
+        del os.environ["STM_FAILPOINT_PLAN_ALLOC"]
+    out = plan.run()
+    for k in ("energy32", "energy64", "assign"):
+        np.testing.assert_array_equal(out[k], ref[k])
+    # allocations allowed again: larger batches, dense and packed, same rows
+    for w_, g, b, sc in [(8, 3, 8, 0), (8, 2, 4, 1), (16, 2, 8, 0)]:
+        plan.set_shape(w_, g, b, sc)
+        assert plan.shape()["batch"] == b
         out = plan.run()
         for k in ("energy32", "energy64", "assign"):
             np.testing.assert_array_equal(out[k], ref[k])

@@ -9,12 +9,12 @@ import pytest
 
 import oracle
 import paper_1505_00581_amd as stm
+from tolerances import energy_tol
 from oracle import chains as C
 from paper_1505_00581_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-RTOL, ATOL = 1e-5, 1e-4
 
 
 def say(*a):
@@ -40,7 +40,7 @@ def check(m, s, p, res, ora, rows=None):
     E = ora["energy"]
     fin = np.isfinite(E)
     assert (np.isfinite(e32) == fin).all()
-    tol = np.maximum(RTOL * np.abs(E[fin]), ATOL)
+    tol = energy_tol(E[fin])
     assert (np.abs(e32[fin] - E[fin]) <= tol).all(), np.abs(e32[fin] - E[fin]).max()
     assert (A[:, [q for q in range(m.n) if q not in sum(ora["chains"], [])]] == C.UNCHAINED).all()
     # the FP64 mean is the mean of the oracle's literal energies of the GPU's chain assignments
@@ -51,7 +51,7 @@ def check(m, s, p, res, ora, rows=None):
     lit /= len(ora["chains"])
     assert np.allclose(e64[fin], lit[fin], rtol=1e-9, atol=1e-9)
     same = (A == ora["assign"]).all(1)
-    assert (np.abs(lit[fin & ~same] - E[fin & ~same]) <= np.maximum(RTOL * np.abs(E[fin & ~same]), ATOL)).all()
+    assert (np.abs(lit[fin & ~same] - E[fin & ~same]) <= energy_tol(E[fin & ~same])).all()
     return dict(n=len(E), feasible=int(fin.sum()), agree=float(same.mean()), chains=len(ora["chains"]))
 
 

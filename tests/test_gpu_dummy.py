@@ -16,11 +16,11 @@ import pytest
 
 import oracle
 import paper_1505_00581_amd as stm
+from tolerances import energy_tol
 from paper_1505_00581_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-RTOL, ATOL = 1e-5, 1e-4
 EPS = -2
 
 
@@ -46,7 +46,7 @@ def check(m, s, p, res, ora, rows=None):
         e32, e64, eu64, A = e32[rows], e64[rows], eu64[rows], A[rows]
     E, Z = ora["energy"], ora["assign"]
     assert np.isfinite(E).all() and np.isfinite(e32).all()  # the all-dummy assignment is allowed
-    tol = np.maximum(RTOL * np.abs(E), ATOL)
+    tol = energy_tol(E)
     err = np.abs(e32 - E)
     bad = np.nonzero(err > tol)[0]
     assert bad.size == 0, f"energy mismatch at {bad[:5]}: gpu {e32[bad[:5]]} oracle {E[bad[:5]]}"

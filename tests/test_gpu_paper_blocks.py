@@ -9,12 +9,12 @@ import pytest
 
 import oracle
 import paper_1505_00581_amd as stm
+from tolerances import energy_tol
 from oracle import energy as E
 from paper_1505_00581_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-RTOL, ATOL = 1e-5, 1e-4
 
 
 def test_blocks_against_oracle():
@@ -31,9 +31,9 @@ def test_blocks_against_oracle():
         e = ora["energy"]
         fin = np.isfinite(e)
         assert (np.isfinite(got["energy32"][sample]) == fin).all()
-        assert (np.abs(got["energy32"][sample][fin] - e[fin]) <= np.maximum(RTOL * e[fin], ATOL)).all()
+        assert (np.abs(got["energy32"][sample][fin] - e[fin]) <= energy_tol(e[fin])).all()
         eg, _ = oracle.energies(m, s, p, got["assign"][sample][fin])
-        assert (np.abs(eg - e[fin]) <= np.maximum(RTOL * e[fin], ATOL)).all()
+        assert (np.abs(eg - e[fin]) <= energy_tol(e[fin])).all()
         np.testing.assert_allclose(got["energy64"][sample][fin], eg, rtol=1e-9)
         checked += int(fin.sum())
     print(f"  {checked} block matchings agree with the oracle", file=sys.stderr)

@@ -10,11 +10,11 @@ import pytest
 
 import oracle
 import paper_1505_00581_amd as stm
+from tolerances import energy_tol
 from paper_1505_00581_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-RTOL, ATOL = 1e-5, 1e-4
 
 
 def say(*a):
@@ -55,7 +55,7 @@ def check(m, s, p, res, ora, rows=None):
     E = ora["energy"]
     fin = np.isfinite(E)
     assert (np.isfinite(e32) == fin).all()
-    tol = np.maximum(RTOL * np.abs(E[fin]), ATOL)
+    tol = energy_tol(E[fin])
     assert (np.abs(e32[fin] - E[fin]) <= tol).all()
     eg, _ = oracle.energies(m, s, p, A[fin])
     assert (np.abs(eg - E[fin]) <= tol).all()
