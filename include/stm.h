@@ -277,17 +277,41 @@ STM_API int stm_plan_run_lists(stm_plan* plan, const int32_t* const* cand, const
 
 /* Launch shape of the persistent recursion kernel: waves per workgroup (4, 8
  * or 16) and workgroups per compute unit (1..3; 16-wave workgroups at most 2).
- * Results do not depend on it. */
+ * The plan keeps its batch and schedule requests (stm_plan_set_shape).
+ * Results do not depend on the shape.  The shape is taken only once the
+ * value-table scratch it needs is allocated: on STM_ENOMEM the plan keeps its
+ * previous shape and scratch.  Graphs captured with the previous shape (plain
+ * and pruned runs) are dropped and captured again at the next run. */
 STM_API int stm_plan_set_tuning(stm_plan* plan, int32_t waves, int32_t wgs_per_cu);
+
+/* The full launch shape, shape [4] host memory: waves, workgroups per CU (as
+ * stm_plan_set_tuning), items per workgroup batch (1..8, whose backtracking
+ * walks run together, one wave each; 0: the largest that fits an eighth of
+ * the free device memory and 16 GiB) and the schedule variant of a step's
+ * cells (0: dense chunks of one frame group, 1: packed chunks with a
+ * predecessor range per lane, -1: packed when every scene has at most 3
+ * points per frame).  Plans with STM_DUMMY always run the dense schedule,
+ * and the dummy and packed variants run 8 waves per workgroup.  Same
+ * allocation and graph rules as stm_plan_set_tuning; a given batch must fit
+ * as it is (STM_ENOMEM otherwise, the plan unchanged). */
+STM_API int stm_plan_set_shape(stm_plan* plan, const int32_t* shape);
+
+/* The shape in effect, shape [4] host memory: waves the kernel runs,
+ * workgroups per CU, batch, schedule variant (0 dense, 1 packed). */
+STM_API int stm_plan_get_shape(const stm_plan* plan, int32_t* shape);
 
 /* Picks the launch shape: looks up the key (GPU architecture, K bucket = k_max
  * rounded up to a power of two, M bucket = the largest model rounded up to a
- * multiple of 32, density flag) in the cache file `cache_path` (nullable;
- * one JSON object, one entry per line); if absent, times every candidate
- * shape on an evenly spaced sample of at most `n_sample` items (<= 0: a
- * default) of the work list, keeps the fastest and writes it to the cache.
- * chosen [3] (nullable) receives waves, workgroups per CU, and 1 if the
- * shape came from the cache. */
+ * multiple of 32, density flag, unary precision, dummies, whether the scenes
+ * are sparse) in the cache file `cache_path` (nullable; one JSON object, one
+ * entry per line); if absent, times every candidate shape (waves and
+ * workgroups per CU in {(4,3), (8,2), (8,3), (16,1), (16,2)}, batch in 1, 2,
+ * 4, 8 up to the waves, dense and packed schedules) on an evenly spaced
+ * sample of at most `n_sample` items (<= 0: 24 per compute unit) of the work
+ * list, keeps the fastest and writes it to the cache.  chosen [5] (nullable)
+ * receives the shape in effect: waves, workgroups per CU, 1 if it came from
+ * the cache, batch, schedule variant.  On an error the plan keeps its
+ * previous shape. */
 STM_API int stm_plan_autotune(stm_plan* plan, const char* cache_path, int32_t n_sample, int32_t* chosen);
 
 /* One-shot batch: plan, run once, destroy.  row_offsets [n_pairs + 1]

@@ -29,7 +29,8 @@ STM_UNCHAINED_NODE = -3  # assignment value of a point in no kept chain (stm_mat
 EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_match",
            "stm_candidates", "stm_unary", "stm_count_work", "stm_set_dp_waves",
            "stm_profile_enable", "stm_profile_read", "stm_plan_create", "stm_plan_destroy",
-           "stm_plan_rows", "stm_plan_run", "stm_plan_set_tuning", "stm_plan_autotune",
+           "stm_plan_rows", "stm_plan_run", "stm_plan_set_tuning", "stm_plan_set_shape",
+           "stm_plan_get_shape", "stm_plan_autotune",
            "stm_match_batch", "stm_pruner_num_params", "stm_pruner_create", "stm_pruner_destroy",
            "stm_pruner_set_params", "stm_pruner_get_params", "stm_pruner_save", "stm_pruner_load",
            "stm_pruner_features", "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
@@ -93,6 +94,8 @@ def load() -> ctypes.CDLL:
         lib.stm_plan_rows.argtypes = [P, P, P, P, P]
         lib.stm_plan_run.argtypes = [P, P, P, P, P, P]
         lib.stm_plan_set_tuning.argtypes = [P, i32, i32]
+        lib.stm_plan_set_shape.argtypes = [P, P]
+        lib.stm_plan_get_shape.argtypes = [P, P]
         lib.stm_plan_autotune.argtypes = [P, ctypes.c_char_p, i32, P]
         lib.stm_match_batch.argtypes = [P, P, i32, P, i32, P, i32, ctypes.POINTER(_Params), P, P, P,
                                         P, P]
@@ -121,7 +124,7 @@ def load() -> ctypes.CDLL:
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
                      "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
-                     "stm_plan_set_tuning", "stm_plan_autotune", "stm_match_batch",
+                     "stm_plan_set_tuning", "stm_plan_set_shape", "stm_plan_get_shape", "stm_plan_autotune", "stm_match_batch",
                      "stm_pruner_create", "stm_pruner_set_params", "stm_pruner_get_params",
                      "stm_pruner_save", "stm_pruner_load", "stm_pruner_features",
                      "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
@@ -501,11 +504,20 @@ class Plan:
     def set_tuning(self, waves: int, wgs_per_cu: int):
         _check(self._lib.stm_plan_set_tuning(self.handle, waves, wgs_per_cu))
 
+    def set_shape(self, waves: int, wgs_per_cu: int, batch: int = 0, sched: int = -1):
+        sh = (ctypes.c_int32 * 4)(waves, wgs_per_cu, batch, sched)
+        _check(self._lib.stm_plan_set_shape(self.handle, ctypes.addressof(sh)))
+
+    def shape(self) -> dict:
+        sh = (ctypes.c_int32 * 4)()
+        _check(self._lib.stm_plan_get_shape(self.handle, ctypes.addressof(sh)))
+        return dict(waves=sh[0], wgs_per_cu=sh[1], batch=sh[2], packed=sh[3])
+
     def autotune(self, cache_path=None, n_sample: int = 0):
-        ch = (ctypes.c_int32 * 3)()
+        ch = (ctypes.c_int32 * 5)()
         _check(self._lib.stm_plan_autotune(self.handle, cache_path.encode() if cache_path else None,
                                            n_sample, ctypes.addressof(ch)))
-        return dict(waves=ch[0], wgs_per_cu=ch[1], cached=bool(ch[2]))
+        return dict(waves=ch[0], wgs_per_cu=ch[1], cached=bool(ch[2]), batch=ch[3], packed=ch[4])
 
 
 def pruner_num_params(dim: int) -> int:

@@ -1,5 +1,7 @@
 // Host side of batched plans: many (model, scene) pairs, every offset, one
 // persistent recursion launch replayed as a HIP graph, and its autotuner.
+#include <cstdlib>
+
 #include "host_common.h"
 
 using namespace stmh;
@@ -40,6 +42,8 @@ struct stm_plan {
   std::vector<int64_t> row_off, asg_off;
   int n_cu = 0;
   int waves = 8, wgs_per_cu = 3;
+  int batch_req = 0;                    // requested batch (0: the largest that fits)
+  int sched = -1;                       // schedule: -1 the rule, 0 dense, 1 packed
   // graph of the last run
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -74,9 +78,18 @@ struct stm_plan {
 
 namespace {
 
+// Allocation failure injection for tests of the error paths: while the
+// environment variable STM_FAILPOINT_PLAN_ALLOC is set, every plan allocation
+// larger than its value in bytes fails as if the device were out of memory.
+bool plan_alloc_refused(size_t bytes) {
+  const char* v = std::getenv("STM_FAILPOINT_PLAN_ALLOC");
+  if (!v || !*v) return false;
+  return bytes > std::strtoull(v, nullptr, 10);
+}
+
 void* plan_alloc(stm_plan* p, size_t bytes, int* rc) {
   void* q = nullptr;
-  if (hipMalloc(&q, bytes ? bytes : 1) != hipSuccess) {
+  if (plan_alloc_refused(bytes) || hipMalloc(&q, bytes ? bytes : 1) != hipSuccess) {
     (void)hipGetLastError();
     *rc = fail(STM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     return nullptr;
@@ -114,37 +127,80 @@ void plan_free(stm_plan* p) {
   delete p;
 }
 
-// Scratch of the persistent kernel for the current launch shape: value tables
-// for batch items per workgroup, the largest batch (at most kMaxBatch) whose
-// tables fit an eighth of the free device memory and at most 16 GiB, halved
-// while the allocation fails, down to one.
-int plan_scratch(stm_plan* p) {
-  const size_t per_batch = (size_t)p->n_cu * p->wgs_per_cu * (size_t)p->vt_stride;
+// Launch-shape limits: 4, 8 or 16 waves per workgroup, 1..3 resident
+// workgroups per CU (16-wave workgroups at most 2), 1..kMaxBatch items per
+// workgroup batch, schedule -1 (the rule), 0 (dense) or 1 (packed).
+const char* shape_error(int waves, int wgs, int batch, int sched) {
+  if (waves != 4 && waves != 8 && waves != 16) return "waves must be 4, 8 or 16";
+  if (wgs < 1 || wgs > 3 || (waves == 16 && wgs > 2)) return "workgroups per CU must be 1..3 (1..2 with 16 waves)";
+  if (batch < 0 || batch > stm::kMaxBatch) return "batch must be 0 (automatic) or 1..8";
+  if (sched < -1 || sched > 1) return "schedule must be -1 (rule), 0 (dense) or 1 (packed)";
+  return nullptr;
+}
+
+// The schedule variant a run uses: dummies always take the dense one; packed
+// by the plan's request, or by the rule (every scene sparse).
+int plan_packed(const stm_plan* p, int sched) {
+  if (dummy_on(&p->params)) return 0;
+  if (sched >= 0) return sched;
+  int packed = 1;
+  for (const auto& sv : p->sv) packed &= sparse_scene(sv.S, sv.F) ? 1 : 0;
+  return packed;
+}
+
+// Waves per workgroup of the kernel a shape launches (the dummy and packed
+// variants run 8 whatever the request).
+int plan_eff_waves(const stm_plan* p, int waves, int sched) {
+  return dummy_on(&p->params) || plan_packed(p, sched) ? 8 : waves;
+}
+
+// Makes (waves, wgs, batch_req, sched) the plan's launch shape, with the
+// value-table scratch it needs: batch items per workgroup, each item's tables
+// vt_stride floats.  batch_req 0 takes the largest batch (at most kMaxBatch
+// and the workgroup's waves) whose tables fit an eighth of the free device
+// memory and 16 GiB, halved while the allocation fails, down to one; a given
+// batch must fit as it is.  The shape is committed only once its scratch is
+// in place: on failure the plan keeps its previous shape, batch and scratch,
+// so a later run never indexes past the buffer it has.  Graphs captured with
+// the previous shape are dropped.
+int plan_set_shape(stm_plan* p, int waves, int wgs, int batch_req, int sched) {
+  const int nw = plan_eff_waves(p, waves, sched);
+  const size_t per_batch = (size_t)p->n_cu * wgs * (size_t)p->vt_stride;
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     (void)hipGetLastError();
     free_b = 0;
   }
   const size_t budget = std::min<size_t>(size_t(16) << 30, free_b / 8);
-  int batch = stm::kMaxBatch;
-  while (batch > 1 && per_batch * batch * sizeof(float) > budget) --batch;
-  for (;; batch = batch > 1 ? batch / 2 : 0) {
+  int batch = batch_req > 0 ? batch_req : std::min(stm::kMaxBatch, nw);
+  if (batch_req <= 0)
+    while (batch > 1 && per_batch * batch * sizeof(float) > budget) --batch;
+  for (;;) {
     const size_t need = per_batch * batch;
-    if (need <= p->vt_cap) {
-      p->batch = batch;
-      return STM_OK;
-    }
-    int rc = STM_OK;
-    float* q = static_cast<float*>(plan_alloc(p, need * sizeof(float), &rc));
-    if (q) {
+    if (need > p->vt_cap) {
+      int rc = STM_OK;
+      float* q = static_cast<float*>(plan_alloc(p, need * sizeof(float), &rc));
+      if (!q) {
+        if (batch_req > 0 || batch == 1) return rc;
+        batch = batch / 2;
+        continue;
+      }
       p->vt = q;  // an older, smaller buffer stays owned until the plan is freed
       p->vt_cap = need;
-      p->batch = batch;
       err().clear();
-      return STM_OK;
     }
-    if (batch == 1) return rc;
+    break;
   }
+  if (p->waves != waves || p->wgs_per_cu != wgs || p->batch != batch || p->sched != sched) {
+    plan_drop_graph(p);
+    plan_drop_pruned_graph(p);
+  }
+  p->waves = waves;
+  p->wgs_per_cu = wgs;
+  p->batch = batch;
+  p->batch_req = batch_req;
+  p->sched = sched;
+  return STM_OK;
 }
 
 stm::BatchLaunch plan_launch(stm_plan* p, const stm::PairDev* pairs, const int2* items, int n_items,
@@ -165,11 +221,7 @@ stm::BatchLaunch plan_launch(stm_plan* p, const stm::PairDev* pairs, const int2*
   b.batch = p->batch;
   b.dummy = dummy_on(&p->params) ? 1 : 0;
   b.cw = dummy_cost32(&p->params);
-  b.packed = 0;
-  if (!b.dummy) {
-    b.packed = 1;
-    for (const auto& sv : p->sv) b.packed &= sparse_scene(sv.S, sv.F) ? 1 : 0;
-  }
+  b.packed = plan_packed(p, p->sched);
   b.e32 = e32;
   b.assign = assign;
   b.waves = p->waves;
@@ -221,7 +273,8 @@ std::string plan_key(const stm_plan* p) {
   while (k < p->params.k_max) k <<= 1;
   const int mb = (p->m_max + 31) / 32 * 32;
   return std::string("gfx950/K") + std::to_string(k) + "/M" + std::to_string(mb) + "/dens" +
-         ((p->params.flags & STM_K_DENSITY) ? "1" : "0") + (p->bf16 ? "/bf16" : "/f32");
+         ((p->params.flags & STM_K_DENSITY) ? "1" : "0") + (p->bf16 ? "/bf16" : "/f32") +
+         (dummy_on(&p->params) ? "/dummy" : "") + (plan_packed(p, -1) ? "/sparse" : "/dense");
 }
 
 }  // namespace
@@ -420,7 +473,7 @@ int stm_plan_create(stm_ctx* ctx, const stm_points* models, int32_t n_models, co
       STM_HIP(hipMemcpyAsync(p->items_dev, sorted.data(), sorted.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     }
     p->vt_stride = (long long)std::max(1, p->m_max - 2) * vt_side(params) * vt_side(params);
-    if ((rc2 = plan_scratch(p))) return rc2;
+    if ((rc2 = plan_set_shape(p, p->waves, p->wgs_per_cu, 0, -1))) return rc2;
     if (!p->device) {
       const int64_t nr = p->row_off.back(), na = p->asg_off.back();
       p->o_e32 = static_cast<float*>(plan_alloc(p, (size_t)nr * sizeof(float), &rc2));
@@ -458,15 +511,29 @@ int stm_plan_rows(const stm_plan* p, int64_t* row_offsets, int64_t* assign_offse
 int stm_plan_set_tuning(stm_plan* p, int32_t waves, int32_t wgs_per_cu) {
   err().clear();
   if (!p) return fail(STM_EINVAL, "null plan");
-  if (waves != 4 && waves != 8 && waves != 16) return fail(STM_EINVAL, "waves must be 4, 8 or 16");
-  if (wgs_per_cu < 1 || wgs_per_cu > 3 || (waves == 16 && wgs_per_cu > 2))
-    return fail(STM_EINVAL, "workgroups per CU must be 1..3 (1..2 with 16 waves)");
+  if (const char* e = shape_error(waves, wgs_per_cu, 0, -1)) return fail(STM_EINVAL, e);
   STM_HIP(hipSetDevice(p->ctx->device));
   STM_HIP(hipStreamSynchronize(p->stream));
-  p->waves = waves;
-  p->wgs_per_cu = wgs_per_cu;
-  plan_drop_graph(p);
-  return plan_scratch(p);
+  return plan_set_shape(p, waves, wgs_per_cu, p->batch_req, p->sched);
+}
+
+int stm_plan_set_shape(stm_plan* p, const int32_t* shape) {
+  err().clear();
+  if (!p || !shape) return fail(STM_EINVAL, "null plan or shape");
+  if (const char* e = shape_error(shape[0], shape[1], shape[2], shape[3])) return fail(STM_EINVAL, e);
+  STM_HIP(hipSetDevice(p->ctx->device));
+  STM_HIP(hipStreamSynchronize(p->stream));
+  return plan_set_shape(p, shape[0], shape[1], shape[2], shape[3]);
+}
+
+int stm_plan_get_shape(const stm_plan* p, int32_t* shape) {
+  err().clear();
+  if (!p || !shape) return fail(STM_EINVAL, "null plan or shape");
+  shape[0] = plan_eff_waves(p, p->waves, p->sched);
+  shape[1] = p->wgs_per_cu;
+  shape[2] = std::min(p->batch, shape[0]);
+  shape[3] = plan_packed(p, p->sched);
+  return STM_OK;
 }
 
 int stm_plan_run(stm_plan* p, float* energy32, double* energy64, double* energy_u64, int32_t* assign,
@@ -737,7 +804,20 @@ int stm_plan_autotune(stm_plan* p, const char* cache_path, int32_t n_sample, int
   err().clear();
   if (!p) return fail(STM_EINVAL, "null plan");
   const std::string key = plan_key(p);
-  // cache lookup: lines of the form  "key": {"waves": W, "wgs_per_cu": G, "ms": T},
+  // chosen: the shape in effect (waves, workgroups per CU), whether it came
+  // from the cache, the batch and the schedule variant
+  auto report = [&](int cached) {
+    if (!chosen) return;
+    int32_t eff[4];
+    (void)stm_plan_get_shape(p, eff);
+    chosen[0] = eff[0];
+    chosen[1] = eff[1];
+    chosen[2] = cached;
+    chosen[3] = eff[2];
+    chosen[4] = eff[3];
+  };
+  // cache lookup: lines of the form
+  //   "key": {"waves": W, "wgs_per_cu": G, "batch": B, "sched": S, "ms": T},
   std::vector<std::string> lines;
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
@@ -746,15 +826,18 @@ int stm_plan_autotune(stm_plan* p, const char* cache_path, int32_t n_sample, int
         std::string line(buf);
         while (!line.empty() && (line.back() == '\n' || line.back() == '\r')) line.pop_back();
         char k[256];
-        int w = 0, g = 0;
+        int w = 0, g = 0, bt = 0, sc = 0;
         double ms = 0;
-        if (std::sscanf(line.c_str(), " \"%255[^\"]\": {\"waves\": %d, \"wgs_per_cu\": %d, \"ms\": %lf}", k, &w,
-                        &g, &ms) == 4) {
-          if (key == k) {
+        if (std::sscanf(line.c_str(),
+                        " \"%255[^\"]\": {\"waves\": %d, \"wgs_per_cu\": %d, \"batch\": %d, \"sched\": %d, \"ms\": %lf}",
+                        k, &w, &g, &bt, &sc, &ms) == 6) {
+          if (key == k && !shape_error(w, g, bt, sc)) {
             std::fclose(f);
-            int rc = stm_plan_set_tuning(p, w, g);
+            STM_HIP(hipSetDevice(p->ctx->device));
+            STM_HIP(hipStreamSynchronize(p->stream));
+            int rc = plan_set_shape(p, w, g, bt, sc);
             if (rc) return rc;
-            if (chosen) { chosen[0] = w; chosen[1] = g; chosen[2] = 1; }
+            report(1);
             return STM_OK;
           }
           lines.push_back(line);
@@ -763,10 +846,15 @@ int stm_plan_autotune(stm_plan* p, const char* cache_path, int32_t n_sample, int
       std::fclose(f);
     }
   }
-  if (p->n_items == 0) return stm_plan_set_tuning(p, 8, 3);
   STM_HIP(hipSetDevice(p->ctx->device));
   const hipStream_t st = p->stream;
   STM_HIP(hipStreamSynchronize(st));
+  if (p->n_items == 0) {
+    int rc = plan_set_shape(p, 8, 3, 0, -1);
+    if (!rc) report(0);
+    return rc;
+  }
+  const int w0 = p->waves, g0 = p->wgs_per_cu, b0 = p->batch_req, s0 = p->sched;
   int rc = STM_OK;
   // outputs for the timing runs
   float* e32 = p->o_e32;
@@ -785,16 +873,27 @@ int stm_plan_autotune(stm_plan* p, const char* cache_path, int32_t n_sample, int
   if (!sdev) return rc;
   STM_HIP(hipMemcpy(sdev, sample.data(), sample.size() * sizeof(int2), hipMemcpyHostToDevice));
   if ((rc = plan_enqueue_tables(p, st))) return rc;
-  const int cand[][2] = {{4, 3}, {8, 2}, {8, 3}, {16, 1}, {16, 2}};
+  // the search space: (waves, workgroups per CU) x items per workgroup batch x
+  // schedule variant (the packed one, 8 waves, wherever dummies are off)
+  struct Cand { int w, g, b, s; };
+  std::vector<Cand> cands;
+  const int wg_pairs[][2] = {{4, 3}, {8, 2}, {8, 3}, {16, 1}, {16, 2}};
+  const bool dum = dummy_on(&p->params);
+  for (int sc = 0; sc <= (dum ? 0 : 1); ++sc)
+    for (const auto& wg : wg_pairs) {
+      if ((sc == 1 || dum) && wg[0] != 8) continue;  // those variants run 8 waves
+      for (int bt = 1; bt <= std::min(stm::kMaxBatch, wg[0]); bt *= 2) cands.push_back({wg[0], wg[1], bt, sc});
+    }
   hipEvent_t e0, e1;
   STM_HIP(hipEventCreate(&e0));
   STM_HIP(hipEventCreate(&e1));
-  int best_w = 8, best_g = 3;
+  Cand best{8, 3, 0, -1};
   double best_ms = 1e300;
-  for (const auto& c : cand) {
-    p->waves = c[0];
-    p->wgs_per_cu = c[1];
-    if ((rc = plan_scratch(p))) break;
+  for (const Cand& c : cands) {
+    if (plan_set_shape(p, c.w, c.g, c.b, c.s)) {  // a batch whose scratch does not fit: skip it
+      err().clear();
+      continue;
+    }
     const stm::BatchLaunch b = plan_launch(p, p->pairs_dev, sdev, ns, e32, asg);
     double ms_min = 1e300;
     for (int rep = 0; rep < 3 && !rc; ++rep) {
@@ -809,17 +908,28 @@ int stm_plan_autotune(stm_plan* p, const char* cache_path, int32_t n_sample, int
       if (rep > 0) ms_min = std::min<double>(ms_min, ms);  // the first run warms up
     }
     if (rc) break;
-    if (ms_min < best_ms) { best_ms = ms_min; best_w = c[0]; best_g = c[1]; }
+    if (ms_min < best_ms) { best_ms = ms_min; best = c; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (rc) return rc;
-  if ((rc = stm_plan_set_tuning(p, best_w, best_g))) return rc;
-  if (chosen) { chosen[0] = best_w; chosen[1] = best_g; chosen[2] = 0; }
+  if (rc) {
+    const std::string msg = err();
+    (void)plan_set_shape(p, w0, g0, b0, s0);  // fits: its scratch is still owned
+    err() = msg;
+    return rc;
+  }
+  if ((rc = plan_set_shape(p, best.w, best.g, best.b, best.s))) {
+    const std::string msg = err();
+    (void)plan_set_shape(p, w0, g0, b0, s0);
+    err() = msg;
+    return rc;
+  }
+  report(0);
   if (cache_path) {
     char entry[512];
-    std::snprintf(entry, sizeof(entry), "  \"%s\": {\"waves\": %d, \"wgs_per_cu\": %d, \"ms\": %.4f}", key.c_str(),
-                  best_w, best_g, best_ms);
+    std::snprintf(entry, sizeof(entry),
+                  "  \"%s\": {\"waves\": %d, \"wgs_per_cu\": %d, \"batch\": %d, \"sched\": %d, \"ms\": %.4f}",
+                  key.c_str(), best.w, best.g, best.b, best.s, best_ms);
     lines.push_back(entry);
     if (FILE* f = std::fopen(cache_path, "w")) {
       std::fputs("{\n", f);
