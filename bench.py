@@ -14,9 +14,14 @@ per model is timed beside it (per_model_launches).
 Prints one JSON line: matchings/s, DP cells/s and relaxations/s, the
 roofline of the recursion kernel (VALU-bound) from HIP events around its
 launches, and the FP64 CPU oracle timed on a bounded sample of the same
-workload on this host's cores.
+workload on this host's cores.  Further sections of the same line: the same
+step as per-model calls, with split precision and with dummy assignments;
+the multiple-points chains; the learned pruner against the exact matching;
+the step against the closeness limit T; and the batched uneven workload
+(64 models x 8 scenes in one autotuned persistent launch against one call per
+(model, scene) pair).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-batched]
 """
 import argparse
 import dataclasses
@@ -49,6 +54,8 @@ def log(*a):
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_dp_realistic_single_scene_traffic.md")
 TRAFFIC_FILE_PLAN = os.path.join(HERE, "profiles", "k_dp_persistent_realistic_single_scene_traffic.md")
+COUNTERS_FILE_PLAN = os.path.join(HERE, "profiles", "k_dp_persistent_realistic_single_scene_counters.md")
+COUNTERS_FILE_BATCHED = os.path.join(HERE, "profiles", "k_dp_persistent_batched_uneven_counters.md")
 DP_SOURCES = [os.path.join(HERE, "paper_1505_00581_amd", "csrc", f) for f in ("dp.hip", "stm_internal.h")]
 
 
@@ -80,6 +87,31 @@ def measured_traffic(path):
     try:
         return int(float(vals["calibrated fetch bytes per launch:"]) +
                    float(vals["calibrated write bytes per launch:"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_counters(path):
+    """VALU lane-instructions per feasible relaxation and VALU issue of the
+    persistent recursion kernel from its committed counter summary, or None
+    when the summary is missing or the kernel sources have changed since."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        for key in ("kernel sources sha256:", "VALU lane-instructions per feasible relaxation:",
+                    "VALU issue, all VALU instructions:", "VALU issue without transcendentals:"):
+            if line.strip().startswith(key):
+                vals[key] = line.split(":", 1)[1].strip()
+    if vals.get("kernel sources sha256:") != dp_source_hash():
+        return None
+    try:
+        return dict(valu_lane_instr_per_feasible_relax=float(vals["VALU lane-instructions per feasible relaxation:"]),
+                    valu_issue=float(vals["VALU issue, all VALU instructions:"]),
+                    valu_issue_no_trans=float(vals["VALU issue without transcendentals:"]),
+                    source=os.path.relpath(path, HERE))
     except (KeyError, ValueError):
         return None
 
@@ -124,20 +156,33 @@ def cpu_baseline(workload, target_s: float, seed: int):
         oracle.match(workload.models[mi], s, p, taus=np.array([t], np.int32), n_threads=1)
     one_s = time.perf_counter() - t0
     log(f"  cpu oracle, one core: {len(one)} matchings in {one_s:.1f}s")
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
     return solved, dict(value=done / elapsed if elapsed > 0 else None, unit="matchings/s", cores=threads,
                 kind="oracle",
-                sample=(f"{done} (model, offset) matchings drawn uniformly (seed {seed + 77}) from "
-                        f"the same workload, FP64 C oracle (literal backward recursion), "
-                        f"OpenMP over offsets, {elapsed:.1f}s"),
+                sample=(f"{done} of the workload's {len(pairs)} (model, offset) matchings "
+                        f"({100.0 * done / len(pairs):.2f}%), drawn uniformly (seed {seed + 77}), "
+                        f"FP64 C oracle (literal backward recursion), OpenMP over offsets, "
+                        f"{elapsed:.1f}s against a {target_s:.0f}s budget"),
+                sampled_fraction=round(done / len(pairs), 5),
                 one_core_value=round(len(one) / one_s, 4) if one_s > 0 else None,
                 one_core_sample=f"the first {len(one)} matchings of that sample, {one_s:.1f}s",
-                cpu_model=model, nproc=os.cpu_count())
+                cpu_model=cpu_model_name(), nproc=os.cpu_count())
+
+
+def cpu_model_name() -> str:
+    """The host CPU's model name as lscpu prints it (else /proc/cpuinfo's)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.strip().startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        return ""
 
 
 def sample_parity(solved, outs, outs_bf):
@@ -188,8 +233,16 @@ def bench_batched(ctx, seed: int, runs: int, cache_path: str):
         for k in counts:
             counts[k] += c[k]
     plan = stm.Plan(ctx, dms, dss, pairs, p)
-    tune = plan.autotune(cache_path)
+    # the launch shape the library picks without tuning, timed once, then the autotuned one
+    default_shape = plan.shape()
     out = plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(out)
+    torch.cuda.synchronize()
+    dt_default = time.perf_counter() - t0
+    tune = plan.autotune(cache_path)
+    plan.run(out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(runs):
@@ -197,7 +250,23 @@ def bench_batched(ctx, seed: int, runs: int, cache_path: str):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / runs
     n = plan.n_rows
-    log(f"  plan: {n} matchings, {dt * 1e3:.1f} ms per run, tuning {tune}")
+    log(f"  plan: {n} matchings, {dt * 1e3:.1f} ms per run (default shape {default_shape}: "
+        f"{dt_default * 1e3:.1f} ms), tuning {tune}")
+    # the recursion launches alone, between HIP events (a profiled run launches the
+    # captured kernels directly)
+    ctx.profile_enable(True)
+    for _ in range(runs):
+        plan.run(out)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    avg_s = prof["dp_ms"] / 1e3 / max(prof["dp_launches"], 1)
+    ach = counts["feasible_relax"] * OPS_PER_RELAX / avg_s / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    roof = dict(bound="alu", achieved=round(ach, 3), peak=round(peak, 3), unit="TOP/s", frac=round(ach / peak, 4),
+                kernel="k_dp_persistent (fast variant + degenerate re-run)", avg_launch_ms=round(1e3 * avg_s, 3),
+                ops_per_relax=OPS_PER_RELAX, counters=measured_counters(COUNTERS_FILE_BATCHED))
+    log(f"  recursion launch {1e3 * avg_s:.1f} ms, {roof['frac']:.3f} of the VALU ceiling")
     # baseline: one stm_match call per (model, scene) pair, no graph
     base_out = []
     for i, j in pairs:
@@ -227,7 +296,9 @@ def bench_batched(ctx, seed: int, runs: int, cache_path: str):
                 matchings=int(n), value=round(n / dt, 2), unit="matchings/s",
                 ms_per_run=round(dt * 1e3, 3), per_pair_launch_value=round(n / dt_base, 2),
                 per_pair_launch_ms=round(dt_base * 1e3, 3), speedup=round(dt_base / dt, 3),
-                identical_to_per_pair=same, tuning=tune,
+                identical_to_per_pair=same, tuning=tune, default_shape=default_shape,
+                default_shape_ms_per_run=round(dt_default * 1e3, 3),
+                tuned_speedup_vs_default_shape=round(dt_default / dt, 3), roofline=roof,
                 relax_per_s={"dense": round(counts["dense_relax"] / dt, 1),
                              "feasible": round(counts["feasible_relax"] / dt, 1)},
                 dp_cells_per_s={"dense": round(counts["dense_cells"] / dt, 1),
@@ -521,18 +592,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="CPU oracle budget in seconds")
     ap.add_argument("--dp-waves", type=int, default=0, help="waves per recursion workgroup (4, 8, 16)")
-    ap.add_argument("--batched", action="store_true",
-                    help="also time the batched uneven workload (persistent plan vs per-pair launches)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched uneven workload (persistent plan vs per-pair launches)")
     ap.add_argument("--batched-runs", type=int, default=3)
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "stm_tuning_cache.json"))
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruner section")
     ap.add_argument("--no-chains", action="store_true", help="skip the multiple-points (chains) section")
     ap.add_argument("--dummy-cost", default="0.16,0.5,1.0",
                     help="comma-separated W^d values of the dummy-assignment section (Eq. 2); empty: skip it")
-    ap.add_argument("--t-sweep", default="", help="comma-separated closeness limits T to time "
-                    "(e.g. 2,4,6,8,10,0; 0 = no limit)")
+    ap.add_argument("--t-sweep", default="2,4,6,8,10,0", help="comma-separated closeness limits T to time "
+                    "(0 = no limit); empty: skip the sweep")
     ap.add_argument("--paper-blocks", action="store_true",
                     help="also time the paper's own streaming workload (60-point blocks)")
     ap.add_argument("--pruned-k", default="16,32,48", help="pruned list sizes to evaluate")
@@ -636,23 +707,32 @@ def main():
     for _ in range(args.warmup):
         plan.run(pout)
     torch.cuda.synchronize()
-    ctx.profile_enable(True)
+    # the measured steps: graph replays
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.run(pout)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    pprof = ctx.profile_read()
-    ctx.profile_enable(False)
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = n_match * args.steps / elapsed
+    # the same steps again with HIP events around the recursion launches (a
+    # profiled run launches the graph's kernels directly on the plan's stream)
+    ctx.profile_enable(True)
+    tp = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run(pout)
+    torch.cuda.synchronize()
+    ms_profiled = 1e3 * (time.perf_counter() - tp) / args.steps
+    pprof = ctx.profile_read()
+    ctx.profile_enable(False)
     same = all(bool(torch.equal(plan.pair_rows(pout, q)[0], outs[q]["energy32"]))
                and bool(torch.equal(plan.pair_rows(pout, q)[3], outs[q]["assign"])) for q in range(len(dms)))
-    log(f"persistent plan, {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} matchings/s, "
-        f"kernel {pprof}, tuning {tuning}, identical to per-model launches: {same}")
+    log(f"persistent plan, {args.steps} steps: {ms_per_step:.2f} ms/step (graph replays), {value:.1f} matchings/s; "
+        f"profiled steps {ms_profiled:.2f} ms, kernel {pprof}, tuning {tuning}, identical to per-model launches: {same}")
     roofline = roof(pprof, 1.0, "k_dp_persistent (fast variant + degenerate re-run)",
                     measured_traffic(TRAFFIC_FILE_PLAN))
+    roofline["counters"] = measured_counters(COUNTERS_FILE_PLAN)
     plan.close()
 
     # split precision: the same step with the unary table from BF16 MFMA dot products
@@ -702,7 +782,7 @@ def main():
         blocks = bench_paper_blocks(ctx, args.steps)
 
     batched = None
-    if args.batched:
+    if not args.no_batched:
         batched = bench_batched(ctx, args.seed, args.batched_runs, args.tune_cache)
 
     sec = elapsed / args.steps
@@ -723,14 +803,17 @@ def main():
                                "1500 frames x 20 pts (320x240, 5 planted copies/model), D=162, "
                                "K=64, W=3, T=10, all offsets",
                    "matchings": n_match, "scene_points": int(s.n), "seed": args.seed,
-                   "launch": "one persistent recursion launch for all models per step, graph-replayed "
-                             "(unary tables, recursion, fused backtracking, FP64 re-score)",
+                   "launch": "one persistent recursion launch for all models per step; value and "
+                             "ms_per_step time replays of the captured HIP graph (unary tables, recursion, "
+                             "fused backtracking, FP64 re-score); roofline times the same steps launched "
+                             "directly with HIP events around the recursion launches",
+                   "profiled_ms_per_step": round(ms_profiled, 3),
                    "tuning": tuning, "identical_to_per_model_launches": same},
         "dp_cells_per_s": {"dense": round(counts["dense_cells"] / sec, 1),
                            "feasible": round(counts["feasible_cells"] / sec, 1)},
         "relax_per_s": {"dense": round(counts["dense_relax"] / sec, 1),
                         "feasible": round(counts["feasible_relax"] / sec, 1)},
-        "dp_kernel_share": round(pprof["dp_ms"] / 1e3 / elapsed, 4),
+        "dp_kernel_share": round(pprof["dp_ms"] / (ms_profiled * args.steps), 4),
         "roofline": roofline,
         "per_model_launches": per_model,
         "cpu_baseline": cpu,
