@@ -48,13 +48,13 @@ def _load():
             i32, f64 = ctypes.c_int32, ctypes.c_double
             lib.oracle_match.restype = ctypes.c_int
             lib.oracle_match.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
-                                         i32, i32, i32, i32, i32, f64, P, i32, P, P, P, P, i32]
+                                         i32, i32, i32, i32, i32, i32, f64, P, i32, P, P, P, P, i32]
             lib.oracle_match_lists.restype = ctypes.c_int
             lib.oracle_match_lists.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
-                                               i32, i32, i32, f64, P, P, i32, P, P, P, i32]
+                                               i32, i32, i32, i32, f64, P, P, i32, P, P, P, i32]
             lib.oracle_energies.restype = None
             lib.oracle_energies.argtypes = [i32, P, P, P, i32, i32, P, P, P, i32, f64, f64, f64,
-                                            i32, i32, f64, P, i32, P, P]
+                                            i32, i32, i32, f64, P, i32, P, P]
             lib.oracle_candidate_list.restype = i32
             lib.oracle_candidate_list.argtypes = [i32, P, i32, P, i32, i32, i32, i32, i32, P]
             lib.oracle_num_threads.restype = ctypes.c_int
@@ -84,6 +84,14 @@ def _dummy(params):
     return (0, 0.0) if w is None else (1, float(w))
 
 
+def _span(params) -> int:
+    """1 for the span reading of temporal closeness (params.closeness_span)."""
+    span = int(bool(getattr(params, "closeness_span", False)))
+    if span and getattr(params, "w_dummy", None) is not None:
+        raise ValueError("the span reading of closeness is not defined with dummies")
+    return span
+
+
 def match(model, scene, params, taus=None, n_threads: int = 0):
     """Exact optimum at each offset in `taus` (default: every offset).
 
@@ -103,7 +111,7 @@ def match(model, scene, params, taus=None, n_threads: int = 0):
             _f32(scene.desc)]
     rc = lib.oracle_match(M, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n, scene.n_frames,
                           _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]), model.dim,
-                          params.lambda1, params.lambda2, params.lambda3, params.T,
+                          params.lambda1, params.lambda2, params.lambda3, params.T, _span(params),
                           params.window, params.k_max, int(params.k_density), *_dummy(params),
                           _ptr(taus), n,
                           _ptr(e), _ptr(eu), _ptr(z), _ptr(c), n_threads)
@@ -131,7 +139,7 @@ def match_lists(model, scene, params, lists, counts, n_threads: int = 0):
     rc = lib.oracle_match_lists(M, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n,
                                 scene.n_frames, _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]),
                                 model.dim, params.lambda1, params.lambda2, params.lambda3, params.T,
-                                K, *_dummy(params), _ptr(lists), _ptr(counts), n, _ptr(e), _ptr(eu),
+                                _span(params), K, *_dummy(params), _ptr(lists), _ptr(counts), n, _ptr(e), _ptr(eu),
                                 _ptr(z),
                                 n_threads)
     if rc != 0:
@@ -150,8 +158,8 @@ def energies(model, scene, params, assign):
             _f32(scene.desc)]
     lib.oracle_energies(model.n, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n,
                         scene.n_frames, _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]), model.dim,
-                        params.lambda1, params.lambda2, params.lambda3, params.T, *_dummy(params),
-                        _ptr(z), n,
+                        params.lambda1, params.lambda2, params.lambda3, params.T, _span(params),
+                        *_dummy(params), _ptr(z), n,
                         _ptr(e), _ptr(eu))
     return e, eu
 

@@ -97,6 +97,20 @@ def wrap(x: float) -> float:
     return x - 2.0 * math.pi * round(x / (2.0 * math.pi))
 
 
+def closeness_span(params) -> bool:
+    """True for the span reading of temporal closeness (flag STM_CLOSENESS_SPAN)."""
+    return bool(getattr(params, "closeness_span", False))
+
+
+def span_ok(tp_first: int, tp_last: int, T: int) -> bool:
+    """Span reading of temporal closeness, from the loop bounds of Section 3.4
+    (Eq. 14, second line): the scene frames of the three points of a triangle
+    (z_{i-2}, z_{i-1}, z_i) lie less than T apart, t'(z_i) - t'(z_{i-2}) < T.
+    T <= 0 means no limit.  Under this reading consecutive points keep
+    causality (Eq. 7) only; their closeness follows from the triangles."""
+    return T <= 0 or int(tp_last) - int(tp_first) < T
+
+
 def admissible(tp_prev: int, tp_cur: int, T: int) -> bool:
     """Causality (Eq. 7) for consecutive model points i-1 < i: the scene frames
     must be strictly increasing.  Temporal closeness (Eq. 8): consecutive scene
@@ -147,15 +161,27 @@ def energy(model, scene, z, params) -> float:
     (Eq. 1 restricted to the chain hypergraph, Eq. 9), or +inf when a pair of
     consecutive points breaks causality or closeness (Eq. 7, Eq. 8).  READING:
     the constraints bind consecutive points that are both scene points; a
-    dummy on either side lifts them."""
+    dummy on either side lifts them.  With params.closeness_span, closeness is
+    the span of each triangle instead (span_ok, Section 3.4)."""
     M = len(z)
     if DUMMY in list(z) and w_dummy(params) is None:
         return INF
-    for i in range(1, M):
-        if z[i - 1] == DUMMY or z[i] == DUMMY:
-            continue
-        if not admissible(int(scene.t[z[i - 1]]), int(scene.t[z[i]]), params.T):
-            return INF
+    if closeness_span(params):
+        if DUMMY in list(z):
+            raise ValueError("the span reading of closeness is not defined with dummies")
+        st = scene.t
+        for i in range(1, M):
+            if not int(st[z[i - 1]]) < int(st[z[i]]):  # causality (Eq. 7)
+                return INF
+        for i in range(2, M):
+            if not span_ok(st[z[i - 2]], st[z[i]], params.T):
+                return INF
+    else:
+        for i in range(1, M):
+            if z[i - 1] == DUMMY or z[i] == DUMMY:
+                continue
+            if not admissible(int(scene.t[z[i - 1]]), int(scene.t[z[i]]), params.T):
+                return INF
     eu = sum(unary_of(model, scene, i, z[i], params) for i in range(M))
     ed = sum(triangle_cost(model, scene, i, z[i], z[i - 1], z[i - 2], params.lambda3)
              for i in range(2, M))

@@ -47,6 +47,7 @@ typedef struct {
   int32_t T, W, K, k_density;
   int32_t dummy; /* dummy assignments enabled */
   double wd;     /* W^d, the unary cost of a dummy (Eq. 2) */
+  int32_t span;  /* closeness as the span of each triangle (see triple_ok) */
 } problem;
 
 /* Oriented angle at vertex b of triangle (a, b, c), ray b->a to ray b->c;
@@ -73,10 +74,29 @@ static double delta(int32_t tp, int32_t tq, int32_t sp, int32_t sq) {
 }
 
 /* A consecutive pair (z_{i-1}, z_i) is allowed: admissible, or a dummy on
- * either side. */
+ * either side.  Under the span reading only causality binds the pair. */
 static int pair_ok(const problem* p, int32_t zprev, int32_t zcur) {
   if (zprev == ORACLE_EPS || zcur == ORACLE_EPS) return 1;
+  if (p->span) return p->st[zprev] < p->st[zcur];
   return admissible(p->st[zprev], p->st[zcur], p->T);
+}
+
+/* READING (span form of temporal closeness, from the loop bounds of Section
+ * 3.4, Eq. 14): the first and last scene frames of a triangle (z_{i-2},
+ * z_{i-1}, z_i) lie less than T apart.  Always true in the pairwise reading
+ * (Eq. 8), and for T <= 0. */
+static int triple_ok(const problem* p, int32_t zk, int32_t zi) {
+  if (!p->span || p->T <= 0) return 1;
+  return p->st[zi] - p->st[zk] < p->T;
+}
+
+/* A pair that can sit in an admissible assignment, for the work counts: the
+ * pairwise constraints, or under the span reading causality with a gap of at
+ * most T - 2 (a triangle holding the pair spans at least one more frame). */
+static int cell_ok(const problem* p, int32_t zprev, int32_t zcur) {
+  if (!p->span) return admissible(p->st[zprev], p->st[zcur], p->T);
+  if (!(p->st[zprev] < p->st[zcur])) return 0;
+  return p->T <= 0 || p->st[zcur] - p->st[zprev] <= p->T - 2;
 }
 
 /* D(z_i, z_{i-1}, z_{i-2}) = D^t + lambda3 * D^g (Eq. 3, 4, 6); with dummies,
@@ -113,7 +133,8 @@ static double unary(const problem* p, int i, int32_t n) {
  * non-null it receives lambda1 * sum U. */
 double oracle_energy(const problem* p, const int32_t* z, double* eu) {
   for (int i = 0; i < p->M; ++i)
-    if (z[i] == -1 || (z[i] == ORACLE_EPS && !p->dummy) || (i > 0 && !pair_ok(p, z[i - 1], z[i]))) {
+    if (z[i] == -1 || (z[i] == ORACLE_EPS && !p->dummy) || (i > 0 && !pair_ok(p, z[i - 1], z[i])) ||
+        (i > 1 && !triple_ok(p, z[i - 2], z[i]))) {
       if (eu) *eu = INFINITY;
       return INFINITY;
     }
@@ -223,15 +244,17 @@ static int match_one(const problem* p, int32_t tau, const int32_t* given, const 
     for (int b = 0; b < cnt[i - 1]; ++b)
       for (int a = 0; a < cnt[i]; ++a) {
         counts[0] += 1;
-        counts[1] += admissible(p->st[cand[(size_t)(i - 1) * K + b]], p->st[cand[(size_t)i * K + a]], p->T);
+        counts[1] += cell_ok(p, cand[(size_t)(i - 1) * K + b], cand[(size_t)i * K + a]);
       }
   for (int i = 2; i < M; ++i)
     for (int c = 0; c < cnt[i - 2]; ++c)
       for (int b = 0; b < cnt[i - 1]; ++b) {
-        int ab = admissible(p->st[cand[(size_t)(i - 2) * K + c]], p->st[cand[(size_t)(i - 1) * K + b]], p->T);
+        const int32_t zk = cand[(size_t)(i - 2) * K + c], zj = cand[(size_t)(i - 1) * K + b];
+        int ab = cell_ok(p, zk, zj);
         for (int a = 0; a < cnt[i]; ++a) {
+          const int32_t zi = cand[(size_t)i * K + a];
           counts[2] += 1;
-          counts[3] += ab && admissible(p->st[cand[(size_t)(i - 1) * K + b]], p->st[cand[(size_t)i * K + a]], p->T);
+          counts[3] += ab && cell_ok(p, zj, zi) && triple_ok(p, zk, zi);
         }
       }
 
@@ -247,7 +270,7 @@ static int match_one(const problem* p, int32_t tau, const int32_t* given, const 
         if (pair_ok(p, zk, zj)) {
           for (int ai = 0; ai < nst[i]; ++ai) {
             const int32_t zi = NODE(i, ai);
-            if (!pair_ok(p, zj, zi)) continue;
+            if (!pair_ok(p, zj, zi) || !triple_ok(p, zk, zi)) continue;
             double v = u[(size_t)i * KS + ai] + p->lambda2 * triangle_cost(p, i, zi, zj, zk);
             if (i < M - 1) v += alpha[((size_t)(i + 1) * KS + ai) * KS + aj];
             if (v < best) { best = v; arg = ai; }
@@ -301,12 +324,12 @@ done:
 static problem make_problem(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                             int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
                             int32_t dim, double l1, double l2, double l3, int32_t T, int32_t W, int32_t K,
-                            int32_t k_density, int32_t dummy, double wd) {
+                            int32_t k_density, int32_t dummy, double wd, int32_t span) {
   problem p;
   p.M = M; p.S = S; p.F = F; p.dim = dim;
   p.mxy = mxy; p.mt = mt; p.mdesc = mdesc; p.sxy = sxy; p.st = st; p.sdesc = sdesc;
   p.lambda1 = l1; p.lambda2 = l2; p.lambda3 = l3; p.T = T; p.W = W; p.K = K; p.k_density = k_density;
-  p.dummy = dummy; p.wd = wd;
+  p.dummy = dummy; p.wd = wd; p.span = span;
   return p;
 }
 
@@ -316,11 +339,11 @@ static problem make_problem(int32_t M, const float* mxy, const int32_t* mt, cons
  * Returns 0, or -5 if a re-evaluated optimum disagreed with the recursion. */
 int oracle_match(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                  int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
-                 int32_t dim, double l1, double l2, double l3, int32_t T, int32_t W, int32_t K,
+                 int32_t dim, double l1, double l2, double l3, int32_t T, int32_t span, int32_t W, int32_t K,
                  int32_t k_density, int32_t dummy, double wd, const int32_t* taus, int32_t n_tau,
                  double* energy, double* energy_u, int32_t* assign, long long* counts, int32_t n_threads) {
   problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, W, K, k_density,
-                           dummy, wd);
+                           dummy, wd, span);
   long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
   int rc = 0;
 #ifdef _OPENMP
@@ -342,10 +365,11 @@ int oracle_match(int32_t M, const float* mxy, const int32_t* mt, const float* md
  * offsets matter only through the lists.  Returns as oracle_match. */
 int oracle_match_lists(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                        int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
-                       int32_t dim, double l1, double l2, double l3, int32_t T, int32_t K,
+                       int32_t dim, double l1, double l2, double l3, int32_t T, int32_t span, int32_t K,
                        int32_t dummy, double wd, const int32_t* lists, const int32_t* counts_in,
                        int32_t n_tau, double* energy, double* energy_u, int32_t* assign, int32_t n_threads) {
-  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, K, 0, dummy, wd);
+  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, K, 0, dummy, wd,
+                           span);
   int rc = 0;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -364,9 +388,10 @@ int oracle_match_lists(int32_t M, const float* mxy, const int32_t* mt, const flo
  * energy_u nullable. */
 void oracle_energies(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                      int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
-                     int32_t dim, double l1, double l2, double l3, int32_t T, int32_t dummy, double wd,
-                     const int32_t* z, int32_t n, double* energy, double* energy_u) {
-  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, 1, 0, dummy, wd);
+                     int32_t dim, double l1, double l2, double l3, int32_t T, int32_t span, int32_t dummy,
+                     double wd, const int32_t* z, int32_t n, double* energy, double* energy_u) {
+  problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, 1, 0, dummy, wd,
+                           span);
   for (int32_t j = 0; j < n; ++j)
     energy[j] = oracle_energy(&p, z + (size_t)j * M, energy_u ? energy_u + j : NULL);
 }
@@ -375,7 +400,7 @@ void oracle_energies(int32_t M, const float* mxy, const int32_t* mt, const float
 int32_t oracle_candidate_list(int32_t M, const int32_t* mt, int32_t S, const int32_t* st,
                               int32_t W, int32_t K, int32_t k_density, int32_t tau, int32_t i,
                               int32_t* out) {
-  problem p = make_problem(M, NULL, mt, NULL, S, 0, NULL, st, NULL, 0, 0, 0, 0, 0, W, K, k_density, 0, 0.0);
+  problem p = make_problem(M, NULL, mt, NULL, S, 0, NULL, st, NULL, 0, 0, 0, 0, 0, W, K, k_density, 0, 0.0, 0);
   return oracle_candidates(&p, tau, i, out);
 }
 
