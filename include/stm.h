@@ -180,6 +180,38 @@ STM_API int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* s
               float* energy32, double* energy64, double* energy_u64, int32_t* assign,
               void* hip_stream);
 
+/* ---- the exact matching without allocation -------------------------------
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels, results and tie rules as stm_match, with all device scratch taken
+ * from one fixed array of STM_NOALLOC_SCRATCH_BYTES per device, which the
+ * library holds from the first stm_create on that device until the process
+ * ends.  It never calls hipMalloc or hipFree.
+ *
+ * params->flags must hold STM_DEVICE_PTRS: every input and output is a
+ * caller-owned device pointer, the work is queued on `hip_stream` (NULL: the
+ * HIP default stream) and the call returns after the input validation (one
+ * small device-to-host read, so the call itself cannot be captured into a
+ * graph).  The offsets run in chunks of as many as the array holds beside the
+ * frame index, model angles and unary table (and the BF16 copies with
+ * STM_UNARY_BF16).
+ *
+ * Every call on a device shares that device's array and leaves its contents
+ * behind; calls that overlap on one device (from several host threads, or on
+ * streams not ordered with each other) race on it and must be serialised by
+ * the caller.
+ * Errors: as stm_match; STM_EINVAL without STM_DEVICE_PTRS, or when the
+ * frame index, angles and unary table plus the buffers of one offset exceed
+ * the array (M * S * 4 bytes of unary table, (M - 2) * K^2 * 4 bytes per
+ * offset, (K + 1)^2 with STM_DUMMY); STM_EHIP if the array's device address
+ * could not be looked up at context creation. */
+#define STM_NOALLOC_SCRATCH_BYTES (256u << 20)
+STM_API int stm_match_noalloc(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
+                              const stm_params* params, int32_t tau_begin, int32_t tau_end,
+                              float* energy32, double* energy64, double* energy_u64, int32_t* assign,
+                              void* hip_stream);
+
 /* ---- several points per model frame ------------------------------------------
  *
  * The multiple-points model, variant 2 of Section 4 (Table 4): the model is

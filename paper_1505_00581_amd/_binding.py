@@ -25,6 +25,7 @@ STM_K_DENSITY = 0x4
 STM_DUMMY = 0x8
 STM_DUMMY_NODE = -2  # assignment value of a dummy (unmatched model point)
 STM_UNCHAINED_NODE = -3  # assignment value of a point in no kept chain (stm_match_chains)
+STM_NOALLOC_SCRATCH_BYTES = 256 << 20  # fixed device array of stm_match_noalloc
 
 EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_match",
            "stm_candidates", "stm_unary", "stm_count_work", "stm_set_dp_waves",
@@ -35,7 +36,7 @@ EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_ma
            "stm_pruner_set_params", "stm_pruner_get_params", "stm_pruner_save", "stm_pruner_load",
            "stm_pruner_features", "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
            "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned",
-           "stm_match_chains", "stm_plan_run_lists")
+           "stm_match_chains", "stm_plan_run_lists", "stm_match_noalloc")
 
 
 class StmError(RuntimeError):
@@ -121,6 +122,7 @@ def load() -> ctypes.CDLL:
         lib.stm_plan_run_pruned.argtypes = [P, P, i32, P, P, P, P, P, P]
         lib.stm_match_chains.argtypes = [P, PP, P, i32, PP, PS, i32, i32, P, P, P, P, P, P]
         lib.stm_plan_run_lists.argtypes = [P, P, P, i32, P, P, P, P, P]
+        lib.stm_match_noalloc.argtypes = [P, PP, PP, PS, i32, i32, P, P, P, P, P]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
                      "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
@@ -129,7 +131,7 @@ def load() -> ctypes.CDLL:
                      "stm_pruner_save", "stm_pruner_load", "stm_pruner_features",
                      "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
                      "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned",
-                     "stm_match_chains", "stm_plan_run_lists"):
+                     "stm_match_chains", "stm_plan_run_lists", "stm_match_noalloc"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -265,6 +267,31 @@ class Context:
                                    ctypes.byref(pp), b, e, _ptr(out["energy32"]),
                                    _ptr(out["energy64"]), _ptr(out["energy_u64"]),
                                    _ptr(out["assign"]), stream))
+        out["tau_begin"], out["tau_end"] = b, e
+        return out
+
+    def match_noalloc(self, model, scene, params, tau_begin=None, tau_end=None, out=None):
+        """stm_match_noalloc: the exact matching on the library's fixed device
+        array (no device allocation by the library).  DevicePoints only; the
+        outputs are torch tensors (`out`, or new ones)."""
+        if not _is_device(model) or not _is_device(scene):
+            raise TypeError("match_noalloc takes DevicePoints (device pointers only)")
+        import torch
+        b, e = self._range(model, scene, tau_begin, tau_end)
+        n, M = e - b, int(model.t.shape[0])
+        keep = []
+        pm, ps = _points(model, keep), _points(scene, keep)
+        d = model.xy.device
+        if out is None:
+            out = dict(energy32=torch.empty(n, dtype=torch.float32, device=d),
+                       energy64=torch.empty(n, dtype=torch.float64, device=d),
+                       energy_u64=torch.empty(n, dtype=torch.float64, device=d),
+                       assign=torch.empty((n, M), dtype=torch.int32, device=d))
+        pp = _params(params, True)
+        _check(self._lib.stm_match_noalloc(self.handle, ctypes.byref(pm), ctypes.byref(ps),
+                                           ctypes.byref(pp), b, e, _ptr(out["energy32"]),
+                                           _ptr(out["energy64"]), _ptr(out["energy_u64"]),
+                                           _ptr(out["assign"]), _stream()))
         out["tau_begin"], out["tau_end"] = b, e
         return out
 

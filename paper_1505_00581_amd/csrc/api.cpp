@@ -102,7 +102,7 @@ int stage(stm_ctx* ctx, DevBuf& b, const T* host, size_t count, hipStream_t st) 
 }
 
 int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_params* p,
-            void* hip_stream, Prepared& out) {
+            void* hip_stream, Prepared& out, const FixedPrep* fixed) {
   int rc = check_shapes(m, s, p);
   if (rc) return rc;
   if (!(p->flags & STM_DEVICE_PTRS)) {
@@ -118,11 +118,18 @@ int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_pa
   if (out.device) {
     out.m = {reinterpret_cast<const float2*>(m->xy), m->t, m->desc, M};
     out.s = {reinterpret_cast<const float2*>(s->xy), s->t, s->desc, nullptr, S, F, D};
-    if ((rc = grow(ctx, ctx->val, 2 * sizeof(int32_t), out.st))) return rc;
-    STM_HIP(hipMemsetAsync(ctx->val.p, 0, 2 * sizeof(int32_t), out.st));
-    STM_HIP(stm::launch_validate(out.m, out.s, static_cast<int32_t*>(ctx->val.p), out.st));
+    int32_t* val = nullptr;
+    if (fixed) {
+      val = fixed->val;
+      STM_HIP(stm::launch_fill_i32(val, 2, 0, out.st));
+    } else {
+      if ((rc = grow(ctx, ctx->val, 2 * sizeof(int32_t), out.st))) return rc;
+      val = static_cast<int32_t*>(ctx->val.p);
+      STM_HIP(hipMemsetAsync(val, 0, 2 * sizeof(int32_t), out.st));
+    }
+    STM_HIP(stm::launch_validate(out.m, out.s, val, out.st));
     int32_t hv[2] = {0, 0};
-    STM_HIP(hipMemcpyAsync(hv, ctx->val.p, sizeof(hv), hipMemcpyDeviceToHost, out.st));
+    STM_HIP(hipMemcpyAsync(hv, val, sizeof(hv), hipMemcpyDeviceToHost, out.st));
     STM_HIP(hipStreamSynchronize(out.st));
     if (hv[0]) return fail(STM_EINVAL, bit_message(hv[0]));
     out.span = hv[1];
@@ -139,30 +146,45 @@ int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_pa
     out.s = {static_cast<const float2*>(ctx->sxy.p), static_cast<const int32_t*>(ctx->st.p),
              static_cast<const float*>(ctx->sdesc.p), nullptr, S, F, D};
   }
-  if ((rc = grow(ctx, ctx->fstart, ((size_t)F + 1) * sizeof(int32_t), out.st))) return rc;
-  STM_HIP(stm::launch_fstart(out.s.t, S, F, static_cast<int32_t*>(ctx->fstart.p), out.st));
-  out.s.fstart = static_cast<const int32_t*>(ctx->fstart.p);
+  int32_t* fst = nullptr;
+  if (fixed) {
+    fst = fixed->fstart;
+  } else {
+    if ((rc = grow(ctx, ctx->fstart, ((size_t)F + 1) * sizeof(int32_t), out.st))) return rc;
+    fst = static_cast<int32_t*>(ctx->fstart.p);
+  }
+  STM_HIP(stm::launch_fstart(out.s.t, S, F, fst, out.st));
+  out.s.fstart = fst;
   // a window wider than the scene adds only empty frames
   out.sp = {p->T, std::min(p->window, F), p->k_max, (p->flags & STM_K_DENSITY) ? 1 : 0};
   return STM_OK;
 }
 
-int unary_table(stm_ctx* ctx, const Prepared& pr, float* U) {
+int unary_table(stm_ctx* ctx, const Prepared& pr, float* U, const Bf16Bufs* fixed) {
   if (!pr.bf16) {
     STM_HIP(stm::launch_unary_f32(pr.m, pr.s, U, pr.st));
     return STM_OK;
   }
   const int M = pr.m.M, S = pr.s.S, dim = pr.s.dim;
-  const int Mp = (M + 15) / 16 * 16, Sp = (S + 255) / 256 * 256, dp = stm::bf16_padded_dim(dim);
-  int rc;
-  if ((rc = grow(ctx, ctx->fb, (size_t)Mp * dp * 2, pr.st))) return rc;
-  if ((rc = grow(ctx, ctx->fn, (size_t)Mp * sizeof(float), pr.st))) return rc;
-  if ((rc = grow(ctx, ctx->gb, (size_t)Sp * dp * 2, pr.st))) return rc;
-  if ((rc = grow(ctx, ctx->gn, (size_t)Sp * sizeof(float), pr.st))) return rc;
-  uint16_t* fb = static_cast<uint16_t*>(ctx->fb.p);
-  uint16_t* gb = static_cast<uint16_t*>(ctx->gb.p);
-  float* fn = static_cast<float*>(ctx->fn.p);
-  float* gn = static_cast<float*>(ctx->gn.p);
+  const int Mp = bf16_rows_model(M), Sp = bf16_rows_scene(S), dp = stm::bf16_padded_dim(dim);
+  uint16_t *fb, *gb;
+  float *fn, *gn;
+  if (fixed && fixed->fb) {
+    fb = fixed->fb;
+    fn = fixed->fn;
+    gb = fixed->gb;
+    gn = fixed->gn;
+  } else {
+    int rc;
+    if ((rc = grow(ctx, ctx->fb, (size_t)Mp * dp * 2, pr.st))) return rc;
+    if ((rc = grow(ctx, ctx->fn, (size_t)Mp * sizeof(float), pr.st))) return rc;
+    if ((rc = grow(ctx, ctx->gb, (size_t)Sp * dp * 2, pr.st))) return rc;
+    if ((rc = grow(ctx, ctx->gn, (size_t)Sp * sizeof(float), pr.st))) return rc;
+    fb = static_cast<uint16_t*>(ctx->fb.p);
+    gb = static_cast<uint16_t*>(ctx->gb.p);
+    fn = static_cast<float*>(ctx->fn.p);
+    gn = static_cast<float*>(ctx->gn.p);
+  }
   STM_HIP(stm::launch_to_bf16(pr.m.desc, M, dim, Mp, fb, fn, pr.st));
   STM_HIP(stm::launch_to_bf16(pr.s.desc, S, dim, Sp, gb, gn, pr.st));
   STM_HIP(stm::launch_unary_bf16(fb, fn, M, gb, gn, S, dim, U, pr.st));
@@ -174,6 +196,59 @@ int check_range(const Prepared& pr, int32_t tau_begin, int32_t tau_end) {
   if (tau_begin < 0 || tau_end < tau_begin || tau_end > n_off)
     return fail(STM_EINVAL, "offset range [" + std::to_string(tau_begin) + ", " +
                                 std::to_string(tau_end) + ") outside [0, " + std::to_string(n_off) + ")");
+  return STM_OK;
+}
+
+int match_kernels(stm_ctx* ctx, const Prepared& pr, const stm_params* params, int32_t tau_begin, int n_tau,
+                  float* d_e32, double* d_e64, double* d_eu, int32_t* d_as, const MatchScratch& sc, bool timed) {
+  const int M = pr.m.M;
+  const hipStream_t st = pr.st;
+  int rc;
+  STM_HIP(stm::launch_model_angles(pr.m, sc.theta, st));
+  if ((rc = unary_table(ctx, pr, sc.U, &sc.bf))) return rc;
+  for (int c0 = 0; c0 < n_tau; c0 += sc.chunk) {
+    const int nc = std::min(sc.chunk, n_tau - c0);
+    stm::DPLaunch a;
+    a.m = pr.m;
+    a.s = pr.s;
+    a.sp = pr.sp;
+    a.U = sc.U;
+    a.theta = sc.theta;
+    a.lambda1 = static_cast<float>(params->lambda1);
+    a.lambda2 = static_cast<float>(params->lambda2);
+    a.w = static_cast<float>(params->lambda2 * params->lambda3);
+    a.dummy = dummy_on(params) ? 1 : 0;
+    a.cw = dummy_cost32(params);
+    a.packed = !a.dummy && sparse_scene(pr.s.S, pr.s.F) ? 1 : 0;
+    a.tau0 = tau_begin + c0;
+    a.n_tau = nc;
+    a.vt = sc.vt;
+    a.e32 = d_e32 + c0;
+    a.last2 = sc.last2;
+    a.degen = sc.degen;
+    a.waves = ctx->dp_waves;
+    if (timed && ctx->prof) {
+      if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
+        for (int q = 0; q < 2; ++q) {
+          hipEvent_t ev;
+          STM_HIP(hipEventCreate(&ev));
+          ctx->prof_ev.push_back(ev);
+        }
+      }
+      STM_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used], st));
+      STM_HIP(stm::launch_dp_fast(a, st));
+      STM_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used + 1], st));
+      ctx->prof_used += 2;
+      ctx->prof_matchings += nc;
+    } else {
+      STM_HIP(stm::launch_dp_fast(a, st));
+    }
+    STM_HIP(stm::launch_dp_degenerate(a, st));
+    STM_HIP(stm::launch_backtrack(a, d_as + (size_t)c0 * M, st));
+    STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp.T, params->lambda1, params->lambda2,
+                                params->lambda3, w_dummy_of(params), d_as + (size_t)c0 * M, nc,
+                                d_e64 ? d_e64 + c0 : nullptr, d_eu ? d_eu + c0 : nullptr, st));
+  }
   return STM_OK;
 }
 
@@ -194,6 +269,9 @@ int stm_create(stm_ctx** out, int hip_device) {
   stm_ctx* c = new (std::nothrow) stm_ctx();
   if (!c) return fail(STM_ENOMEM, "host allocation failed");
   c->device = hip_device;
+  // the fixed scratch of stm_match_noalloc on this device; a failed lookup is
+  // reported by that entry point only
+  (void)noalloc_init(hip_device);
   *out = c;
   return STM_OK;
 }
@@ -247,7 +325,7 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
   const int n_tau = tau_end - tau_begin;
   if (n_tau == 0) return STM_OK;
   if (!energy32 || !assign) return fail(STM_EINVAL, "energy32 and assign are required");
-  const int M = pr.m.M, S = pr.s.S, K = pr.sp.K;
+  const int M = pr.m.M, S = pr.s.S;
   const hipStream_t st = pr.st;
 
   // outputs: caller's device buffers, or staging for host pointers
@@ -270,61 +348,22 @@ int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
     }
   }
 
-  // model angles and the unary table (Section 3.3)
+  // model angles, the unary table (Section 3.3) and the recursion's scratch,
+  // the value tables in chunks of offsets bounded by vt_chunk_bytes
+  MatchScratch sc;
   if ((rc = grow(ctx, ctx->theta, (size_t)M * sizeof(float2), st))) return rc;
-  STM_HIP(stm::launch_model_angles(pr.m, static_cast<float2*>(ctx->theta.p), st));
   if ((rc = grow(ctx, ctx->U, (size_t)M * S * sizeof(float), st))) return rc;
-  if ((rc = unary_table(ctx, pr, static_cast<float*>(ctx->U.p)))) return rc;
-
-  // the recursion, in chunks of offsets bounded by the value-table scratch
-  const size_t per_tau = (size_t)(M - 2) * vt_side(params) * vt_side(params) * sizeof(float);
-  int chunk = static_cast<int>(std::min<size_t>(n_tau, std::max<size_t>(1, ctx->vt_chunk_bytes / per_tau)));
-  if ((rc = grow(ctx, ctx->vt, per_tau * chunk, st))) return rc;
-  if ((rc = grow(ctx, ctx->last2, (size_t)chunk * sizeof(int2), st))) return rc;
-  if ((rc = grow(ctx, ctx->degen, (size_t)chunk * sizeof(int32_t), st))) return rc;
-  for (int c0 = 0; c0 < n_tau; c0 += chunk) {
-    const int nc = std::min(chunk, n_tau - c0);
-    stm::DPLaunch a;
-    a.m = pr.m;
-    a.s = pr.s;
-    a.sp = pr.sp;
-    a.U = static_cast<const float*>(ctx->U.p);
-    a.theta = static_cast<const float2*>(ctx->theta.p);
-    a.lambda1 = static_cast<float>(params->lambda1);
-    a.lambda2 = static_cast<float>(params->lambda2);
-    a.w = static_cast<float>(params->lambda2 * params->lambda3);
-    a.dummy = dummy_on(params) ? 1 : 0;
-    a.cw = dummy_cost32(params);
-    a.packed = !a.dummy && sparse_scene(pr.s.S, pr.s.F) ? 1 : 0;
-    a.tau0 = tau_begin + c0;
-    a.n_tau = nc;
-    a.vt = static_cast<float*>(ctx->vt.p);
-    a.e32 = d_e32 + c0;
-    a.last2 = static_cast<int2*>(ctx->last2.p);
-    a.degen = static_cast<int32_t*>(ctx->degen.p);
-    a.waves = ctx->dp_waves;
-    if (ctx->prof) {
-      if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
-        for (int q = 0; q < 2; ++q) {
-          hipEvent_t ev;
-          STM_HIP(hipEventCreate(&ev));
-          ctx->prof_ev.push_back(ev);
-        }
-      }
-      STM_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used], st));
-      STM_HIP(stm::launch_dp_fast(a, st));
-      STM_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used + 1], st));
-      ctx->prof_used += 2;
-      ctx->prof_matchings += nc;
-    } else {
-      STM_HIP(stm::launch_dp_fast(a, st));
-    }
-    STM_HIP(stm::launch_dp_degenerate(a, st));
-    STM_HIP(stm::launch_backtrack(a, d_as + (size_t)c0 * M, st));
-    STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp.T, params->lambda1, params->lambda2,
-                                params->lambda3, w_dummy_of(params), d_as + (size_t)c0 * M, nc,
-                                d_e64 ? d_e64 + c0 : nullptr, d_eu ? d_eu + c0 : nullptr, st));
-  }
+  const size_t per_tau = vt_bytes_per_offset(M, params);
+  sc.chunk = static_cast<int>(std::min<size_t>(n_tau, std::max<size_t>(1, ctx->vt_chunk_bytes / per_tau)));
+  if ((rc = grow(ctx, ctx->vt, per_tau * sc.chunk, st))) return rc;
+  if ((rc = grow(ctx, ctx->last2, (size_t)sc.chunk * sizeof(int2), st))) return rc;
+  if ((rc = grow(ctx, ctx->degen, (size_t)sc.chunk * sizeof(int32_t), st))) return rc;
+  sc.theta = static_cast<float2*>(ctx->theta.p);
+  sc.U = static_cast<float*>(ctx->U.p);
+  sc.vt = static_cast<float*>(ctx->vt.p);
+  sc.last2 = static_cast<int2*>(ctx->last2.p);
+  sc.degen = static_cast<int32_t*>(ctx->degen.p);
+  if ((rc = match_kernels(ctx, pr, params, tau_begin, n_tau, d_e32, d_e64, d_eu, d_as, sc, true))) return rc;
 
   if (!pr.device) {
     STM_HIP(hipMemcpyAsync(energy32, d_e32, (size_t)n_tau * sizeof(float), hipMemcpyDeviceToHost, st));

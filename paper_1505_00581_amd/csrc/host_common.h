@@ -99,17 +99,69 @@ struct Prepared {
   bool bf16 = false;
 };
 
+// Fixed device buffers for prepare() instead of the context's: the
+// validation words (2 int32, cleared here by a fill kernel) and the frame
+// index (n_frames + 1 int32).
+struct FixedPrep {
+  int32_t* val = nullptr;
+  int32_t* fstart = nullptr;
+};
+
 int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_params* p,
-            void* hip_stream, Prepared& out);
+            void* hip_stream, Prepared& out, const FixedPrep* fixed = nullptr);
+
+// Buffers of the split-precision unary table: BF16 descriptors (rows padded to
+// the MFMA tile) and their squared norms.  All null: the context's, grown on
+// demand.
+struct Bf16Bufs {
+  uint16_t* fb = nullptr;
+  float* fn = nullptr;
+  uint16_t* gb = nullptr;
+  float* gn = nullptr;
+};
+// Rows and padded dimension of the BF16 copies of M model and S scene rows.
+inline int bf16_rows_model(int M) { return (M + 15) / 16 * 16; }
+inline int bf16_rows_scene(int S) { return (S + 255) / 256 * 256; }
+
 // The unary table U [M][S] (Section 3.3), FP32 direct or BF16 on MFMA.
-int unary_table(stm_ctx* ctx, const Prepared& pr, float* U);
+int unary_table(stm_ctx* ctx, const Prepared& pr, float* U, const Bf16Bufs* fixed = nullptr);
 int check_range(const Prepared& pr, int32_t tau_begin, int32_t tau_end);
+
+// Device scratch of one exact matching call: the model angles [M], the unary
+// table [M][S], the BF16 buffers (split precision), and for `chunk` offsets
+// at a time the value tables (per offset (M - 2) x side^2 floats), the last
+// state pairs and the degenerate flags.
+struct MatchScratch {
+  float2* theta = nullptr;
+  float* U = nullptr;
+  Bf16Bufs bf;
+  float* vt = nullptr;
+  int2* last2 = nullptr;
+  int32_t* degen = nullptr;
+  int chunk = 0;
+};
+
+// The kernels of stm_match over offsets [tau_begin, tau_begin + n_tau) on
+// prepared inputs and device outputs: model angles, unary table, then per
+// chunk of offsets the recursion (fast and degenerate variants),
+// backtracking and the FP64 re-score.  `timed`: HIP events around the fast
+// recursion launches when the context's profiling is on.
+int match_kernels(stm_ctx* ctx, const Prepared& pr, const stm_params* p, int32_t tau_begin, int n_tau,
+                  float* e32, double* e64, double* eu, int32_t* assign, const MatchScratch& sc, bool timed);
+
+
+// Looks up the device address of stm_match_noalloc's fixed array on the
+// current device `device`, once per device (at context creation).
+int noalloc_init(int device);
 
 // Dummy assignments (STM_DUMMY): W^d for the FP64 re-score (0 when off), and
 // the value-table side K (+1 for the dummy state).
 inline bool dummy_on(const stm_params* p) { return (p->flags & STM_DUMMY) != 0; }
 inline double w_dummy_of(const stm_params* p) { return dummy_on(p) ? p->w_dummy : 0.0; }
 inline long long vt_side(const stm_params* p) { return (long long)p->k_max + (dummy_on(p) ? 1 : 0); }
+inline size_t vt_bytes_per_offset(int M, const stm_params* p) {
+  return (size_t)(M - 2) * vt_side(p) * vt_side(p) * sizeof(float);
+}
 // Packed schedules for sparse scenes (at most 3 points per frame on average,
 // as interest points usually are), where a frame group holds a few cells.
 inline bool sparse_scene(int32_t S, int32_t F) { return (long long)S <= 3LL * F; }

@@ -1,0 +1,118 @@
+"""stm_match_noalloc (the exact matching on the library's fixed device array,
+for callers that cannot allocate) against stm_match through the C ABI.
+
+Both run the same kernels on the same inputs, so the bar is bit-identical
+energies (FP32 and the FP64 re-score) and assignments.  Each case makes two
+calls in a row on the shared array, the second with a smaller input, so a
+call that read the previous call's leftovers would show.  Sizes beyond the
+array and host pointers are rejected before any kernel runs.
+"""
+import ctypes
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1505_00581_amd as stm
+from paper_1505_00581_amd import _binding as B
+from paper_1505_00581_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = stm.Context(0)
+    yield c
+    c.close()
+
+
+def _cut_scene(s, n_frames):
+    keep = s.t < n_frames
+    return synth.Points(s.xy[keep].copy(), s.t[keep].copy(), s.desc[keep].copy(), n_frames)
+
+
+def _same(ctx, m, s, p, tau=(None, None)):
+    dm, ds = stm.DevicePoints.from_host(m), stm.DevicePoints.from_host(s)
+    ref = ctx.match(dm, ds, p, *tau)
+    got = ctx.match_noalloc(dm, ds, p, *tau)
+    torch.cuda.synchronize()
+    for k in ("energy32", "energy64", "energy_u64", "assign"):
+        a, b = ref[k], got[k]
+        assert a.shape == b.shape, k
+        # NaN never occurs; +inf rows (infeasible offsets) compare equal
+        assert torch.equal(a, b), f"{k} differs from stm_match"
+    return int(ref["energy32"].numel()), int(torch.isfinite(ref["energy32"]).sum())
+
+
+@pytest.mark.parametrize("variant", ["plain", "dummy", "bf16"])
+def test_noalloc_equals_stm_match_two_calls(ctx, variant):
+    w = synth.config1(0)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    if variant == "dummy":
+        p = dataclasses.replace(p, w_dummy=0.5)
+    elif variant == "bf16":
+        p = dataclasses.replace(p, unary_bf16=True)
+    say(f"noalloc {variant}: plain workload, all offsets")
+    n1, f1 = _same(ctx, m, s, p)
+    # second call: a smaller model and scene
+    m2 = synth.Points(m.xy[:9].copy(), m.t[:9].copy(), m.desc[:9].copy())
+    s2 = _cut_scene(s, 50)
+    say(f"noalloc {variant}: smaller model (9 points) and scene (50 frames)")
+    n2, f2 = _same(ctx, m2, s2, p)
+    assert n2 < n1 and f1 > 0 and f2 > 0
+
+
+def test_noalloc_chunks_realistic_sizes(ctx):
+    # a 1500-frame scene of ~33.6k points: the array holds the unary table and
+    # ~150 offsets of value tables, so 600 offsets run in several chunks
+    w = synth.config2(0, n_models=2)
+    s, p = w.scenes[0], w.params
+    m = max(w.models, key=lambda q: q.n)
+    per_tau = (m.n - 2) * p.k_max * p.k_max * 4
+    assert m.n * s.n * 4 + 2 * per_tau < stm.STM_NOALLOC_SCRATCH_BYTES
+    assert 600 * per_tau > stm.STM_NOALLOC_SCRATCH_BYTES - m.n * s.n * 4  # more than one chunk
+    say(f"noalloc realistic: M={m.n}, S={s.n}, offsets 0..600")
+    n1, f1 = _same(ctx, m, s, p, (0, 600))
+    mm = min(w.models, key=lambda q: q.n)
+    say(f"noalloc realistic: M={mm.n}, offsets 100..160")
+    n2, f2 = _same(ctx, mm, s, p, (100, 160))
+    assert n2 < n1 and f1 > 0
+
+
+def test_noalloc_rejects_sizes_beyond_the_array(ctx):
+    # M x S x 4 bytes of unary table above the array: refused from the sizes
+    # alone, before any kernel reads the inputs
+    M, S, dim = 100, (stm.STM_NOALLOC_SCRATCH_BYTES // (100 * 4)) + 1, 2
+    dev = "cuda"
+    model = stm.DevicePoints(torch.zeros((M, 2), device=dev), torch.arange(M, dtype=torch.int32, device=dev),
+                             torch.zeros((M, dim), device=dev), 0)
+    scene = stm.DevicePoints(torch.zeros((S, 2), device=dev), torch.zeros(S, dtype=torch.int32, device=dev),
+                             torch.zeros((S, dim), device=dev), 200)
+    p = synth.Params(k_max=16, window=2)
+    with pytest.raises(stm.StmError) as ei:
+        ctx.match_noalloc(model, scene, p, 0, 1)
+    assert ei.value.code == stm.STM_EINVAL and "STM_NOALLOC_SCRATCH_BYTES" in str(ei.value)
+    # and a following call of ordinary size still works
+    w = synth.config1(1)
+    _same(ctx, w.models[0], w.scenes[0], w.params)
+
+
+def test_noalloc_rejects_host_pointers(ctx):
+    w = synth.config1(0)
+    m, s, p = w.models[0], w.scenes[0], w.params
+    lib = stm.load()
+    keep = []
+    pm, ps = B._points(m, keep), B._points(s, keep)
+    pp = B._params(p, False)
+    e = np.zeros(1, np.float32)
+    a = np.zeros((1, m.n), np.int32)
+    rc = lib.stm_match_noalloc(ctx.handle, ctypes.byref(pm), ctypes.byref(ps), ctypes.byref(pp), 0, 1,
+                               e.ctypes.data, None, None, a.ctypes.data, None)
+    assert rc == stm.STM_EINVAL and "device pointers" in lib.stm_last_error().decode()
