@@ -95,6 +95,15 @@ extern "C" {
                                  plans (stm_plan_run) take it; the pruned entry
                                  points return STM_EUNSUPPORTED.                       */
 
+#define STM_CLOSENESS_SPAN 0x10u  /* temporal closeness read from the loop bounds of
+                                 Section 3.4 (Eq. 14): the first and last scene
+                                 frames of every triangle (z_{i-2}, z_{i-1}, z_i)
+                                 lie less than T apart, and consecutive points keep
+                                 causality (Eq. 7) only, instead of Eq. 8's limit on
+                                 consecutive points.  Consecutive points are then at
+                                 most T - 2 frames apart.  No effect with T <= 0;
+                                 not with STM_DUMMY (STM_EUNSUPPORTED).             */
+
 /* Node id of a dummy assignment in assignment rows (STM_DUMMY); -1 marks the
  * rows of infeasible offsets. */
 #define STM_DUMMY_NODE (-2)
@@ -127,7 +136,7 @@ typedef struct {
   int32_t window;       /* candidate window half-width in frames, >= 0             */
   int32_t k_max;        /* candidate cap K, 1..STM_K_LIMIT                         */
   uint32_t flags;       /* STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY |
-                           STM_DUMMY                                                */
+                           STM_DUMMY | STM_CLOSENESS_SPAN                          */
   double w_dummy;       /* W^d, the unary cost of a dummy (Eq. 2), finite, >= 0;
                            read only with STM_DUMMY                                 */
 } stm_params;

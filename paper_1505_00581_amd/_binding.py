@@ -23,6 +23,7 @@ STM_DEVICE_PTRS = 0x1
 STM_UNARY_BF16 = 0x2
 STM_K_DENSITY = 0x4
 STM_DUMMY = 0x8
+STM_CLOSENESS_SPAN = 0x10
 STM_DUMMY_NODE = -2  # assignment value of a dummy (unmatched model point)
 STM_UNCHAINED_NODE = -3  # assignment value of a point in no kept chain (stm_match_chains)
 STM_NOALLOC_SCRATCH_BYTES = 256 << 20  # fixed device array of stm_match_noalloc
@@ -187,7 +188,8 @@ def _params(params, device: bool) -> _Params:
     wd = getattr(params, "w_dummy", None)
     flags = ((STM_DEVICE_PTRS if device else 0) | (STM_K_DENSITY if params.k_density else 0)
              | (STM_UNARY_BF16 if getattr(params, "unary_bf16", False) else 0)
-             | (STM_DUMMY if wd is not None else 0))
+             | (STM_DUMMY if wd is not None else 0)
+             | (STM_CLOSENESS_SPAN if getattr(params, "closeness_span", False) else 0))
     return _Params(params.lambda1, params.lambda2, params.lambda3, params.T, params.window,
                    params.k_max, flags, 0.0 if wd is None else float(wd))
 

@@ -59,8 +59,10 @@ int check_shapes(const stm_points* m, const stm_points* s, const stm_params* p) 
   if (p->window < 0) return fail(STM_EINVAL, "window < 0");
   if (!finite_lambda(p->lambda1) || !finite_lambda(p->lambda2) || !finite_lambda(p->lambda3))
     return fail(STM_EINVAL, "lambdas must be finite and >= 0");
-  if (p->flags & ~(STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY | STM_DUMMY))
+  if (p->flags & ~(STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY | STM_DUMMY | STM_CLOSENESS_SPAN))
     return fail(STM_EUNSUPPORTED, "unknown flag");
+  if ((p->flags & STM_DUMMY) && (p->flags & STM_CLOSENESS_SPAN))
+    return fail(STM_EUNSUPPORTED, "the span reading of closeness is not defined with dummies");
   if ((p->flags & STM_DUMMY) && !finite_lambda(p->w_dummy))
     return fail(STM_EINVAL, "w_dummy must be finite and >= 0");
   return STM_OK;
@@ -156,7 +158,7 @@ int prepare(stm_ctx* ctx, const stm_points* m, const stm_points* s, const stm_pa
   STM_HIP(stm::launch_fstart(out.s.t, S, F, fst, out.st));
   out.s.fstart = fst;
   // a window wider than the scene adds only empty frames
-  out.sp = {p->T, std::min(p->window, F), p->k_max, (p->flags & STM_K_DENSITY) ? 1 : 0};
+  out.sp = search_params(p, std::min(p->window, F));
   return STM_OK;
 }
 
@@ -245,7 +247,7 @@ int match_kernels(stm_ctx* ctx, const Prepared& pr, const stm_params* params, in
     }
     STM_HIP(stm::launch_dp_degenerate(a, st));
     STM_HIP(stm::launch_backtrack(a, d_as + (size_t)c0 * M, st));
-    STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp.T, params->lambda1, params->lambda2,
+    STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp, params->lambda1, params->lambda2,
                                 params->lambda3, w_dummy_of(params), d_as + (size_t)c0 * M, nc,
                                 d_e64 ? d_e64 + c0 : nullptr, d_eu ? d_eu + c0 : nullptr, st));
   }

@@ -141,6 +141,10 @@ __device__ __forceinline__ float relax(float v, float A, float C, float bm, floa
                                        bool same_rc, float w) {
   float x1, x2;
   if (DEGEN) {
+    // +inf marks a triangle the span reading of closeness excludes (the fast
+    // variant reaches +inf or NaN through the arithmetic, both ignored by the
+    // minimum)
+    if (C == __builtin_inff()) return __builtin_inff();
     x1 = (same_rc || isnan(A)) ? th.x : A + bm;
     x2 = (same_rc || isnan(C)) ? th.y : C + be;
   } else {
@@ -417,7 +421,8 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int M = a.m.M;
-  const int T = a.sp.T;
+  const int T = pair_limit(a.sp);   // consecutive points
+  const int TS = span_limit(a.sp);  // first and last points of a triangle (span reading)
   const int Kc = a.sp.K;
   const int VS = a.vs;
   const int tm0 = ro(a.m.t);
@@ -550,10 +555,16 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
     {
       // the (a_{i-2}, a_i) direction of row k, column c; a pair is used only
       // if some z_{i-1} fits strictly between its frames and within T of
-      // both: 2 <= t_i - t_{i-2} <= 2T - 2
+      // both: 2 <= t_i - t_{i-2} <= 2T - 2.  Under the span reading a pair
+      // whose frames are TS or more apart gets +inf, which takes its terms
+      // out of every minimum.
       const auto direction = [&](int k, int c, int tc, float2 pc) {
         const int gap = tc - sh.ctt[s2][k];
         if (gap >= 2 && (T <= 0 || gap <= 2 * T - 2)) {
+          if (TS > 0 && gap >= TS) {
+            sh.ct[k * KL + c] = INF;
+            return;
+          }
           const float2 pk = sh.cxy[s2][k];
           if (!DEGEN && pk.x == pc.x && pk.y == pc.y) sh.flag = 1;
           sh.ct[k * KL + c] = neg_dir<DEGEN>(pk, pc);
@@ -781,6 +792,7 @@ template <bool DEGEN, bool DUMMY = false>
 __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int c, int lane,
                                int32_t* out) {
   const int M = a.m.M, Kc = a.sp.K, VS = a.vs;
+  const int T = pair_limit(a.sp), TS = span_limit(a.sp);
   const float INF = __builtin_inff();
   auto node_of = [&](const Cands& q, int idx) { return DUMMY && idx == kEps ? kDummyNode : q.node(idx); };
   Cands cc = cands_of(a, M - 1);
@@ -805,17 +817,19 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
       if (DUMMY) teps = vp[Kc * VS + r];
       if (DUMMY && c == kEps) {
         // V_i(r, eps) = l1 W^d + min(V_{i-1}(eps, r), min_k V_{i-1}(k, r))
-        if (lane < nk && admissible(ro(a.s.t + ck.node(lane)), tr, a.sp.T)) tot = vp[lane * VS + r];
+        if (lane < nk && admissible(ro(a.s.t + ck.node(lane)), tr, T)) tot = vp[lane * VS + r];
       } else {
         const int nc = cc.node(c);
         const float2 xa = ro(a.s.xy + nc);
+        const int tc = ro(a.s.t + nc);
         const float2 th = ro(a.theta + i);
         const bool same = xa.x == xr.x && xa.y == xr.y;
         float bm, be;
         cell_brackets(th, -neg_dir<DEGEN>(xr, xa), bm, be);
         if (lane < nk) {
           const int nkn = ck.node(lane);
-          if (admissible(ro(a.s.t + nkn), tr, a.sp.T)) {
+          const int tk = ro(a.s.t + nkn);
+          if (admissible(tk, tr, T) && span_ok(tk, tc, TS)) {
             const float2 pk = ro(a.s.xy + nkn);
             const float v = vp[lane * VS + r];
             tot = relax<DEGEN>(v, neg_dir<DEGEN>(pk, xr), neg_dir<DEGEN>(pk, xa), bm, be, th, same, a.w);
@@ -1047,10 +1061,11 @@ __device__ __forceinline__ double wrap64(double x) {
 // The descriptor distances are taken four points at a time, 16 lanes per
 // point striding its descriptor (coalesced reads; partial sums joined by a
 // 16-lane tree); the triangle terms one point per lane.
-__device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, double l1, double l2,
+__device__ void rescore_wave(const ModelView& m, const SceneView& s, const SearchParams& sp, double l1, double l2,
                              double l3, double wd, const int32_t* __restrict__ z, long long tl,
                              double* __restrict__ e64, double* __restrict__ eu64) {
   const int lane = threadIdx.x & 63;
+  const int32_t T = pair_limit(sp), TS = span_limit(sp);
   const int M = m.M, dim = s.dim;
   const double inf = __builtin_inf();
   if (ro(z) == -1) {
@@ -1083,6 +1098,8 @@ __device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, 
     const int nj = i >= 1 ? ro(z + (i - 1)) : kDummyNode;
     const int nk = i >= 2 ? ro(z + (i - 2)) : kDummyNode;
     if (n != kDummyNode && nj != kDummyNode && !admissible(ro(s.t + nj), ro(s.t + n), T)) bad = 1;
+    // the span reading (no dummies): the triangle's first and last frames
+    if (TS > 0 && i >= 2 && !span_ok(ro(s.t + ro(z + (i - 2))), ro(s.t + n), TS)) bad = 1;
     if (i >= 2 && (n == kDummyNode || nj == kDummyNode || nk == kDummyNode)) {
       // the Delta terms whose points are both matched; no D^g
       if (n != kDummyNode && nj != kDummyNode) {
@@ -1118,23 +1135,23 @@ __device__ void rescore_wave(const ModelView& m, const SceneView& s, int32_t T, 
   }
 }
 
-__global__ __launch_bounds__(64) void k_rescore(ModelView m, SceneView s, int32_t T, double l1, double l2,
+__global__ __launch_bounds__(64) void k_rescore(ModelView m, SceneView s, SearchParams sp, double l1, double l2,
                                                double l3, double wd, const int32_t* __restrict__ assign,
                                                double* __restrict__ e64, double* __restrict__ eu64) {
   const int tl = blockIdx.x;
-  rescore_wave(m, s, T, l1, l2, l3, wd, assign + (long long)tl * m.M, tl, e64, eu64);
+  rescore_wave(m, s, sp, l1, l2, l3, wd, assign + (long long)tl * m.M, tl, e64, eu64);
 }
 
 __global__ __launch_bounds__(64) void k_rescore_batch(const PairDev* __restrict__ pairs,
                                                      const int2* __restrict__ items, int n_items,
-                                                     int32_t T, double l1, double l2, double l3, double wd,
+                                                     SearchParams sp, double l1, double l2, double l3, double wd,
                                                      const int32_t* __restrict__ assign,
                                                      double* __restrict__ e64, double* __restrict__ eu64) {
   const int item = blockIdx.x;
   if (item >= n_items) return;
   const int2 it = items[item];
   const PairDev pd = pairs[it.x];
-  rescore_wave(pd.m, pd.s, T, l1, l2, l3, wd, assign + pd.assign0 + (long long)it.y * pd.m.M,
+  rescore_wave(pd.m, pd.s, sp, l1, l2, l3, wd, assign + pd.assign0 + (long long)it.y * pd.m.M,
                pd.row0 + it.y, e64, eu64);
 }
 
@@ -1230,11 +1247,11 @@ hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, int32_t T,
+hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, const SearchParams& sp,
                                 double lambda1, double lambda2, double lambda3, double w_dummy,
                                 const int32_t* assign, double* e64, double* eu64, hipStream_t st) {
   if (n_items <= 0 || (!e64 && !eu64)) return hipSuccess;
-  hipLaunchKernelGGL(k_rescore_batch, dim3(n_items), dim3(64), 0, st, pairs, items, n_items, T,
+  hipLaunchKernelGGL(k_rescore_batch, dim3(n_items), dim3(64), 0, st, pairs, items, n_items, sp,
                      lambda1, lambda2, lambda3, w_dummy, assign, e64, eu64);
   return hipGetLastError();
 }
@@ -1245,11 +1262,11 @@ hipError_t launch_backtrack(const DPLaunch& a, int32_t* assign, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_rescore(const ModelView& m, const SceneView& s, int32_t T, double lambda1,
+hipError_t launch_rescore(const ModelView& m, const SceneView& s, const SearchParams& sp, double lambda1,
                           double lambda2, double lambda3, double w_dummy, const int32_t* assign,
                           int32_t n_tau, double* e64, double* eu64, hipStream_t st) {
   if (n_tau <= 0 || (!e64 && !eu64)) return hipSuccess;
-  hipLaunchKernelGGL(k_rescore, dim3(n_tau), dim3(64), 0, st, m, s, T, lambda1, lambda2, lambda3,
+  hipLaunchKernelGGL(k_rescore, dim3(n_tau), dim3(64), 0, st, m, s, sp, lambda1, lambda2, lambda3,
                      w_dummy, assign, e64, eu64);
   return hipGetLastError();
 }

@@ -165,6 +165,12 @@ inline size_t vt_bytes_per_offset(int M, const stm_params* p) {
 // Packed schedules for sparse scenes (at most 3 points per frame on average,
 // as interest points usually are), where a frame group holds a few cells.
 inline bool sparse_scene(int32_t S, int32_t F) { return (long long)S <= 3LL * F; }
+// The kernels' search parameters of a call: closeness, window, cap, density
+// rule and the span reading of closeness.
+inline stm::SearchParams search_params(const stm_params* p, int32_t window) {
+  return stm::SearchParams{p->T, window, p->k_max, (p->flags & STM_K_DENSITY) ? 1 : 0,
+                           (p->flags & STM_CLOSENESS_SPAN) ? 1 : 0};
+}
 // lambda1 * W^d in FP32, the dummy's unary term in the recursion.
 inline float dummy_cost32(const stm_params* p) {
   return dummy_on(p) ? static_cast<float>(p->lambda1 * p->w_dummy) : 0.f;

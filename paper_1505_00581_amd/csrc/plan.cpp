@@ -212,7 +212,7 @@ stm::BatchLaunch plan_launch(stm_plan* p, const stm::PairDev* pairs, const int2*
   b.counter = p->counters;
   b.degen_count = p->counters + 2;
   b.degen_items = p->degen_items;
-  b.sp = {p->params.T, p->params.window, p->params.k_max, (p->params.flags & STM_K_DENSITY) ? 1 : 0};
+  b.sp = stmh::search_params(&p->params, p->params.window);
   b.lambda1 = static_cast<float>(p->params.lambda1);
   b.lambda2 = static_cast<float>(p->params.lambda2);
   b.w = static_cast<float>(p->params.lambda2 * p->params.lambda3);
@@ -262,7 +262,7 @@ int plan_enqueue_run(stm_plan* p, float* e32, double* e64, double* eu, int32_t* 
   if (timed) STM_HIP(hipEventRecord(p->ev_k0, st));
   STM_HIP(stm::launch_dp_persistent(b, p->n_cu * p->wgs_per_cu, st));
   if (timed) STM_HIP(hipEventRecord(p->ev_k1, st));
-  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, p->params.T,
+  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, stmh::search_params(&p->params, p->params.window),
                                     p->params.lambda1, p->params.lambda2, p->params.lambda3,
                                     w_dummy_of(&p->params), assign, e64, eu, st));
   return STM_OK;
@@ -459,8 +459,7 @@ int stm_plan_create(stm_ctx* ctx, const stm_points* models, int32_t n_models, co
     for (int q = 0; q < n_pairs; ++q) p->pair_ms[q] = make_int2(pairs[2 * q], pairs[2 * q + 1]);
     if (!items.empty()) {
       STM_HIP(hipMemcpyAsync(p->items_dev, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, st));
-      const stm::SearchParams sp{p->params.T, p->params.window, p->params.k_max,
-                                 (p->params.flags & STM_K_DENSITY) ? 1 : 0};
+      const stm::SearchParams sp = stmh::search_params(&p->params, p->params.window);
       STM_HIP(stm::launch_item_cost(p->pairs_dev, p->items_dev, p->n_items, sp, cost, st));
       std::vector<long long> hc(items.size());
       STM_HIP(hipMemcpyAsync(hc.data(), cost, hc.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
@@ -681,8 +680,7 @@ int plan_enqueue_pruned(stm_plan* p, stm_pruner* P, int kp, float* e32, double* 
     STM_HIP(stm::launch_project_bf16(p->pr_xs[j], S, dp, p->pr_wb, static_cast<float>(D), nullptr, p->pr_B[j], st));
   }
   // the pruned lists of every pair
-  const stm::SearchParams sp{p->params.T, std::min(p->params.window, 0x3fffffff), p->params.k_max,
-                             (p->params.flags & STM_K_DENSITY) ? 1 : 0};
+  const stm::SearchParams sp = stmh::search_params(&p->params, std::min(p->params.window, 0x3fffffff));
   long long off = 0;
   for (int q = 0; q < p->n_pairs; ++q) {
     const stm::PairDev& d = p->pairs_host[q];
@@ -726,7 +724,7 @@ int plan_enqueue_pruned(stm_plan* p, stm_pruner* P, int kp, float* e32, double* 
   x.list = p->pr_list;
   x.list_count = inf_count;
   STM_HIP(stm::launch_dp_persistent(x, p->n_cu * p->wgs_per_cu, st));
-  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, p->params.T, p->params.lambda1,
+  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, stmh::search_params(&p->params, p->params.window), p->params.lambda1,
                                     p->params.lambda2, p->params.lambda3, w_dummy_of(&p->params), asg, e64,
                                     eu, st));
   return STM_OK;
@@ -1021,7 +1019,7 @@ int stm_plan_run_lists(stm_plan* p, const int32_t* const* cand, const int32_t* c
   if (timed) STM_HIP(hipEventRecord(p->ev_k0, st));
   STM_HIP(stm::launch_dp_persistent(b, p->n_cu * p->wgs_per_cu, st));
   if (timed) STM_HIP(hipEventRecord(p->ev_k1, st));
-  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, p->params.T, p->params.lambda1,
+  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_items, stmh::search_params(&p->params, p->params.window), p->params.lambda1,
                                     p->params.lambda2, p->params.lambda3, w_dummy_of(&p->params), asg, e64, eu,
                                     st));
   STM_HIP(hipEventRecord(p->ev_out, st));

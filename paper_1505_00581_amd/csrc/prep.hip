@@ -151,19 +151,34 @@ __global__ void k_count(ModelView m, SceneView s, SearchParams sp, int32_t tau0,
     __syncthreads();
     if (i >= 1) {
       const int32_t kp = kk[(i - 1) % 3], kc = kk[i % 3];
+      const int32_t T = pair_limit(sp), TS = span_limit(sp);
       // lane = candidate r of point i-1
       if (lane < kp) {
         const int32_t tr = tt[(i - 1) % 3][lane];
+        const int32_t* tcur = tt[i % 3];
         int32_t na = 0;
-        for (int32_t a = 0; a < kc; ++a) na += admissible(tr, tt[i % 3][a], sp.T);
+        for (int32_t a = 0; a < kc; ++a) na += admissible(tr, tcur[a], T);
         dc += kc;
         fc += na;
         if (i >= 2) {
           const int32_t kq = kk[(i - 2) % 3];
-          int32_t nk = 0;
-          for (int32_t q = 0; q < kq; ++q) nk += admissible(tt[(i - 2) % 3][q], tr, sp.T);
+          const int32_t* tprev = tt[(i - 2) % 3];
           dr += (unsigned long long)kq * kc;
-          fr += (unsigned long long)nk * na;
+          if (TS <= 0) {
+            int32_t nk = 0;
+            for (int32_t q = 0; q < kq; ++q) nk += admissible(tprev[q], tr, T);
+            fr += (unsigned long long)nk * na;
+          } else {
+            // span reading: for each admissible predecessor, the admissible
+            // columns less than TS frames after it (frames ascend, so the
+            // bound only moves forward)
+            int32_t a = 0, n_below = 0;
+            for (int32_t q = 0; q < kq; ++q) {
+              if (!admissible(tprev[q], tr, T)) continue;
+              for (; a < kc && tcur[a] - tprev[q] < TS; ++a) n_below += admissible(tr, tcur[a], T);
+              fr += n_below;
+            }
+          }
         }
       }
     }

@@ -298,7 +298,7 @@ int dp_rows(const Prepared& pr, const stm_params* params, stm::DPLaunch b, float
   STM_HIP(stm::launch_dp_fast(b, pr.st));
   STM_HIP(stm::launch_dp_degenerate(b, pr.st));
   STM_HIP(stm::launch_backtrack(b, as, pr.st));
-  STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp.T, params->lambda1, params->lambda2, params->lambda3,
+  STM_HIP(stm::launch_rescore(pr.m, pr.s, pr.sp, params->lambda1, params->lambda2, params->lambda3,
                               w_dummy_of(params), as, b.n_tau,
                               e64, eu, pr.st));
   return STM_OK;

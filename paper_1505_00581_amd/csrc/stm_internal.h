@@ -28,7 +28,21 @@ struct ModelView {
 
 struct SearchParams {
   int32_t T, W, K, kdensity;
+  int32_t span;  // closeness as the span of each triangle (Section 3.4, Eq. 14)
 };
+
+// Closeness limit of consecutive points: T of Eq. 8, or under the span reading
+// T - 1, since a pair inside a triangle whose first and last frames are less
+// than T apart is at most T - 2 frames apart (T = 1, 2: no pair); <= 0: none.
+__host__ __device__ __forceinline__ int32_t pair_limit(const SearchParams& sp) {
+  return sp.span && sp.T > 0 ? (sp.T > 2 ? sp.T - 1 : 1) : sp.T;
+}
+
+// Limit on the first and last frames of a triangle under the span reading
+// (t'(z_i) - t'(z_{i-2}) < limit); 0 when it does not apply.
+__host__ __device__ __forceinline__ int32_t span_limit(const SearchParams& sp) {
+  return sp.span && sp.T > 0 ? sp.T : 0;
+}
 
 // Candidate list of one model point at one offset, as two ascending node
 // ranges: [s1, s1 + k1) then [s2, s2 + k2), with s1 + k1 <= s2.
@@ -139,6 +153,12 @@ __device__ __forceinline__ bool admissible(int32_t tp_prev, int32_t tp_cur, int3
   return tp_prev < tp_cur && (T <= 0 || tp_cur - tp_prev < T);
 }
 
+// The span reading's condition on a triangle's first and last scene frames
+// (limit from span_limit; 0: always true).
+__device__ __forceinline__ bool span_ok(int32_t tp_first, int32_t tp_last, int32_t limit) {
+  return limit <= 0 || tp_last - tp_first < limit;
+}
+
 // Oriented angle at vertex b of the triangle (a, b, c), from ray b->a to ray
 // b->c, in FP64; 0 when a side has zero length (Eq. 6).
 __device__ __forceinline__ double ang64(double ax, double ay, double bx, double by, double cx,
@@ -208,7 +228,7 @@ hipError_t launch_backtrack(const DPLaunch& a, int32_t* assign, hipStream_t st);
 
 // FP64 energy of each assignment row; w_dummy is W^d, the unary cost of a
 // dummy (node id -2 in assign; never present when dummies are off).
-hipError_t launch_rescore(const ModelView& m, const SceneView& s, int32_t T, double lambda1,
+hipError_t launch_rescore(const ModelView& m, const SceneView& s, const SearchParams& sp, double lambda1,
                           double lambda2, double lambda3, double w_dummy, const int32_t* assign,
                           int32_t n_tau, double* e64, double* eu64, hipStream_t st);
 
@@ -269,7 +289,7 @@ hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st);
 // for them when fell is given (rows of the other items are left as they are).
 hipError_t launch_collect_infeasible(const PairDev* pairs, const int2* items, int n_items, const float* e32,
                                      int32_t* list, int32_t* count, int32_t* fell, hipStream_t st);
-hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, int32_t T,
+hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_items, const SearchParams& sp,
                                 double lambda1, double lambda2, double lambda3, double w_dummy,
                                 const int32_t* assign, double* e64, double* eu64, hipStream_t st);
 

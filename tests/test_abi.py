@@ -82,6 +82,13 @@ def test_invalid_inputs_rejected_on_host(mutate, needle):
     assert needle in msg
 
 
+def test_span_with_dummies_unsupported():
+    m, s, p = _good()
+    p.w_dummy, p.closeness_span = 0.5, True
+    rc, msg = _call_match(m, s, p)
+    assert rc == stm.STM_EUNSUPPORTED and "span" in msg
+
+
 def test_short_model_and_dim_mismatch_rejected():
     m, s, p = _good()
     m2 = synth.Points(m.xy[:2].copy(), m.t[:2].copy(), m.desc[:2].copy())
