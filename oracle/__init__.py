@@ -147,6 +147,22 @@ def match_lists(model, scene, params, lists, counts, n_threads: int = 0):
     return dict(energy=e, energy_u=eu, assign=z)
 
 
+def match_trellis(model, scene, params, node_begin: int = 0, node_end=None, n_threads: int = 0):
+    """The paper's own problem (Section 2.2): one trellis in which every model
+    point may take any scene node of the block [node_begin, node_end), under
+    causality and closeness (Eq. 7, 8; the loop bounds of Section 3.4 are a
+    consequence of these, not extra constraints).  The literal recursion on
+    the lists that hold the whole block for every point.  Returns dict(energy,
+    energy_u, assign) with one row."""
+    e = scene.n if node_end is None else int(node_end)
+    b = int(node_begin)
+    assert 0 <= b < e <= scene.n
+    M = model.n
+    lists = np.broadcast_to(np.arange(b, e, dtype=np.int32), (1, M, e - b)).copy()
+    counts = np.full((1, M), e - b, np.int32)
+    return match_lists(model, scene, params, lists, counts, n_threads)
+
+
 def energies(model, scene, params, assign):
     """Literal FP64 energy (Eq. 1) of each assignment row; returns (E, E_U)."""
     lib = _load()

@@ -203,7 +203,7 @@ int32_t oracle_candidates(const problem* p, int32_t tau, int32_t i, int32_t* out
 
 /* ---- the literal backward recursion (Section 2.2) ------------------------- */
 
-/* counts[0..3]: dense cells, feasible cells, dense relaxations, feasible
+/* counts[0..3] (nullable): dense cells, feasible cells, dense relaxations, feasible
  * relaxations.  A cell is a state pair of consecutive points (a_{i-1}, a_i);
  * a relaxation is a triple (a_{i-2}, a_{i-1}, a_i); "feasible" means every
  * consecutive pair in it is admissible. */
@@ -239,14 +239,14 @@ static int match_one(const problem* p, int32_t tau, const int32_t* given, const 
   for (int i = 0; i < M; ++i)
     for (int a = 0; a < nst[i]; ++a) u[(size_t)i * KS + a] = p->lambda1 * unary(p, i, NODE(i, a));
 
-  /* work counts (scene candidates only) */
-  for (int i = 1; i < M; ++i)
+  /* work counts (scene candidates only), when asked for */
+  for (int i = 1; counts && i < M; ++i)
     for (int b = 0; b < cnt[i - 1]; ++b)
       for (int a = 0; a < cnt[i]; ++a) {
         counts[0] += 1;
         counts[1] += cell_ok(p, cand[(size_t)(i - 1) * K + b], cand[(size_t)i * K + a]);
       }
-  for (int i = 2; i < M; ++i)
+  for (int i = 2; counts && i < M; ++i)
     for (int c = 0; c < cnt[i - 2]; ++c)
       for (int b = 0; b < cnt[i - 1]; ++b) {
         const int32_t zk = cand[(size_t)(i - 2) * K + c], zj = cand[(size_t)(i - 1) * K + b];
@@ -376,9 +376,8 @@ int oracle_match_lists(int32_t M, const float* mxy, const int32_t* mt, const flo
 #endif
 #pragma omp parallel for schedule(dynamic, 1) reduction(min : rc)
   for (int32_t j = 0; j < n_tau; ++j) {
-    long long c[4] = {0, 0, 0, 0};
     int r = match_one(&p, 0, lists + (size_t)j * M * K, counts_in + (size_t)j * M, energy + j,
-                      energy_u ? energy_u + j : NULL, assign + (size_t)j * M, c);
+                      energy_u ? energy_u + j : NULL, assign + (size_t)j * M, NULL);
     if (r < rc) rc = r;
   }
   return rc;
