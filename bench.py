@@ -56,7 +56,7 @@ TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_dp_realistic_single_scene_traff
 TRAFFIC_FILE_PLAN = os.path.join(HERE, "profiles", "k_dp_persistent_realistic_single_scene_traffic.md")
 COUNTERS_FILE_PLAN = os.path.join(HERE, "profiles", "k_dp_persistent_realistic_single_scene_counters.md")
 COUNTERS_FILE_BATCHED = os.path.join(HERE, "profiles", "k_dp_persistent_batched_uneven_counters.md")
-DP_SOURCES = [os.path.join(HERE, "paper_1505_00581_amd", "csrc", f) for f in ("dp.hip", "stm_internal.h")]
+DP_SOURCES = [os.path.join(HERE, "paper_1505_00581_amd", "csrc", f) for f in ("dp.hip", "dp_math.h", "stm_internal.h")]
 
 
 def dp_source_hash() -> str:

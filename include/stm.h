@@ -362,6 +362,54 @@ STM_API int stm_match_batch(stm_ctx* ctx, const stm_points* models, int32_t n_mo
                     int32_t n_pairs, const stm_params* params, int64_t* row_offsets,
                     float* energy32, double* energy64, int32_t* assign, void* hip_stream);
 
+/* ---- the trellis over a scene block (the paper's own problem) -------------
+ *
+ * Section 2.2 matches a model against a scene block without offsets or
+ * windows: every model point may take any node of the block, the trellis is
+ * pruned only by causality and closeness (Eq. 7, 8), and the loop bounds of
+ * Section 3.4 follow from them: with nodes sorted by frame, the successors of
+ * a node (frames in (t, t + T)) and its predecessors (frames in (t - T, t))
+ * are contiguous node ranges.  Here the cells of every step are stored as that
+ * band (cells (r, c) with c a successor of r, row after row), so the work is
+ * the number of admissible (a_{i-2}, a_{i-1}, a_i) triples, not K^3 per step;
+ * T <= 0 (no closeness limit) is the full upper-triangular trellis.  This is
+ * the whole-video workload of the paper's Table 2 (M = 30 against 754 nodes)
+ * and its T sweep (Fig. 7).
+ *
+ * A trellis object holds n_models models against the nodes [node_begin,
+ * node_end) of one scene: the band, its tiles, the direction tables and the
+ * value tables (sum over models of (M - 1) x cells floats).  A run solves
+ * every model: the unary tables, one launch per step of the min-sum recursion
+ * (forward form of Eq. 10-11) over all models, the optimum and backtracking
+ * (Eq. 12-13) on the device, and the FP64 re-score (Eq. 1).
+ * Outputs: energy32, energy64, energy_u64 [n_models] (nullable: the FP64 ones)
+ * and assign [sum of model sizes] (model q's points from the sum of the sizes
+ * before it), scene node ids (-1 rows when a model has no admissible
+ * assignment in the block).  Ties: the first row-major minimum of the last
+ * step, the lowest node inside each minimum.
+ * params: lambda1..3 and T as for stm_match; window and k_max are not used;
+ * flags: STM_DEVICE_PTRS (device inputs, referenced by the object and the
+ * scene not copied; device outputs; runs queued on `hip_stream`) and
+ * STM_CLOSENESS_SPAN; STM_UNARY_BF16, STM_K_DENSITY and STM_DUMMY give
+ * STM_EUNSUPPORTED.  Errors as stm_match, plus STM_EINVAL for an empty or
+ * out-of-range node range, STM_ENOMEM when the value tables do not fit. */
+typedef struct stm_trellis stm_trellis;
+STM_API int stm_trellis_create(stm_ctx* ctx, const stm_points* models, int32_t n_models, const stm_points* scene,
+                               int32_t node_begin, int32_t node_end, const stm_params* params, stm_trellis** out);
+STM_API void stm_trellis_destroy(stm_trellis* trellis);
+STM_API int stm_trellis_run(stm_trellis* trellis, float* energy32, double* energy64, double* energy_u64,
+                            int32_t* assign, void* hip_stream);
+/* info [9], host memory: cells per step, two-step direction pairs, tiles per
+ * step launch, 1 if the degenerate variant runs (coincident points), then the
+ * work of one run over all models: dense cells (M - 1) n^2, feasible cells
+ * (M - 1) x band cells, dense relaxations (M - 2) n^3, feasible relaxations
+ * (admissible triples), and the sum of the model sizes. */
+STM_API int stm_trellis_info(const stm_trellis* trellis, int64_t* info);
+/* One-shot: create, run once, destroy (waits for the run). */
+STM_API int stm_match_trellis(stm_ctx* ctx, const stm_points* models, int32_t n_models, const stm_points* scene,
+                              int32_t node_begin, int32_t node_end, const stm_params* params, float* energy32,
+                              double* energy64, double* energy_u64, int32_t* assign, void* hip_stream);
+
 /* ---- the steps of the path, exposed for checking ------------------------- */
 
 /* Candidate lists of every model point at every offset in [tau_begin,

@@ -8,11 +8,11 @@ synthetic workloads.  Build the library with
 from ._binding import (EXPORTS, LIB_PATH, STM_DEVICE_PTRS, STM_EHIP, STM_EINVAL, STM_ENOMEM,
                        STM_EUNSUPPORTED, STM_K_DENSITY, STM_K_LIMIT, STM_NOALLOC_SCRATCH_BYTES, STM_OK,
                        STM_UNARY_BF16,
-                       Context, DevicePoints, Plan, Pruner, StmError, load,
+                       Context, DevicePoints, Plan, Pruner, StmError, Trellis, load,
                        pruner_num_params)
 from .synth import Params, Points
 
-__all__ = ["Context", "DevicePoints", "Params", "Plan", "Points", "Pruner", "pruner_num_params", "StmError", "load", "EXPORTS",
+__all__ = ["Context", "DevicePoints", "Params", "Plan", "Points", "Pruner", "Trellis", "pruner_num_params", "StmError", "load", "EXPORTS",
            "LIB_PATH", "STM_OK", "STM_EINVAL", "STM_ENOMEM", "STM_EHIP", "STM_EUNSUPPORTED",
            "STM_K_LIMIT", "STM_DEVICE_PTRS", "STM_K_DENSITY", "STM_UNARY_BF16",
            "STM_NOALLOC_SCRATCH_BYTES"]

@@ -37,7 +37,8 @@ EXPORTS = ("stm_create", "stm_destroy", "stm_last_error", "stm_offsets", "stm_ma
            "stm_pruner_set_params", "stm_pruner_get_params", "stm_pruner_save", "stm_pruner_load",
            "stm_pruner_features", "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
            "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned",
-           "stm_match_chains", "stm_plan_run_lists", "stm_match_noalloc")
+           "stm_match_chains", "stm_plan_run_lists", "stm_match_noalloc", "stm_trellis_create",
+           "stm_trellis_destroy", "stm_trellis_run", "stm_trellis_info", "stm_match_trellis")
 
 
 class StmError(RuntimeError):
@@ -124,6 +125,12 @@ def load() -> ctypes.CDLL:
         lib.stm_match_chains.argtypes = [P, PP, P, i32, PP, PS, i32, i32, P, P, P, P, P, P]
         lib.stm_plan_run_lists.argtypes = [P, P, P, i32, P, P, P, P, P]
         lib.stm_match_noalloc.argtypes = [P, PP, PP, PS, i32, i32, P, P, P, P, P]
+        lib.stm_trellis_create.argtypes = [P, P, i32, PP, i32, i32, PS, ctypes.POINTER(P)]
+        lib.stm_trellis_destroy.argtypes = [P]
+        lib.stm_trellis_destroy.restype = None
+        lib.stm_trellis_run.argtypes = [P, P, P, P, P, P]
+        lib.stm_trellis_info.argtypes = [P, P]
+        lib.stm_match_trellis.argtypes = [P, P, i32, PP, i32, i32, PS, P, P, P, P, P]
         for name in ("stm_create", "stm_offsets", "stm_match", "stm_candidates", "stm_unary",
                      "stm_count_work", "stm_set_dp_waves", "stm_profile_enable",
                      "stm_profile_read", "stm_plan_create", "stm_plan_rows", "stm_plan_run",
@@ -132,7 +139,8 @@ def load() -> ctypes.CDLL:
                      "stm_pruner_save", "stm_pruner_load", "stm_pruner_features",
                      "stm_pruner_gradient", "stm_pruner_train_step", "stm_pruner_infer",
                      "stm_match_pruned", "stm_match_lists", "stm_pruner_set_rule", "stm_plan_run_pruned",
-                     "stm_match_chains", "stm_plan_run_lists", "stm_match_noalloc"):
+                     "stm_match_chains", "stm_plan_run_lists", "stm_match_noalloc", "stm_trellis_create",
+                     "stm_trellis_run", "stm_trellis_info", "stm_match_trellis"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -431,6 +439,72 @@ class Context:
         _check(self._lib.stm_profile_read(self.handle, ctypes.addressof(ms), ctypes.addressof(nl),
                                           ctypes.addressof(nm)))
         return dict(dp_ms=ms.value, dp_launches=nl.value, dp_matchings=nm.value)
+
+
+class Trellis:
+    """The trellis over a scene block (stm_trellis_*): every model against every
+    node of scene nodes [node_begin, node_end), the paper's own problem.
+    Device point sets (DevicePoints) are referenced and must outlive it."""
+
+    def __init__(self, ctx: Context, models, scene, params, node_begin: int = 0, node_end=None):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        self.device = _is_device(scene)
+        self._keep = []
+        self._models = (_Points * len(models))(*[_points(m, self._keep) for m in models])
+        self._scene = _points(scene, self._keep)
+        self.msizes = [int(m.t.shape[0]) for m in models]
+        self.assign_offsets = np.concatenate([[0], np.cumsum(self.msizes)]).astype(np.int64)
+        e = int(scene.t.shape[0]) if node_end is None else int(node_end)
+        pp = _params(params, self.device)
+        h = ctypes.c_void_p()
+        _check(self._lib.stm_trellis_create(ctx.handle, ctypes.addressof(self._models), len(models),
+                                            ctypes.byref(self._scene), int(node_begin), e, ctypes.byref(pp),
+                                            ctypes.byref(h)))
+        self.handle = h
+
+    def info(self) -> dict:
+        v = np.zeros(9, np.int64)
+        _check(self._lib.stm_trellis_info(self.handle, v.ctypes.data))
+        return dict(cells_per_step=int(v[0]), pairs=int(v[1]), tiles=int(v[2]), degenerate=bool(v[3]),
+                    dense_cells=int(v[4]), feasible_cells=int(v[5]), dense_relax=int(v[6]),
+                    feasible_relax=int(v[7]), points=int(v[8]))
+
+    def run(self, out=None):
+        """Solves every model.  Returns dict(energy32, energy64, energy_u64
+        [n_models], assign [sum of model sizes]); torch tensors on the current
+        stream for device point sets (`out` reused when given), numpy otherwise."""
+        n, na = len(self.msizes), int(self.assign_offsets[-1])
+        if self.device:
+            import torch
+            if out is None:
+                out = dict(energy32=torch.empty(n, dtype=torch.float32, device="cuda"),
+                           energy64=torch.empty(n, dtype=torch.float64, device="cuda"),
+                           energy_u64=torch.empty(n, dtype=torch.float64, device="cuda"),
+                           assign=torch.empty(na, dtype=torch.int32, device="cuda"))
+            stream = _stream()
+        else:
+            out = dict(energy32=np.empty(n, np.float32), energy64=np.empty(n, np.float64),
+                       energy_u64=np.empty(n, np.float64), assign=np.empty(na, np.int32))
+            stream = None
+        _check(self._lib.stm_trellis_run(self.handle, _ptr(out["energy32"]), _ptr(out["energy64"]),
+                                         _ptr(out["energy_u64"]), _ptr(out["assign"]), stream))
+        return out
+
+    def model_rows(self, out, q):
+        """Assignment of model q from a run's output."""
+        return out["assign"][self.assign_offsets[q]:self.assign_offsets[q + 1]]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.stm_trellis_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

@@ -22,8 +22,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "plan.cpp", "prep.hip", "dp.hip", "unary_bf16.hip", "pruner.hip", "pruner_api.cpp",
-           "chains.hip", "noalloc.hip"]
+           "chains.hip", "noalloc.hip", "trellis.hip", "trellis_api.cpp"]
 HEADERS = [os.path.join(CSRC, "stm_internal.h"), os.path.join(CSRC, "host_common.h"),
+           os.path.join(CSRC, "dp_math.h"),
            os.path.join(ROOT, "include", "stm.h")]
 
 FLAGS = [

@@ -293,6 +293,67 @@ hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_i
                                 double lambda1, double lambda2, double lambda3, double w_dummy,
                                 const int32_t* assign, double* e64, double* eu64, hipStream_t st);
 
+// ---- the trellis over a scene block ---------------------------------------------------
+
+// Tiles of a step: rows [r0, r1) by columns [c0, c1) of the band, ncell >= 1
+// cells (c a successor of r inside the window), predecessors [k0, k1).
+constexpr int kTrellisTileRows = 64;
+constexpr int kTrellisTileCols = 128;
+constexpr int kTrellisTileCells = 1024;
+struct TrellisTile {
+  int32_t r0, r1, c0, c1, k0, k1, ncell, pad;
+};
+
+// The band of a scene block of n nodes (local ids, sorted by frame): successors
+// [s_lo, s_hi) (frames in (t, t + T)), predecessors [p_lo, p_hi) (frames in
+// (t - T, t)), two-step pairs [q_lo, q_hi) (frames in [t + 2, t + 2T - 2]), with
+// T the limit of consecutive points (pair_limit); rowoff [n + 1] and qoff
+// [n + 1] number the cells and the pairs row after row; A [rowoff[n]] holds
+// -phi(r -> c) of every cell, C [qoff[n]] -phi(k -> c) of every pair (+inf
+// for pairs the span reading excludes; NaN for coincident points).
+struct TrellisBand {
+  int32_t *s_lo, *s_hi, *p_lo, *p_hi, *q_lo, *q_hi;
+  long long *rowoff, *qoff;
+  float *A, *C;
+};
+
+// One model of a trellis run: U [M][n] raw distances to the block's nodes,
+// V [(M - 1)][Q] the value tables of steps 1..M-1, assignments from
+// assign + assign0.
+struct TrellisModel {
+  ModelView m;
+  const float2* theta;
+  const float* U;
+  float* V;
+  long long assign0;
+};
+
+struct TrellisRun {
+  const TrellisModel* models;
+  int32_t n_models;
+  TrellisBand band;
+  const TrellisTile* tiles;
+  const int32_t* t;     // [n] the block's frames
+  const float2* xy;     // [n] the block's coordinates
+  int32_t n;            // block nodes
+  int32_t node0;        // scene id of the block's first node
+  long long Q;          // cells per step
+  int32_t span_lim;     // span_limit of the search parameters
+  float lambda1, lambda2, w;
+  float* e32;           // [n_models]
+  int32_t* assign;      // scene node ids, -1 rows when infeasible
+};
+
+// The band of the block (t [n] sorted): ranges, then offsets by two scans.
+hipError_t launch_trellis_band(const int32_t* t, int32_t n, const SearchParams& sp, const TrellisBand& b,
+                               hipStream_t st);
+// The direction tables A and C; *flag |= 1 when coincident points take part.
+hipError_t launch_trellis_dirs(const TrellisBand& b, int32_t n, const float2* xy, const int32_t* t, int32_t span_lim,
+                               int32_t* flag, hipStream_t st);
+// Steps 1..M-1 of every model, then the optimum and backtracking (degen: the
+// variant that handles coincident points).
+hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_max, bool degen, hipStream_t st);
+
 // ---- learned candidate pruner -------------------------------------------------------
 
 constexpr int kPrunerHidden = 128;

@@ -1,0 +1,421 @@
+// Host side of the trellis over a scene block (the paper's own problem,
+// Section 2.2): validation, the band and its tiles, scratch, work counts and
+// the order of the kernels.
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "host_common.h"
+
+using namespace stmh;
+
+struct stm_trellis {
+  stm_ctx* ctx = nullptr;
+  stm_params params{};
+  stm::SearchParams sp{};
+  bool device = false;
+  int n_models = 0, m_max = 0, dim = 0;
+  std::vector<int32_t> msize;
+  std::vector<long long> mrow;  // first row of each model in the concatenated arrays
+  long long m_total = 0;
+  int32_t node0 = 0, n = 0;
+  stm::SceneView scene{};       // the whole scene (assignments hold its node ids)
+  std::vector<void*> owned;
+  float2* mxy = nullptr;
+  int32_t* mt = nullptr;
+  float* mdesc = nullptr;
+  float2* theta = nullptr;
+  float* U = nullptr;           // [m_total][n]
+  float* V = nullptr;
+  stm::TrellisBand band{};
+  long long Q = 0, QC = 0;
+  stm::TrellisTile* tiles = nullptr;
+  int32_t n_tiles = 0;
+  stm::TrellisModel* models_dev = nullptr;
+  stm::PairDev* pairs_dev = nullptr;
+  int2* items_dev = nullptr;
+  bool degen = false;
+  int64_t work[4] = {0, 0, 0, 0};
+  float* o_e32 = nullptr;
+  double* o_e64 = nullptr;
+  double* o_eu = nullptr;
+  int32_t* o_asg = nullptr;
+};
+
+namespace {
+
+void* tr_alloc(stm_trellis* p, size_t bytes, int* rc) {
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes ? bytes : 1) != hipSuccess) {
+    (void)hipGetLastError();
+    *rc = fail(STM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return nullptr;
+  }
+  p->owned.push_back(q);
+  return q;
+}
+
+void tr_free(stm_trellis* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->ctx->device);
+  (void)hipDeviceSynchronize();
+  for (void* q : p->owned) (void)hipFree(q);
+  delete p;
+}
+
+// Tiles of a step from the band's ranges (host copies): narrow bands take up
+// to 64 consecutive rows whose successors span at most 128 nodes and hold at
+// most 1024 cells; a row with more than 128 successors starts a block of up to
+// 8 rows cut into 128-column windows.  Tiles without cells are left out.
+std::vector<stm::TrellisTile> make_tiles(const std::vector<int32_t>& slo, const std::vector<int32_t>& shi,
+                                         const std::vector<int32_t>& plo, const std::vector<int32_t>& phi) {
+  constexpr int kRows = stm::kTrellisTileRows, kCols = stm::kTrellisTileCols, kCells = stm::kTrellisTileCells;
+  constexpr int kWideRows = kCells / kCols;
+  std::vector<stm::TrellisTile> out;
+  const int32_t n = static_cast<int32_t>(slo.size());
+  int32_t r0 = 0;
+  while (r0 < n) {
+    const int32_t w0 = shi[r0] - slo[r0];
+    if (w0 > kCols) {
+      const int32_t r1 = std::min(n, r0 + kWideRows);
+      int32_t cu1 = slo[r0];
+      for (int32_t r = r0; r < r1; ++r) cu1 = std::max(cu1, shi[r]);
+      for (int32_t c0 = slo[r0]; c0 < cu1; c0 += kCols) {
+        const int32_t c1 = std::min(cu1, c0 + kCols);
+        int32_t cells = 0;
+        for (int32_t r = r0; r < r1; ++r) cells += std::max(0, std::min(shi[r], c1) - std::max(slo[r], c0));
+        if (cells > 0) out.push_back({r0, r1, c0, c1, plo[r0], phi[r1 - 1], cells, 0});
+      }
+      r0 = r1;
+      continue;
+    }
+    int32_t r1 = r0 + 1, cells = w0, chi = shi[r0];
+    while (r1 < n && r1 - r0 < kRows && shi[r1] - slo[r0] <= kCols && shi[r1] - slo[r1] <= kCols &&
+           cells + (shi[r1] - slo[r1]) <= kCells) {
+      cells += shi[r1] - slo[r1];
+      chi = std::max(chi, shi[r1]);
+      ++r1;
+    }
+    if (cells > 0) out.push_back({r0, r1, slo[r0], std::max(chi, slo[r0] + 1), plo[r0], phi[r1 - 1], cells, 0});
+    r0 = r1;
+  }
+  return out;
+}
+
+int check_trellis_params(const stm_params* p) {
+  if (!p) return fail(STM_EINVAL, "null params");
+  if (p->flags & (STM_UNARY_BF16 | STM_K_DENSITY | STM_DUMMY))
+    return fail(STM_EUNSUPPORTED, "the trellis takes STM_DEVICE_PTRS and STM_CLOSENESS_SPAN only");
+  if (p->flags & ~(STM_DEVICE_PTRS | STM_CLOSENESS_SPAN)) return fail(STM_EUNSUPPORTED, "unknown flag");
+  return STM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stm_trellis_create(stm_ctx* ctx, const stm_points* models, int32_t n_models, const stm_points* scene,
+                       int32_t node_begin, int32_t node_end, const stm_params* params, stm_trellis** out) {
+  err().clear();
+  if (!out) return fail(STM_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!ctx) return fail(STM_EINVAL, "null context");
+  if (!models || n_models < 1 || !scene) return fail(STM_EINVAL, "need at least one model and a scene");
+  if (n_models > 65535) return fail(STM_EUNSUPPORTED, "more than 65535 models in one trellis");
+  int rc = check_trellis_params(params);
+  if (rc) return rc;
+  // the shape checks of the exact matching; window and k_max do not apply here
+  stm_params pc = *params;
+  pc.k_max = 1;
+  pc.window = 0;
+  pc.flags &= STM_DEVICE_PTRS;
+  for (int q = 0; q < n_models; ++q)
+    if ((rc = check_shapes(&models[q], scene, &pc))) return rc;
+  if (node_begin < 0 || node_end > scene->n || node_begin >= node_end)
+    return fail(STM_EINVAL, "node range [" + std::to_string(node_begin) + ", " + std::to_string(node_end) +
+                                ") outside [0, " + std::to_string(scene->n) + ") or empty");
+  const bool device = (params->flags & STM_DEVICE_PTRS) != 0;
+  if (!device)
+    for (int q = 0; q < n_models; ++q) {
+      const int bits = host_validate(&models[q], scene);
+      if (bits) return fail(STM_EINVAL, bit_message(bits));
+    }
+  STM_HIP(hipSetDevice(ctx->device));
+  stm_trellis* p = new (std::nothrow) stm_trellis();
+  if (!p) return fail(STM_ENOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->params = *params;
+  p->sp = search_params(params, 0);
+  p->device = device;
+  p->n_models = n_models;
+  p->dim = scene->dim;
+  p->node0 = node_begin;
+  p->n = node_end - node_begin;
+  const hipStream_t st = nullptr;
+  auto bail = [&](int code) {
+    tr_free(p);
+    return code;
+  };
+#define TR_HIP(expr)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return bail(fail(STM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+#define TR_ALLOC(dst, T, count)                                      \
+  do {                                                               \
+    dst = static_cast<T*>(tr_alloc(p, sizeof(T) * (size_t)(count), &rc)); \
+    if (!dst) return bail(rc);                                       \
+  } while (0)
+
+  for (int q = 0; q < n_models; ++q) {
+    p->msize.push_back(models[q].n);
+    p->mrow.push_back(p->m_total);
+    p->m_total += models[q].n;
+    p->m_max = std::max(p->m_max, models[q].n);
+  }
+  const int D = p->dim, S = scene->n, F = scene->n_frames;
+  const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  // device data: validation (device pointers), concatenated models, the scene
+  int32_t* val = nullptr;
+  TR_ALLOC(val, int32_t, 2);
+  if (device) {
+    const stm::SceneView sv{reinterpret_cast<const float2*>(scene->xy), scene->t, scene->desc, nullptr, S, F, D};
+    for (int q = 0; q < n_models; ++q) {
+      const stm::ModelView mv{reinterpret_cast<const float2*>(models[q].xy), models[q].t, models[q].desc, models[q].n};
+      TR_HIP(hipMemsetAsync(val, 0, 2 * sizeof(int32_t), st));
+      TR_HIP(stm::launch_validate(mv, sv, val, st));
+      int32_t hv[2] = {0, 0};
+      TR_HIP(hipMemcpyAsync(hv, val, sizeof(hv), hipMemcpyDeviceToHost, st));
+      TR_HIP(hipStreamSynchronize(st));
+      if (hv[0]) return bail(fail(STM_EINVAL, bit_message(hv[0])));
+    }
+    p->scene = sv;
+  } else {
+    float2* sxy;
+    int32_t* stt;
+    float* sd;
+    TR_ALLOC(sxy, float2, S);
+    TR_ALLOC(stt, int32_t, S);
+    TR_ALLOC(sd, float, (size_t)S * D);
+    TR_HIP(hipMemcpyAsync(sxy, scene->xy, sizeof(float2) * S, kind, st));
+    TR_HIP(hipMemcpyAsync(stt, scene->t, sizeof(int32_t) * S, kind, st));
+    TR_HIP(hipMemcpyAsync(sd, scene->desc, sizeof(float) * (size_t)S * D, kind, st));
+    p->scene = stm::SceneView{sxy, stt, sd, nullptr, S, F, D};
+  }
+  TR_ALLOC(p->mxy, float2, p->m_total);
+  TR_ALLOC(p->mt, int32_t, p->m_total);
+  TR_ALLOC(p->mdesc, float, (size_t)p->m_total * D);
+  TR_ALLOC(p->theta, float2, p->m_total);
+  for (int q = 0; q < n_models; ++q) {
+    const long long r0 = p->mrow[q];
+    const int M = models[q].n;
+    TR_HIP(hipMemcpyAsync(p->mxy + r0, models[q].xy, sizeof(float2) * M, kind, st));
+    TR_HIP(hipMemcpyAsync(p->mt + r0, models[q].t, sizeof(int32_t) * M, kind, st));
+    TR_HIP(hipMemcpyAsync(p->mdesc + r0 * D, models[q].desc, sizeof(float) * (size_t)M * D, kind, st));
+    TR_HIP(stm::launch_model_angles(stm::ModelView{p->mxy + r0, p->mt + r0, p->mdesc + r0 * D, M}, p->theta + r0, st));
+  }
+
+  // the band of the block, its offsets and its tiles
+  const int32_t n = p->n;
+  const int32_t* bt = p->scene.t + p->node0;
+  const float2* bxy = p->scene.xy + p->node0;
+  stm::TrellisBand& b = p->band;
+  TR_ALLOC(b.s_lo, int32_t, n);
+  TR_ALLOC(b.s_hi, int32_t, n);
+  TR_ALLOC(b.p_lo, int32_t, n);
+  TR_ALLOC(b.p_hi, int32_t, n);
+  TR_ALLOC(b.q_lo, int32_t, n);
+  TR_ALLOC(b.q_hi, int32_t, n);
+  TR_ALLOC(b.rowoff, long long, (size_t)n + 1);
+  TR_ALLOC(b.qoff, long long, (size_t)n + 1);
+  TR_HIP(stm::launch_trellis_band(bt, n, p->sp, b, st));
+  std::vector<int32_t> slo(n), shi(n), plo(n), phi(n), th(n);
+  long long ends[2] = {0, 0};
+  TR_HIP(hipMemcpyAsync(slo.data(), b.s_lo, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  TR_HIP(hipMemcpyAsync(shi.data(), b.s_hi, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  TR_HIP(hipMemcpyAsync(plo.data(), b.p_lo, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  TR_HIP(hipMemcpyAsync(phi.data(), b.p_hi, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  TR_HIP(hipMemcpyAsync(th.data(), bt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  TR_HIP(hipMemcpyAsync(&ends[0], b.rowoff + n, sizeof(long long), hipMemcpyDeviceToHost, st));
+  TR_HIP(hipMemcpyAsync(&ends[1], b.qoff + n, sizeof(long long), hipMemcpyDeviceToHost, st));
+  TR_HIP(hipStreamSynchronize(st));
+  p->Q = ends[0];
+  p->QC = ends[1];
+  const std::vector<stm::TrellisTile> tiles = make_tiles(slo, shi, plo, phi);
+  p->n_tiles = static_cast<int32_t>(tiles.size());
+  TR_ALLOC(p->tiles, stm::TrellisTile, std::max<size_t>(1, tiles.size()));
+  if (!tiles.empty())
+    TR_HIP(hipMemcpyAsync(p->tiles, tiles.data(), sizeof(stm::TrellisTile) * tiles.size(), hipMemcpyHostToDevice, st));
+
+  // work per run: cells of steps 1..M-1, relaxations of steps 2..M-1 (dense:
+  // every pair and triple of block nodes; feasible: the band, and under the
+  // span reading only the predecessors less than T frames before the column)
+  {
+    const int32_t TS = stm::span_limit(p->sp);
+    long long rel = 0;
+    for (int32_t r = 0; r < n; ++r)
+      for (int32_t c = slo[r]; c < shi[r]; ++c) {
+        if (TS <= 0) {
+          rel += phi[r] - plo[r];
+        } else {  // predecessors k of r with th[c] - th[k] < TS: a suffix of [plo, phi)
+          const int32_t first = static_cast<int32_t>(
+              std::lower_bound(th.begin() + plo[r], th.begin() + phi[r], th[c] - TS + 1) - th.begin());
+          rel += phi[r] - first;
+        }
+      }
+    for (int q = 0; q < n_models; ++q) {
+      const long long M = p->msize[q];
+      p->work[0] += (M - 1) * (long long)n * n;
+      p->work[1] += (M - 1) * p->Q;
+      p->work[2] += (M - 2) * (long long)n * n * n;
+      p->work[3] += (M - 2) * rel;
+    }
+  }
+
+  // direction tables, and whether coincident points take part
+  TR_ALLOC(b.A, float, std::max(1LL, p->Q));
+  TR_ALLOC(b.C, float, std::max(1LL, p->QC));
+  TR_HIP(hipMemsetAsync(val, 0, sizeof(int32_t), st));
+  TR_HIP(stm::launch_trellis_dirs(b, n, bxy, bt, stm::span_limit(p->sp), val, st));
+  int32_t flag = 0;
+  TR_HIP(hipMemcpyAsync(&flag, val, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TR_HIP(hipStreamSynchronize(st));
+  p->degen = flag != 0;
+
+  // unary tables, value tables, the model table and the re-score's pair table
+  TR_ALLOC(p->U, float, (size_t)p->m_total * n);
+  long long v_total = 0;
+  for (int q = 0; q < n_models; ++q) v_total += (long long)(p->msize[q] - 1) * p->Q;
+  TR_ALLOC(p->V, float, std::max(1LL, v_total));
+  std::vector<stm::TrellisModel> tm(n_models);
+  std::vector<stm::PairDev> pd(n_models);
+  std::vector<int2> items(n_models);
+  long long voff = 0;
+  for (int q = 0; q < n_models; ++q) {
+    const long long r0 = p->mrow[q];
+    const stm::ModelView mv{p->mxy + r0, p->mt + r0, p->mdesc + r0 * D, p->msize[q]};
+    tm[q].m = mv;
+    tm[q].theta = p->theta + r0;
+    tm[q].U = p->U + r0 * n;
+    tm[q].V = p->V + voff;
+    tm[q].assign0 = r0;
+    voff += (long long)(p->msize[q] - 1) * p->Q;
+    pd[q].m = mv;
+    pd[q].s = p->scene;
+    pd[q].U = nullptr;
+    pd[q].us = 0;
+    pd[q].theta = p->theta + r0;
+    pd[q].row0 = q;
+    pd[q].assign0 = r0;
+    pd[q].n_tau = 1;
+    items[q] = make_int2(q, 0);
+  }
+  TR_ALLOC(p->models_dev, stm::TrellisModel, n_models);
+  TR_ALLOC(p->pairs_dev, stm::PairDev, n_models);
+  TR_ALLOC(p->items_dev, int2, n_models);
+  TR_HIP(hipMemcpyAsync(p->models_dev, tm.data(), sizeof(stm::TrellisModel) * n_models, hipMemcpyHostToDevice, st));
+  TR_HIP(hipMemcpyAsync(p->pairs_dev, pd.data(), sizeof(stm::PairDev) * n_models, hipMemcpyHostToDevice, st));
+  TR_HIP(hipMemcpyAsync(p->items_dev, items.data(), sizeof(int2) * n_models, hipMemcpyHostToDevice, st));
+  if (!device) {
+    TR_ALLOC(p->o_e32, float, n_models);
+    TR_ALLOC(p->o_e64, double, n_models);
+    TR_ALLOC(p->o_eu, double, n_models);
+    TR_ALLOC(p->o_asg, int32_t, p->m_total);
+  }
+  TR_HIP(hipStreamSynchronize(st));
+#undef TR_HIP
+#undef TR_ALLOC
+  *out = p;
+  return STM_OK;
+}
+
+void stm_trellis_destroy(stm_trellis* trellis) { tr_free(trellis); }
+
+int stm_trellis_info(const stm_trellis* trellis, int64_t* info) {
+  err().clear();
+  if (!trellis || !info) return fail(STM_EINVAL, "null argument");
+  info[0] = trellis->Q;
+  info[1] = trellis->QC;
+  info[2] = trellis->n_tiles;
+  info[3] = trellis->degen ? 1 : 0;
+  for (int k = 0; k < 4; ++k) info[4 + k] = trellis->work[k];
+  info[8] = trellis->m_total;
+  return STM_OK;
+}
+
+int stm_trellis_run(stm_trellis* p, float* energy32, double* energy64, double* energy_u64, int32_t* assign,
+                    void* hip_stream) {
+  err().clear();
+  if (!p) return fail(STM_EINVAL, "null trellis");
+  if (!energy32 || !assign) return fail(STM_EINVAL, "energy32 and assign are required");
+  STM_HIP(hipSetDevice(p->ctx->device));
+  const hipStream_t st = p->device ? static_cast<hipStream_t>(hip_stream) : nullptr;
+  float* e32 = p->device ? energy32 : p->o_e32;
+  double* e64 = p->device ? energy64 : (energy64 ? p->o_e64 : nullptr);
+  double* eu = p->device ? energy_u64 : (energy_u64 ? p->o_eu : nullptr);
+  int32_t* as = p->device ? assign : p->o_asg;
+  const int32_t n = p->n;
+  const stm::SceneView block{p->scene.xy + p->node0, p->scene.t + p->node0,
+                             p->scene.desc + (long long)p->node0 * p->dim, nullptr, n, p->scene.F, p->dim};
+  STM_HIP(stm::launch_unary_f32(stm::ModelView{p->mxy, p->mt, p->mdesc, static_cast<int32_t>(p->m_total)}, block,
+                                p->U, st));
+  stm::TrellisRun a;
+  a.models = p->models_dev;
+  a.n_models = p->n_models;
+  a.band = p->band;
+  a.tiles = p->tiles;
+  a.t = block.t;
+  a.xy = block.xy;
+  a.n = n;
+  a.node0 = p->node0;
+  a.Q = p->Q;
+  a.span_lim = stm::span_limit(p->sp);
+  a.lambda1 = static_cast<float>(p->params.lambda1);
+  a.lambda2 = static_cast<float>(p->params.lambda2);
+  a.w = static_cast<float>(p->params.lambda2 * p->params.lambda3);
+  a.e32 = e32;
+  a.assign = as;
+  if (p->ctx->prof) {
+    if (p->ctx->prof_used + 2 > p->ctx->prof_ev.size()) {
+      for (int q = 0; q < 2; ++q) {
+        hipEvent_t ev;
+        STM_HIP(hipEventCreate(&ev));
+        p->ctx->prof_ev.push_back(ev);
+      }
+    }
+    STM_HIP(hipEventRecord(p->ctx->prof_ev[p->ctx->prof_used], st));
+    STM_HIP(stm::launch_trellis_run(a, p->n_tiles, p->m_max, p->degen, st));
+    STM_HIP(hipEventRecord(p->ctx->prof_ev[p->ctx->prof_used + 1], st));
+    p->ctx->prof_used += 2;
+    p->ctx->prof_matchings += p->n_models;
+  } else {
+    STM_HIP(stm::launch_trellis_run(a, p->n_tiles, p->m_max, p->degen, st));
+  }
+  STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_models, p->sp, p->params.lambda1,
+                                    p->params.lambda2, p->params.lambda3, 0.0, as, e64, eu, st));
+  if (!p->device) {
+    STM_HIP(hipMemcpyAsync(energy32, e32, sizeof(float) * p->n_models, hipMemcpyDeviceToHost, st));
+    STM_HIP(hipMemcpyAsync(assign, as, sizeof(int32_t) * p->m_total, hipMemcpyDeviceToHost, st));
+    if (energy64) STM_HIP(hipMemcpyAsync(energy64, e64, sizeof(double) * p->n_models, hipMemcpyDeviceToHost, st));
+    if (energy_u64) STM_HIP(hipMemcpyAsync(energy_u64, eu, sizeof(double) * p->n_models, hipMemcpyDeviceToHost, st));
+    STM_HIP(hipStreamSynchronize(st));
+  }
+  return STM_OK;
+}
+
+int stm_match_trellis(stm_ctx* ctx, const stm_points* models, int32_t n_models, const stm_points* scene,
+                      int32_t node_begin, int32_t node_end, const stm_params* params, float* energy32,
+                      double* energy64, double* energy_u64, int32_t* assign, void* hip_stream) {
+  stm_trellis* p = nullptr;
+  int rc = stm_trellis_create(ctx, models, n_models, scene, node_begin, node_end, params, &p);
+  if (rc) return rc;
+  rc = stm_trellis_run(p, energy32, energy64, energy_u64, assign, hip_stream);
+  if (rc == STM_OK && p->device) {
+    const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) rc = fail(STM_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  }
+  stm_trellis_destroy(p);
+  return rc;
+}
+
+}  // extern "C"

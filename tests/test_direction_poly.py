@@ -1,5 +1,5 @@
 """The scene directions of the HIP recursion use a polynomial atan2
-(paper_1505_00581_amd/csrc/dp.hip, neg_atan2).  This CPU test reads its
+(paper_1505_00581_amd/csrc/dp_math.h, neg_atan2).  This CPU test reads its
 coefficients from the source, evaluates it with float32 roundings (one
 rounding per fused multiply-add) and checks the error bound the source
 states against numpy's FP64 arctan2, over the whole plane and near the axes
@@ -11,7 +11,7 @@ import re
 import numpy as np
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                   "paper_1505_00581_amd", "csrc", "dp.hip")
+                   "paper_1505_00581_amd", "csrc", "dp_math.h")
 BOUND = 3.5e-7
 
 
