@@ -403,6 +403,69 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, plan_ms_per_step: fl
                 plan_speedup_at_target=(per_k[str(best)]["plan_speedup_vs_exact_plan"] if best else None))
 
 
+def bench_trellis(ctx, steps: int, t_values=(10, 0), model_counts=(1, 50)):
+    """The paper's own problem (Table 2's whole video, Fig. 7's T sweep): M=30
+    models against every node of a 723-frame video of 754 points, one trellis
+    per model on the banded layout (stm_trellis_*), at T = 10 and with no
+    closeness limit, for 1 and for 50 models.  A run is the unary tables, one
+    launch per step for all models, the optimum, backtracking and the FP64
+    re-score; the trellis object (band, tiles, direction tables) is built once
+    and timed apart.  The paper's GTX580 figures are context only."""
+    import torch
+
+    import paper_1505_00581_amd as stm
+    from paper_1505_00581_amd import synth
+    w = synth.paper_blocks(0, n_models=max(model_counts))
+    s = w.scenes[0]
+    ds = stm.DevicePoints.from_host(s)
+    dms = [stm.DevicePoints.from_host(m) for m in w.models]
+    out = []
+    for T in t_values:
+        p = dataclasses.replace(w.params, T=int(T))
+        for nm in model_counts:
+            tb = time.perf_counter()
+            tr = stm.Trellis(ctx, dms[:nm], ds, p)
+            torch.cuda.synchronize()
+            build_ms = 1e3 * (time.perf_counter() - tb)
+            info = tr.info()
+            res = tr.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                tr.run(res)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            ctx.profile_enable(True)
+            for _ in range(steps):
+                tr.run(res)
+            torch.cuda.synchronize()
+            prof = ctx.profile_read()
+            ctx.profile_enable(False)
+            dp_ms = prof["dp_ms"] / max(prof["dp_launches"], 1)
+            ach = info["feasible_relax"] * OPS_PER_RELAX / (dp_ms / 1e3) / 1e12
+            e32 = res["energy32"].cpu().numpy()
+            tr.close()
+            row = dict(T=int(T), models=nm, ms_per_run=round(ms, 3), ms_per_frame=round(ms / s.n_frames, 5),
+                       build_ms=round(build_ms, 2), recursion_ms=round(dp_ms, 3),
+                       cells_per_step=info["cells_per_step"], tiles_per_step=info["tiles"],
+                       feasible_relax=info["feasible_relax"],
+                       feasible_relax_per_s=round(info["feasible_relax"] / (ms / 1e3), 1),
+                       roofline=dict(bound="alu", achieved=round(ach, 3), peak=round(VALU_PEAK_OPS / 1e12, 3),
+                                     unit="TOP/s", frac=round(ach * 1e12 / VALU_PEAK_OPS, 4),
+                                     ops_per_relax=OPS_PER_RELAX,
+                                     kernel="k_trellis_first + k_trellis_step x (M-2) + k_trellis_final"),
+                       feasible=int(np.isfinite(e32).sum()))
+            out.append(row)
+            log(f"  trellis T={T} models={nm}: {ms:.3f} ms per run ({ms / s.n_frames:.5f} ms/frame), "
+                f"build {build_ms:.1f} ms, recursion {dp_ms:.3f} ms, {info['feasible_relax']:.3e} relaxations, "
+                f"{row['roofline']['frac']:.3f} of the VALU ceiling")
+    return dict(workload="the paper's whole-video trellis: M=30 models (160x120, frames 0..45) against all "
+                         "754 points of a 723-frame video (about one per frame), one trellis per model",
+                runs=out,
+                paper_context="GTX580 (Table 2 / Fig. 7, other hardware and KTH inputs): 178 ms per model at "
+                              "T=10, 1853 ms with no closeness limit")
+
+
 def bench_paper_blocks(ctx, steps: int):
     """The paper's own streaming workload (Table 2): 50 models of M=30 points
     against a 723-frame video of 754 points, each model matched against every
@@ -606,6 +669,8 @@ def main():
                     "(0 = no limit); empty: skip the sweep")
     ap.add_argument("--paper-blocks", action="store_true",
                     help="also time the paper's own streaming workload (60-point blocks)")
+    ap.add_argument("--no-trellis", action="store_true",
+                    help="skip the paper's whole-video trellis (1 and 50 models, T=10 and no limit)")
     ap.add_argument("--pruned-k", default="16,32,48", help="pruned list sizes to evaluate")
     ap.add_argument("--pruned-groups", type=int, default=200000, help="training groups")
     ap.add_argument("--pruned-epochs", type=int, default=4)
@@ -781,6 +846,10 @@ def main():
     if args.paper_blocks:
         blocks = bench_paper_blocks(ctx, args.steps)
 
+    trellis = None
+    if not args.no_trellis:
+        trellis = bench_trellis(ctx, args.steps)
+
     batched = None
     if not args.no_batched:
         batched = bench_batched(ctx, args.seed, args.batched_runs, args.tune_cache)
@@ -828,6 +897,8 @@ def main():
         line["batched"] = batched
     if blocks is not None:
         line["paper_blocks"] = blocks
+    if trellis is not None:
+        line["trellis"] = trellis
     if sweep is not None:
         line["t_sweep"] = sweep
     print(json.dumps(line), flush=True)

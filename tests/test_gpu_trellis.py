@@ -203,3 +203,35 @@ def test_refused_arguments(ctx, video):
         with pytest.raises(stm.StmError) as ei:
             stm.Trellis(ctx, [m], s, q)
         assert ei.value.code == stm.STM_EUNSUPPORTED
+
+
+def test_graph_replays_equal_direct_launches(ctx, video):
+    # runs into the same outputs replay one captured graph; a profiled run
+    # launches the kernels directly: every replay, with eager work and
+    # synchronisations between them, equals the direct run bit for bit
+    import torch
+    s, p = video.scenes[0], video.params
+    dms = [stm.DevicePoints.from_host(m) for m in video.models[:5]]
+    ds = stm.DevicePoints.from_host(s)
+    for T in (10, 0):
+        tr = stm.Trellis(ctx, dms, ds, dataclasses.replace(p, T=T), 0, 500)
+        ctx.profile_enable(True)
+        ref = tr.run()
+        torch.cuda.synchronize()
+        ctx.profile_enable(False)
+        ref = {k: v.clone() for k, v in ref.items()}
+        out = tr.run()
+        for rep in range(3):
+            torch.cuda.synchronize()
+            for k in ref:
+                assert torch.equal(out[k], ref[k]), (T, rep, k)
+            x = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+            out["energy32"].fill_(-1.0)
+            out["assign"].fill_(-7)
+            torch.cuda.synchronize()
+            assert float(x) == float(x)
+            tr.run(out)
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(out[k], ref[k]), (T, k)
+        tr.close()
