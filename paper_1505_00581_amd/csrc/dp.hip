@@ -313,8 +313,10 @@ __device__ __forceinline__ Cands cands_of(const MatchView& a, int j) {
 }
 
 // Value table of step i (cells V_i(a_{i-1}, a_i), i = 1..M-2) inside the
-// matching's scratch vt [M-2][vs][vs] (with dummies, row and column K hold
-// the epsilon cells).
+// matching's scratch vt [M-2][vs][vs], stored by column: V_i(r, c) at c * vs +
+// r, so that backtracking reads the values of one column (every predecessor of
+// the chosen cell) contiguously (with dummies, index K holds the epsilon state
+// on either side).
 __device__ __forceinline__ float* vtable(float* vt, const MatchView& a, int i) {
   return vt + (long long)(i - 1) * a.vs * a.vs;
 }
@@ -428,7 +430,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
         const float q = a.lambda2 * fabsf(static_cast<float>(dtm - (tp - tr)));
         vr[s] = (sh.cu[0][r] + sh.cu[1][col]) + q;
         ar[s] = neg_dir<DEGEN>(xr, xa);
-        if (valid) vt[r * VS + col] = vr[s];
+        if (valid) vt[col * VS + r] = vr[s];
       }
     }
     if constexpr (DUMMY) {
@@ -437,12 +439,12 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
         if (lane < sh.ck[1]) {
           const float e = cw + sh.cu[1][lane];
           sh.de[1][lane] = e;
-          vt[Kc * VS + lane] = e;
+          vt[lane * VS + Kc] = e;
         }
         if (lane < sh.ck[0]) {
           const float f = sh.cu[0][lane] + cw;
           sh.df[1][lane] = f;
-          vt[lane * VS + Kc] = f;
+          vt[Kc * VS + lane] = f;
         }
         if (lane == 0) {
           sh.dg[1] = cw + cw;
@@ -555,7 +557,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           }
           const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
           vnew = (sh.cu[s0][col] + q) + best;
-          if (valid && vt) vt[r * VS + col] = vnew;
+          if (valid && vt) vt[col * VS + r] = vnew;
         }
       } else {
         if (ch < nch) {
@@ -611,7 +613,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           }
           const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
           vnew = (sh.cu[s0][col] + q) + best;
-          if (valid && vt) vt[r * VS + col] = vnew;
+          if (valid && vt) vt[col * VS + r] = vnew;
         }
       }
       vr[s] = vnew;
@@ -630,7 +632,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           for (int k = lo; k < hi; ++k) m = fminf(m, sh.va[k * KL + lane].x);
           const float v = cw + m;
           sh.df[cur][lane] = v;
-          if (vt) vt[lane * VS + Kc] = v;
+          if (vt) vt[Kc * VS + lane] = v;
         }
         float m = lane < Kq ? sh.df[prv][lane] : INF;
         for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
@@ -638,7 +640,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
         if (lane < Kn) {
           const float v = sh.cu[s0][lane] + m;
           sh.de[cur][lane] = v;
-          if (vt) vt[Kc * VS + lane] = v;
+          if (vt) vt[lane * VS + Kc] = v;
         }
         if (lane == 0) {
           sh.dg[cur] = cw + m;
@@ -708,53 +710,79 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
 // the forward pass's arithmetic and keeps the lowest index of the minimum.
 // With dummies r and c may be kEps; the epsilon predecessor comes last, so it
 // is taken only when its term is strictly smaller.
+//
+// The candidates of a list do not depend on the path, so each lane holds one
+// candidate (node, frame, coordinates) of the three lists of the current
+// step, and the next list is fetched while the current step runs; the chosen
+// nodes' data come from their lanes by shuffles.  The one read that waits for
+// the previous step's choice is the value-table column of the chosen cell.
+struct LaneCand {
+  int node;   // scene node of this lane's candidate, -1 past the list
+  int t;      // its frame
+  float2 xy;  // its coordinates
+  int n;      // list length
+};
+
+__device__ __forceinline__ LaneCand lane_cand(const MatchView& a, int j, int lane) {
+  const Cands q = cands_of(a, j);
+  LaneCand L;
+  L.n = q.count();
+  L.node = lane < L.n ? q.node(lane) : -1;
+  L.t = L.node >= 0 ? ro(a.s.t + L.node) : 0;
+  L.xy = L.node >= 0 ? ro(a.s.xy + L.node) : make_float2(0.f, 0.f);
+  return L;
+}
+
 template <bool DEGEN, bool DUMMY = false>
 __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int c, int lane,
                                int32_t* out) {
   const int M = a.m.M, Kc = a.sp.K, VS = a.vs;
   const int T = pair_limit(a.sp), TS = span_limit(a.sp);
   const float INF = __builtin_inff();
-  auto node_of = [&](const Cands& q, int idx) { return DUMMY && idx == kEps ? kDummyNode : q.node(idx); };
-  Cands cc = cands_of(a, M - 1);
-  Cands cr = cands_of(a, M - 2);
-  if (lane == 0) {
-    out[M - 1] = node_of(cc, c);
-    out[M - 2] = node_of(cr, r);
+  // candidate index idx of a list held in lanes -> its node (dummy: kDummyNode)
+  auto node_at = [&](const LaneCand& L, int idx) {
+    return DUMMY && idx == kEps ? kDummyNode : __shfl(L.node, idx);
+  };
+  LaneCand Lc = lane_cand(a, M - 1, lane);
+  LaneCand Lr = lane_cand(a, M - 2, lane);
+  LaneCand Lk = lane_cand(a, M - 3, lane);
+  {
+    const int nc0 = node_at(Lc, c), nr0 = node_at(Lr, r);
+    if (lane == 0) {
+      out[M - 1] = nc0;
+      out[M - 2] = nr0;
+    }
   }
   for (int i = M - 1; i >= 2; --i) {
-    const Cands ck = cands_of(a, i - 2);
-    const int nk = ck.count();
+    const int nk = Lk.n;
     const float* vp = vtable(vtm, a, i - 1);
+    // the column of the chosen cell: V_{i-1}(k, r) for every candidate k
+    float vcol = INF;
+    if (lane < nk && !(DUMMY && r == kEps)) vcol = vp[r * VS + lane];
+    // the next list, fetched while this step runs
+    LaneCand Ln;
+    if (i >= 3) Ln = lane_cand(a, i - 3, lane);
     float tot = INF, teps = INF;
     if (DUMMY && r == kEps) {
       // V_i(eps, .) = ... + min(V_{i-1}(eps, eps), min_k V_{i-1}(k, eps))
-      if (lane < nk) tot = vp[lane * VS + Kc];
+      if (lane < nk) tot = vp[Kc * VS + lane];
       teps = vp[Kc * VS + Kc];
     } else {
-      const int nr = cr.node(r);
-      const float2 xr = ro(a.s.xy + nr);
-      const int tr = ro(a.s.t + nr);
-      if (DUMMY) teps = vp[Kc * VS + r];
+      const float2 xr = make_float2(__shfl(Lr.xy.x, r), __shfl(Lr.xy.y, r));
+      const int tr = __shfl(Lr.t, r);
+      if (DUMMY) teps = vp[r * VS + Kc];
       if (DUMMY && c == kEps) {
         // V_i(r, eps) = l1 W^d + min(V_{i-1}(eps, r), min_k V_{i-1}(k, r))
-        if (lane < nk && admissible(ro(a.s.t + ck.node(lane)), tr, T)) tot = vp[lane * VS + r];
+        if (lane < nk && admissible(Lk.t, tr, T)) tot = vcol;
       } else {
-        const int nc = cc.node(c);
-        const float2 xa = ro(a.s.xy + nc);
-        const int tc = ro(a.s.t + nc);
+        const float2 xa = make_float2(__shfl(Lc.xy.x, c), __shfl(Lc.xy.y, c));
+        const int tc = __shfl(Lc.t, c);
         const float2 th = ro(a.theta + i);
         const bool same = xa.x == xr.x && xa.y == xr.y;
         float bm, be;
         cell_brackets(th, -neg_dir<DEGEN>(xr, xa), bm, be);
-        if (lane < nk) {
-          const int nkn = ck.node(lane);
-          const int tk = ro(a.s.t + nkn);
-          if (admissible(tk, tr, T) && span_ok(tk, tc, TS)) {
-            const float2 pk = ro(a.s.xy + nkn);
-            const float v = vp[lane * VS + r];
-            tot = relax<DEGEN>(v, neg_dir<DEGEN>(pk, xr), neg_dir<DEGEN>(pk, xa), bm, be, th, same, a.w);
-          }
-        }
+        if (lane < nk && admissible(Lk.t, tr, T) && span_ok(Lk.t, tc, TS))
+          tot = relax<DEGEN>(vcol, neg_dir<DEGEN>(Lk.xy, xr), neg_dir<DEGEN>(Lk.xy, xa), bm, be, th, same, a.w);
       }
     }
     int bk = lane;
@@ -764,11 +792,13 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
       if (ot < tot || (ot == tot && ok < bk)) { tot = ot; bk = ok; }
     }
     if (DUMMY && teps < tot) bk = kEps;
-    if (lane == 0) out[i - 2] = node_of(ck, bk);
+    const int nbk = node_at(Lk, bk);
+    if (lane == 0) out[i - 2] = nbk;
     c = r;
     r = bk;
-    cc = cr;
-    cr = ck;
+    Lc = Lr;
+    Lr = Lk;
+    if (i >= 3) Lk = Ln;
   }
 }
 
