@@ -169,20 +169,38 @@ def cpu_baseline(workload, target_s: float, seed: int):
 
 
 def cpu_model_name() -> str:
-    """The host CPU's model name as lscpu prints it (else /proc/cpuinfo's)."""
+    """The host CPU as lscpu describes it: model name, with the BIOS model
+    name, family/model/stepping and sockets when lscpu gives them (some hosts
+    print only a generic model name), else /proc/cpuinfo's model name."""
     import subprocess
+    fields = {}
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
         for ln in out.splitlines():
-            if ln.strip().startswith("Model name:"):
-                return ln.split(":", 1)[1].strip()
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                fields.setdefault(k.strip(), v.strip())
     except (OSError, subprocess.SubprocessError):
         pass
+    proc = ""
     try:
         with open("/proc/cpuinfo") as f:
-            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+            proc = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
-        return ""
+        pass
+    name = fields.get("Model name") or proc
+    extra = []
+    if fields.get("BIOS Model name") and fields["BIOS Model name"] != name:
+        extra.append("BIOS: " + fields["BIOS Model name"])
+    if proc and proc != name:
+        extra.append("cpuinfo: " + proc)
+    if "CPU family" in fields:
+        extra.append(f"family {fields['CPU family']} model {fields.get('Model', '?')} "
+                     f"stepping {fields.get('Stepping', '?')}")
+    if "Socket(s)" in fields:
+        extra.append(f"{fields['Socket(s)']} socket(s), {fields.get('Core(s) per socket', '?')} cores each, "
+                     f"{fields.get('Thread(s) per core', '?')} threads per core")
+    return name + (" (" + "; ".join(extra) + ")" if extra else "")
 
 
 def sample_parity(solved, outs, outs_bf):

@@ -69,7 +69,8 @@ extern "C" {
 
 /* ---- limits ------------------------------------------------------------- */
 /* Candidate cap: one 64-lane wavefront covers the candidates of one model
- * point. */
+ * point.  A larger k_max gives STM_EUNSUPPORTED; the trellis over a scene
+ * block (stm_trellis_*) searches every node of the block instead. */
 #define STM_K_LIMIT 64
 
 /* ---- flags (stm_params.flags) ------------------------------------------- */
@@ -182,8 +183,9 @@ STM_API int stm_offsets(stm_ctx* ctx, const stm_points* model, const stm_points*
  * Errors: STM_EINVAL for n < 3 (model) or < 1 (scene), dim mismatch, model
  * frames not strictly increasing, scene frames decreasing or outside
  * [0, n_frames), non-finite coordinates or descriptors, window < 0, k_max
- * outside 1..STM_K_LIMIT, a negative or non-finite lambda or w_dummy (with
- * STM_DUMMY), or an offset range outside [0, n_frames - span). */
+ * < 1, a negative or non-finite lambda or w_dummy (with STM_DUMMY), or an
+ * offset range outside [0, n_frames - span); STM_EUNSUPPORTED for k_max above
+ * STM_K_LIMIT. */
 STM_API int stm_match(stm_ctx* ctx, const stm_points* model, const stm_points* scene,
               const stm_params* params, int32_t tau_begin, int32_t tau_end,
               float* energy32, double* energy64, double* energy_u64, int32_t* assign,

@@ -55,7 +55,10 @@ int check_shapes(const stm_points* m, const stm_points* s, const stm_params* p) 
   if (m->reserved != 0 || s->reserved != 0) return fail(STM_EINVAL, "reserved field must be 0");
   if (!m->xy || !m->t || !m->desc || !s->xy || !s->t || !s->desc)
     return fail(STM_EINVAL, "null point array");
-  if (p->k_max < 1 || p->k_max > STM_K_LIMIT) return fail(STM_EINVAL, "k_max outside 1..64");
+  if (p->k_max < 1) return fail(STM_EINVAL, "k_max below 1");
+  if (p->k_max > STM_K_LIMIT)
+    return fail(STM_EUNSUPPORTED, "k_max above 64: per-offset lists hold at most 64 candidates (one wavefront); "
+                                  "the trellis over a scene block (stm_trellis_*) searches every node");
   if (p->window < 0) return fail(STM_EINVAL, "window < 0");
   if (!finite_lambda(p->lambda1) || !finite_lambda(p->lambda2) || !finite_lambda(p->lambda3))
     return fail(STM_EINVAL, "lambdas must be finite and >= 0");

@@ -60,7 +60,6 @@ def test_null_context_is_einval_after_argument_checks():
 
 @pytest.mark.parametrize("mutate,needle", [
     (lambda m, s, p: setattr(p, "k_max", 0), "k_max"),
-    (lambda m, s, p: setattr(p, "k_max", 65), "k_max"),
     (lambda m, s, p: setattr(p, "window", -1), "window"),
     (lambda m, s, p: setattr(p, "lambda2", -0.1), "lambda"),
     (lambda m, s, p: setattr(p, "lambda3", float("nan")), "lambda"),
@@ -80,6 +79,13 @@ def test_invalid_inputs_rejected_on_host(mutate, needle):
     rc, msg = _call_match(m, s, p)
     assert rc == stm.STM_EINVAL, msg
     assert needle in msg
+
+
+def test_k_max_above_64_unsupported():
+    m, s, p = _good()
+    p.k_max = 65
+    rc, msg = _call_match(m, s, p)
+    assert rc == stm.STM_EUNSUPPORTED and "k_max" in msg and "trellis" in msg
 
 
 def test_span_with_dummies_unsupported():
