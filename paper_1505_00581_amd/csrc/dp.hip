@@ -830,7 +830,7 @@ __device__ __forceinline__ float* scratch_of(const DPLaunch& a, int tl) {
 
 template <int NW, bool DEGEN, int KL, bool DUMMY = false, bool PACKED = false>
 __global__ __launch_bounds__(NW * 64)
-__attribute__((amdgpu_waves_per_eu(KL == kMaxList && NW == 8 ? (DUMMY || PACKED ? 4 : 6) : 1)))
+__attribute__((amdgpu_waves_per_eu(KL == kMaxList && NW == 8 ? 4 : 1)))
 void k_dp(DPLaunch a) {
   __shared__ DPShared<NW, KL, DUMMY, PACKED> sh;
   const int tl = blockIdx.x;
@@ -896,12 +896,14 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
 // each leaving the other waves idle.  The fast variant takes every item; an
 // item whose matching has coincident points is appended to the degenerate
 // list instead of being backtracked, and the degenerate variant (a second
-// launch) takes the items of that list.  Occupancy targets: the LDS of one
-// matching allows three 8-wave workgroups per CU (two with the dummy vectors
-// or the packed schedule).
+// launch) takes the items of that list.  Occupancy target: two 8-wave
+// workgroups per CU (four waves per SIMD), which leaves 128 registers per lane;
+// the LDS of one matching would allow three, but at 80 registers the kernel
+// spills and runs slower (1.3% on the realistic workload, 3.9% on the batched
+// one).
 template <int NW, bool DEGEN, int KL = kMaxList, bool DUMMY = false, bool PACKED = false>
 __global__ __launch_bounds__(NW * 64)
-__attribute__((amdgpu_waves_per_eu(DUMMY || PACKED ? 4 : (NW >= 8 ? 6 : 3))))
+__attribute__((amdgpu_waves_per_eu(DUMMY || PACKED ? 4 : (NW >= 8 ? 4 : 3))))
 void k_dp_persistent(BatchLaunch b) {
   __shared__ DPShared<NW, KL, DUMMY, PACKED> sh;
   __shared__ int item_sh;

@@ -41,7 +41,7 @@ struct stm_plan {
   int batch = 1;                        // items a workgroup takes at a time
   std::vector<int64_t> row_off, asg_off;
   int n_cu = 0;
-  int waves = 8, wgs_per_cu = 3;
+  int waves = 8, wgs_per_cu = 2;
   int batch_req = 0;                    // requested batch (0: the largest that fits)
   int sched = -1;                       // schedule: -1 the rule, 0 dense, 1 packed
   // graph of the last run
@@ -848,7 +848,7 @@ int stm_plan_autotune(stm_plan* p, const char* cache_path, int32_t n_sample, int
   const hipStream_t st = p->stream;
   STM_HIP(hipStreamSynchronize(st));
   if (p->n_items == 0) {
-    int rc = plan_set_shape(p, 8, 3, 0, -1);
+    int rc = plan_set_shape(p, 8, 2, 0, -1);
     if (!rc) report(0);
     return rc;
   }
@@ -885,7 +885,7 @@ int stm_plan_autotune(stm_plan* p, const char* cache_path, int32_t n_sample, int
   hipEvent_t e0, e1;
   STM_HIP(hipEventCreate(&e0));
   STM_HIP(hipEventCreate(&e1));
-  Cand best{8, 3, 0, -1};
+  Cand best{8, 2, 0, -1};
   double best_ms = 1e300;
   for (const Cand& c : cands) {
     if (plan_set_shape(p, c.w, c.g, c.b, c.s)) {  // a batch whose scratch does not fit: skip it
