@@ -409,8 +409,9 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
   __syncthreads();
 
   float vr[RPW], ar[RPW];
+  int pi[RPW];  // LDS index (row * KL + column) of each slot's cell, -1: none
 #pragma unroll
-  for (int s = 0; s < RPW; ++s) { vr[s] = INF; ar[s] = 0.f; }
+  for (int s = 0; s < RPW; ++s) { vr[s] = INF; ar[s] = 0.f; pi[s] = -1; }
 
   // ---- the first pair (points 0, 1) ------------------------------------------
   {
@@ -431,6 +432,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
         vr[s] = (sh.cu[0][r] + sh.cu[1][col]) + q;
         ar[s] = neg_dir<DEGEN>(xr, xa);
         if (valid) vt[col * VS + r] = vr[s];
+        pi[s] = valid ? r * KL + col : -1;
       }
     }
     if constexpr (DUMMY) {
@@ -467,10 +469,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
 #pragma unroll
       for (int s = 0; s < RPW; ++s) {
         const int ch = wv + NW * s;
-        if (ch < nprev) {
-          int r, col;
-          if (slot_cell(prv, ch, r, col)) sh.va[r * KL + col] = make_float2(vr[s], ar[s]);
-        }
+        if (ch < nprev && pi[s] >= 0) sh.va[pi[s]] = make_float2(vr[s], ar[s]);
       }
     }
     if (wv == kBuilder) schedule(sh.ctt[s1], Kp, sh.ctt[s0], Kn, sh.ctt[s2], Kq, cur);
@@ -558,6 +557,9 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
           vnew = (sh.cu[s0][col] + q) + best;
           if (valid && vt) vt[col * VS + r] = vnew;
+          pi[s] = valid ? r * KL + col : -1;
+        } else {
+          pi[s] = -1;
         }
       } else {
         if (ch < nch) {
@@ -614,6 +616,9 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
           vnew = (sh.cu[s0][col] + q) + best;
           if (valid && vt) vt[col * VS + r] = vnew;
+          pi[s] = valid ? r * KL + col : -1;
+        } else {
+          pi[s] = -1;
         }
       }
       vr[s] = vnew;
