@@ -229,7 +229,7 @@ def sample_parity(solved, outs, outs_bf):
     return rows
 
 
-def bench_batched(ctx, seed: int, runs: int, cache_path: str):
+def bench_batched(ctx, seed: int, runs: int, cache_path: str, per_pair: bool = True):
     """The batched uneven workload: 64 models (M in 30..150) against 8 scenes
     (500..3000 frames, 10..30 points per frame), density caps K in [8, 64],
     every offset of every pair (~8.0e5 matchings) in one autotuned persistent
@@ -285,6 +285,10 @@ def bench_batched(ctx, seed: int, runs: int, cache_path: str):
                 kernel="k_dp_persistent (fast variant + degenerate re-run)", avg_launch_ms=round(1e3 * avg_s, 3),
                 ops_per_relax=OPS_PER_RELAX, counters=measured_counters(COUNTERS_FILE_BATCHED))
     log(f"  recursion launch {1e3 * avg_s:.1f} ms, {roof['frac']:.3f} of the VALU ceiling")
+    if not per_pair:  # profiling runs: the plan only
+        plan.close()
+        return dict(workload="batched_uneven (plan only)", matchings=int(n), value=round(n / dt, 2),
+                    unit="matchings/s", ms_per_run=round(dt * 1e3, 3), tuning=tune, roofline=roof)
     # baseline: one stm_match call per (model, scene) pair, no graph
     base_out = []
     for i, j in pairs:
@@ -678,6 +682,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched uneven workload (persistent plan vs per-pair launches)")
     ap.add_argument("--batched-runs", type=int, default=3)
+    ap.add_argument("--no-per-pair", action="store_true",
+                    help="batched section without its per-pair launch baseline (for counter passes)")
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "stm_tuning_cache.json"))
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruner section")
     ap.add_argument("--no-chains", action="store_true", help="skip the multiple-points (chains) section")
@@ -870,7 +876,7 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = bench_batched(ctx, args.seed, args.batched_runs, args.tune_cache)
+        batched = bench_batched(ctx, args.seed, args.batched_runs, args.tune_cache, not args.no_per_pair)
 
     sec = elapsed / args.steps
     line = {
