@@ -333,8 +333,10 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, plan_ms_per_step: fl
     from the exact recursion on other seeds (realistic single-scene
     workloads), then per list size k: the pruned matching's time per step
     (inference, recursion on the pruned lists, exact fallback, re-score) and
-    its energy gap, recall and fallback rate against the exact matching, beside
-    the U-ranked and time-nearest top-k lists."""
+    its energy gap, recall and fallback rate against the exact matching under
+    the learned frames-first rule, beside the U-ranked lists and the
+    time-nearest rule (the pruner's default, no network, timed through the same
+    entry points with the same exact fallback)."""
     import torch
 
     import paper_1505_00581_amd as stm
@@ -369,35 +371,30 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, plan_ms_per_step: fl
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - ta) / steps
 
-    per_k = {}
-    for k in topks:
-        outs = []
-        for dm in dms:
-            outs.append(pr.match(dm, ds, p, topk=k))
+    def time_per_model(k):
+        outs = [pr.match(dm, ds, p, topk=k) for dm in dms]
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for _ in range(steps):
             for dm, o in zip(dms, outs):
                 pr.match(dm, ds, p, topk=k, out=o)
         torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - ta) / steps
-        # the rule without a network: the windowed lists capped at k (stm_match, k_max = k)
-        pk = dataclasses.replace(p, k_max=k)
-        touts = [ctx.match(dm, ds, pk) for dm in dms]
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(steps):
-            for dm, o in zip(dms, touts):
-                ctx.match(dm, ds, pk, out=o)
-        torch.cuda.synchronize()
-        ms_t = 1e3 * (time.perf_counter() - ta) / steps
-        # the same in one persistent plan run per step (lists, recursion and
-        # exact fallback on the device), against the exact plan run
+        return 1e3 * (time.perf_counter() - ta) / steps
+
+    default_rule = pr.rule
+    per_k = {}
+    for k in topks:
+        # the learned score (frames-first rule): per-model calls and one
+        # persistent plan run per step (lists, recursion and exact fallback on
+        # the device), against the exact ones
+        pr.set_rule(stm.Pruner.FRAMES_FIRST)
+        ms = time_per_model(k)
         ms_pp = time_plan(lambda o: plan.run_pruned(pr, k, out=o))
-        tplan = stm.Plan(ctx, dms, [ds], pairs, pk)
-        tplan.autotune(tune_cache)
-        ms_tp = time_plan(lambda o: tplan.run(o))
-        tplan.close()
+        # the rule without a network (the pruner's default): the windowed
+        # lists capped at k, with the same exact fallback
+        pr.set_rule(stm.Pruner.TIME_NEAREST)
+        ms_t = time_per_model(k)
+        ms_tp = time_plan(lambda o: plan.run_pruned(pr, k, out=o))
         per_k[str(k)] = dict(ms_per_step=round(ms, 3), matchings_per_s=round(n_match / ms * 1e3, 1),
                              speedup_vs_exact=round(exact_ms_per_step / ms, 3),
                              plan_ms_per_step=round(ms_pp, 3),
@@ -411,8 +408,14 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, plan_ms_per_step: fl
         log(f"  k={k}: {ms:.2f} ms/step per model (exact {exact_ms_per_step:.2f}), plan {ms_pp:.2f} "
             f"(exact plan {plan_ms_per_step:.2f}, time-nearest plan {ms_tp:.2f}), mlp {summary[k]['mlp']}, "
             f"time-nearest {summary[k]['time_nearest']}")
+    pr.set_rule(default_rule)
+    names = {stm.Pruner.SCORE: "score", stm.Pruner.FRAMES_FIRST: "frames_first",
+             stm.Pruner.TIME_NEAREST: "time_nearest"}
     ok = [k for k in topks if summary[k]["mlp"]["mean_gap"] <= 0.01]
     best = min(ok) if ok else None
+    ok_t = [k for k in topks if summary[k]["time_nearest"]["mean_gap"] <= 0.01]
+    best_t = min(ok_t) if ok_t else None
+    tn = per_k[str(best_t)]["time_nearest"] if best_t else {}
     plan.close()
     pr.close()
     return dict(k_exact=int(p.k_max), train=dict(groups=n_train, seeds=f"{train_seeds[0]}-{train_seeds[-1]}",
@@ -420,9 +423,12 @@ def bench_pruned(ctx, w, dms, ds, exact_ms_per_step: float, plan_ms_per_step: fl
                                                  train_s=round(t2 - t1, 2),
                                                  loss=[round(x, 4) for x in hist]),
                 test="the benchmark workload's own seed (held out from the training seeds)",
+                default_rule=names[default_rule],
                 per_k=per_k, gap_target=0.01, smallest_k_within_target=best,
                 speedup_at_target=(per_k[str(best)]["speedup_vs_exact"] if best else None),
-                plan_speedup_at_target=(per_k[str(best)]["plan_speedup_vs_exact_plan"] if best else None))
+                plan_speedup_at_target=(per_k[str(best)]["plan_speedup_vs_exact_plan"] if best else None),
+                time_nearest_at_target=dict(k=best_t, speedup=tn.get("speedup_vs_exact"),
+                                            plan_speedup=tn.get("plan_speedup_vs_exact_plan")))
 
 
 def bench_trellis(ctx, steps: int, t_values=(10, 0), model_counts=(1, 50)):

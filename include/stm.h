@@ -485,14 +485,25 @@ STM_API int64_t stm_pruner_num_params(int32_t dim);
 STM_API int stm_pruner_create(stm_ctx* ctx, int32_t dim, stm_pruner** out);
 STM_API void stm_pruner_destroy(stm_pruner* pruner);
 
-/* Selection rule of the kept candidates (the ranking of stm_pruner_infer and
- * stm_match_pruned):
+/* Selection rule of the kept candidates (the ranking of stm_pruner_infer,
+ * stm_match_pruned and stm_plan_run_pruned):
  *   STM_PRUNE_SCORE         the topk highest scores (lower slot first on ties);
- *   STM_PRUNE_FRAMES_FIRST  (default) candidates in frames nearer the shifted
- *                           model frame first (|t'_n - (tau + t_i - t_0)|), the
- *                           score rule among candidates of one frame distance. */
+ *   STM_PRUNE_FRAMES_FIRST  candidates in frames nearer the shifted model frame
+ *                           first (|t'_n - (tau + t_i - t_0)|), the score rule
+ *                           among candidates of one frame distance;
+ *   STM_PRUNE_TIME_NEAREST  (default) the first topk candidates of the windowed
+ *                           rule, i.e. nearer frames first, lower slot inside a
+ *                           frame; the network is not evaluated by
+ *                           stm_match_pruned / stm_plan_run_pruned, which then
+ *                           equal stm_match at k_max = topk plus the exact
+ *                           fallback.  On the synthetic workloads the learned
+ *                           score reaches the 1% mean-gap target at the same
+ *                           list size as this rule and costs the inference, so
+ *                           this rule is the default; the two score rules stay
+ *                           selectable for descriptors that carry signal. */
 #define STM_PRUNE_SCORE 0
 #define STM_PRUNE_FRAMES_FIRST 1
+#define STM_PRUNE_TIME_NEAREST 2
 STM_API int stm_pruner_set_rule(stm_pruner* pruner, int32_t rule);
 
 /* Copies n = stm_pruner_num_params(dim) FP32 parameters from / to host

@@ -642,7 +642,7 @@ class Pruner:
         h = ctypes.c_void_p()
         _check(self._lib.stm_pruner_create(ctx.handle, self.dim, ctypes.byref(h)))
         self.handle = h
-        self.rule = Pruner.FRAMES_FIRST
+        self.rule = Pruner.TIME_NEAREST
 
     def close(self):
         if getattr(self, "handle", None):
@@ -655,10 +655,12 @@ class Pruner:
         except Exception:
             pass
 
-    SCORE, FRAMES_FIRST = 0, 1
+    SCORE, FRAMES_FIRST, TIME_NEAREST = 0, 1, 2
 
     def set_rule(self, rule: int):
-        """Selection rule: Pruner.SCORE or Pruner.FRAMES_FIRST (the default)."""
+        """Selection rule: Pruner.SCORE, Pruner.FRAMES_FIRST or
+        Pruner.TIME_NEAREST (the default: the windowed rule's first topk, no
+        network evaluation in match_pruned / plan runs)."""
         _check(self._lib.stm_pruner_set_rule(self.handle, int(rule)))
         self.rule = int(rule)
 

@@ -67,7 +67,7 @@ struct stm_pruner {
   int dim = 0;
   long long n = 0;
   long long step = 0;  // Adam steps taken since the parameters were set
-  int rule = STM_PRUNE_FRAMES_FIRST;
+  int rule = STM_PRUNE_TIME_NEAREST;
   stmh::DevBuf theta, grad, am, av;
   // per-call scratch
   stmh::DevBuf groups, labels, node, phi, q, h1, h2, dz1, dz2, ds, loss, scores, part;

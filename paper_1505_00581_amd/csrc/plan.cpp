@@ -661,10 +661,9 @@ int plan_pruned_buffers(stm_plan* p, int dim, int kp) {
   return STM_OK;
 }
 
-int plan_enqueue_pruned(stm_plan* p, stm_pruner* P, int kp, float* e32, double* e64, double* eu, int32_t* asg,
-                        int32_t* fell, hipStream_t st) {
-  int rc;
-  if ((rc = plan_enqueue_tables(p, st))) return rc;
+// The pruner's lists of every (pair, offset, point): first-layer projections,
+// then one inference launch per pair.
+int plan_enqueue_lists(stm_plan* p, stm_pruner* P, int kp, hipStream_t st) {
   const int D = P->dim, NI = 2 * D + 8, dp = stm::bf16_padded_dim(D);
   const float* W1 = static_cast<const float*>(P->theta.p);
   const int mp = static_cast<int>((p->m_total + 15) / 16 * 16);
@@ -710,11 +709,22 @@ int plan_enqueue_pruned(stm_plan* p, stm_pruner* P, int kp, float* e32, double* 
     STM_HIP(stm::launch_pruner_infer(q_, st));
     off += G;
   }
+  return STM_OK;
+}
+
+int plan_enqueue_pruned(stm_plan* p, stm_pruner* P, int kp, float* e32, double* e64, double* eu, int32_t* asg,
+                        int32_t* fell, hipStream_t st) {
+  int rc;
+  if ((rc = plan_enqueue_tables(p, st))) return rc;
+  // the time-nearest rule keeps the windowed rule's first kp candidates: the
+  // recursion builds them itself (K = kp) and the network is not evaluated
+  const bool scored = P->rule != STM_PRUNE_TIME_NEAREST;
+  if (scored && (rc = plan_enqueue_lists(p, P, kp, st))) return rc;
   // the recursion on the pruned lists, then the exact one on the items they left infeasible
   int32_t* inf_count = p->counters + 3;
   STM_HIP(stm::launch_fill_i32(p->counters, 4, 0, st));
   if (fell) STM_HIP(stm::launch_fill_i32(fell, static_cast<int>(p->row_off.back()), 0, st));
-  stm::BatchLaunch b = plan_launch(p, p->pr_pairs_dev, p->items_dev, p->n_items, e32, asg);
+  stm::BatchLaunch b = plan_launch(p, scored ? p->pr_pairs_dev : p->pairs_dev, p->items_dev, p->n_items, e32, asg);
   b.sp.K = kp;
   STM_HIP(stm::launch_dp_persistent(b, p->n_cu * p->wgs_per_cu, st));
   STM_HIP(stm::launch_collect_infeasible(p->pairs_dev, p->items_dev, p->n_items, e32, p->pr_list, inf_count, fell,

@@ -500,9 +500,11 @@ __global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_e
     // rank: candidates ahead in the selection order.  Score rule: a higher
     // score, or an equal score and a lower slot.  Frames-first rule: a frame
     // nearer the shifted model frame, then the score rule inside a frame.
-    // Empty slots carry -inf and the largest frame distance: ranked last.
+    // Time-nearest rule: a nearer frame, then the lower slot (the score is
+    // not consulted).  Empty slots carry -inf and the largest frame distance:
+    // ranked last.
     const int df = n < 0 ? (1 << 25) : abs(s.t[n] - (gi.x + m.t[gi.y] - m.t[0]));
-    const unsigned long long key = select_key(rule ? df : (n < 0 ? 1 : 0), sc, lane);
+    const unsigned long long key = select_key(rule ? df : (n < 0 ? 1 : 0), rule == 2 ? 0.f : sc, lane);
     sh.key[wv][lane] = key;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -396,7 +396,8 @@ int stm_pruner_set_rule(stm_pruner* P, int32_t rule) {
   err().clear();
   int rc = check_pruner(P);
   if (rc) return rc;
-  if (rule != STM_PRUNE_SCORE && rule != STM_PRUNE_FRAMES_FIRST) return fail(STM_EINVAL, "unknown selection rule");
+  if (rule != STM_PRUNE_SCORE && rule != STM_PRUNE_FRAMES_FIRST && rule != STM_PRUNE_TIME_NEAREST)
+    return fail(STM_EINVAL, "unknown selection rule");
   P->rule = rule;
   return STM_OK;
 }
@@ -568,31 +569,36 @@ int stm_match_pruned(stm_ctx* ctx, stm_pruner* P, const stm_points* model, const
   if (o.fell) STM_HIP(stm::launch_fill_i32(o.fell, n_tau, 0, pr.st));
   if ((rc = grow(ctx, ctx->theta, (size_t)M * sizeof(float2), pr.st))) return rc;
   STM_HIP(stm::launch_model_angles(pr.m, static_cast<float2*>(ctx->theta.p), pr.st));
-  if ((rc = project(P, pr))) return rc;
+  // the time-nearest rule keeps the windowed rule's first topk candidates: the
+  // recursion builds them itself (K = topk) and the network is not evaluated
+  const bool scored = P->rule != STM_PRUNE_TIME_NEAREST;
+  if (scored && (rc = project(P, pr))) return rc;
 
   // pruned lists and the recursion on them, in chunks of offsets
   const int kp = std::min(topk, pr.sp.K);
   const int chunk = dp_chunk(ctx, pr, params, n_tau, kp, (size_t)std::max(1, (1 << 20) / M));
   if ((rc = dp_scratch(ctx, pr, params, chunk, kp))) return rc;
-  if ((rc = grow(ctx, P->cand, (size_t)chunk * M * kp * sizeof(int32_t), pr.st))) return rc;
-  if ((rc = grow(ctx, P->count, (size_t)chunk * M * sizeof(int32_t), pr.st))) return rc;
-  if ((rc = grow(ctx, P->node, (size_t)chunk * M * kSlots * sizeof(int32_t), pr.st))) return rc;
-  if ((rc = grow(ctx, P->phi, (size_t)chunk * M * kSlots * 8 * sizeof(float), pr.st))) return rc;
   stm::PrunerInfer q = infer_args(P, pr, kp);
-  q.cand = as<int32_t>(P->cand);
-  q.count = as<int32_t>(P->count);
-  q.node = as<int32_t>(P->node);
-  q.phi = as<float>(P->phi);
   stm::DPLaunch b = dp_base(ctx, pr, params);
   b.sp.K = kp;
-  b.cand = q.cand;
-  b.ccount = q.count;
-  b.cstride = kp;
+  if (scored) {
+    if ((rc = grow(ctx, P->cand, (size_t)chunk * M * kp * sizeof(int32_t), pr.st))) return rc;
+    if ((rc = grow(ctx, P->count, (size_t)chunk * M * sizeof(int32_t), pr.st))) return rc;
+    if ((rc = grow(ctx, P->node, (size_t)chunk * M * kSlots * sizeof(int32_t), pr.st))) return rc;
+    if ((rc = grow(ctx, P->phi, (size_t)chunk * M * kSlots * 8 * sizeof(float), pr.st))) return rc;
+    q.cand = as<int32_t>(P->cand);
+    q.count = as<int32_t>(P->count);
+    q.node = as<int32_t>(P->node);
+    q.phi = as<float>(P->phi);
+    b.cand = q.cand;
+    b.ccount = q.count;
+    b.cstride = kp;
+  }
   for (int c0 = 0; c0 < n_tau; c0 += chunk) {
     const int nc = std::min(chunk, n_tau - c0);
     q.tau0 = tau_begin + c0;
     q.n_groups = (long long)nc * M;
-    STM_HIP(stm::launch_pruner_infer(q, pr.st));
+    if (scored) STM_HIP(stm::launch_pruner_infer(q, pr.st));
     b.tau0 = tau_begin + c0;
     b.n_tau = nc;
     if ((rc = dp_rows(pr, params, b, o.e32 + c0, o.e64 ? o.e64 + c0 : nullptr, o.eu ? o.eu + c0 : nullptr,

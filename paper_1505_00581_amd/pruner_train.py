@@ -124,10 +124,20 @@ def _gap_stats(e, ex, fin):
                 total_gap=float((e[fin] - ex[fin]).sum() / max(ex[fin].sum(), 1e-12)))
 
 
-def evaluate(ctx, pruner, model, scene, params, topks=(16,), baselines: bool = True) -> dict:
+def evaluate(ctx, pruner, model, scene, params, topks=(16,), baselines: bool = True, rule: int = 1) -> dict:
     """Energy gap, recall of the exact optimum's choices and fallback rate of
-    the pruned matching at each k in topks (and of the baselines, with the same
-    exact fallback)."""
+    the pruned matching at each k in topks under selection rule `rule` (the
+    learned frames-first rule unless told otherwise; the pruner's own rule is
+    restored afterwards), and of the baselines, with the same exact fallback."""
+    saved = pruner.rule
+    pruner.set_rule(rule)
+    try:
+        return _evaluate(ctx, pruner, model, scene, params, topks, baselines)
+    finally:
+        pruner.set_rule(saved)
+
+
+def _evaluate(ctx, pruner, model, scene, params, topks, baselines) -> dict:
     ex = ctx.match(model, scene, params)
     e_ex, a_ex = _host(ex["energy32"]).astype(np.float64), _host(ex["assign"])
     fin = np.isfinite(e_ex)

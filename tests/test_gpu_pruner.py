@@ -279,7 +279,7 @@ def test_training_lowers_the_loss(ctx, mid):
     pr.close()
 
 
-@pytest.mark.parametrize("which,rule", [("small", 0), ("mid", 0), ("small", 1), ("mid", 1)])
+@pytest.mark.parametrize("which,rule", [("small", 0), ("mid", 0), ("small", 1), ("mid", 1), ("mid", 2)])
 def test_infer_bf16_and_topk(ctx, request, which, rule):
     model, scene, p = request.getfixturevalue(which)
     pr = stm.Pruner(ctx, model.dim)
@@ -300,13 +300,15 @@ def test_infer_bf16_and_topk(ctx, request, which, rule):
             k = int(valid[g].sum())
             tau, i = groups[g]
             df = np.abs(scene.t[node[g, :k]] - (tau + model.t[i] - model.t[0]))
-            order = sorted(range(k), key=lambda a: ((df[a] if rule else 0), -sb[g, a], a))[:topk]
+            order = sorted(range(k), key=lambda a: ((df[a] if rule else 0), (-sb[g, a] if rule != 2 else 0), a))
+            order = order[:topk]
             want = np.sort(node[g, order])
             assert count[g] == min(topk, k)
             np.testing.assert_array_equal(cand[g, :count[g]], want)
     say(f"  {which}: bf16 score err {err:.3e} (scale {scale:.3f})")
     # the zero network scores every candidate 0: the score rule keeps the
-    # first slots, the frames-first rule the windowed rule's first k
+    # first slots, the frames-first and time-nearest rules the windowed rule's
+    # first k
     pr.set_params(np.zeros(pr.n_params, np.float32))
     sb, cand, count = pr.infer(model, scene, p, groups, 4)
     for g in range(len(groups)):
@@ -327,6 +329,7 @@ def test_zero_network_frames_first_is_the_windowed_rule(ctx, request, which, top
     wherever that is feasible (elsewhere the exact fallback answers)."""
     model, scene, p = request.getfixturevalue(which)
     pr = stm.Pruner(ctx, model.dim)
+    pr.set_rule(stm.Pruner.FRAMES_FIRST)
     pr.set_params(np.zeros(pr.n_params, np.float32))
     got = pr.match(model, scene, p, topk=topk)
     small = ctx.match(model, scene, dataclasses.replace(p, k_max=topk))
@@ -334,6 +337,33 @@ def test_zero_network_frames_first_is_the_windowed_rule(ctx, request, which, top
     assert (got["fell_back"][ok] == 0).all() and (got["fell_back"][~ok] == 1).all()
     for k in ("energy32", "energy64", "assign"):
         np.testing.assert_array_equal(got[k][ok], small[k][ok])
+    pr.close()
+
+
+@pytest.mark.parametrize("which,topk,device", [("small", 6, False), ("mid", 16, True), ("small", 1, False)])
+def test_time_nearest_rule_is_match_at_k(ctx, request, which, topk, device):
+    """The time-nearest rule (the pruner's default) ignores the network: with
+    random weights the pruned matching is stm_match at k_max = k where that is
+    feasible, and the exact matching (fell_back = 1) elsewhere."""
+    import torch
+    model, scene, p = request.getfixturevalue(which)
+    pr = stm.Pruner(ctx, model.dim)
+    assert pr.rule == stm.Pruner.TIME_NEAREST
+    pr.set_params(synth.pruner_init(model.dim, 21))
+    if device:
+        got = pr.match(stm.DevicePoints.from_host(model), stm.DevicePoints.from_host(scene), p, topk=topk)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() if hasattr(v, "cpu") else v for k, v in got.items()}
+    else:
+        got = pr.match(model, scene, p, topk=topk)
+    small = ctx.match(model, scene, dataclasses.replace(p, k_max=topk))
+    ex = ctx.match(model, scene, p)
+    ok = np.isfinite(small["energy32"])
+    assert (got["fell_back"][ok] == 0).all() and (got["fell_back"][~ok] == 1).all()
+    for k in ("energy32", "energy64", "energy_u64", "assign"):
+        np.testing.assert_array_equal(got[k][ok], small[k][ok])
+        np.testing.assert_array_equal(got[k][~ok], ex[k][~ok])
+    say(f"  {which} top-{topk}: {int(ok.sum())} offsets on the time-nearest lists, {int((~ok).sum())} fell back")
     pr.close()
 
 
@@ -398,7 +428,8 @@ def test_pruned_keeping_everything_equals_exact(ctx, small):
     pr.close()
 
 
-@pytest.mark.parametrize("which,topk,rule", [("small", 6, 1), ("mid", 16, 1), ("small", 6, 0), ("small", 1, 0)])
+@pytest.mark.parametrize("which,topk,rule", [("small", 6, 1), ("mid", 16, 1), ("small", 6, 0), ("small", 1, 0),
+                                             ("mid", 16, 2)])
 def test_pruned_against_oracle_and_fallback(ctx, request, which, topk, rule):
     """Pruned matchings against the oracle on the same lists; with the score
     rule and one candidate per point most offsets are infeasible and must be
@@ -440,7 +471,7 @@ def test_pruned_against_oracle_and_fallback(ctx, request, which, topk, rule):
     gap = (got["energy32"][fin] - ex["energy32"][fin]) / np.maximum(ex["energy32"][fin], 1e-6)
     say(f"  {which} top-{topk} rule {rule}: fallback {fell.mean():.3f}, mean gap {gap.mean():.4f}, "
         f"{len(taus)} offsets checked against the oracle")
-    if topk == 1:
+    if topk == 1 and rule == 0:
         assert fell.any()
     pr.close()
 
@@ -462,7 +493,8 @@ def test_save_load_roundtrip(ctx, small, tmp_path):
         x.close()
 
 
-@pytest.mark.parametrize("topk,rule,device", [(16, 1, True), (1, 0, False), (48, 1, False)])
+@pytest.mark.parametrize("topk,rule,device", [(16, 1, True), (1, 0, False), (48, 1, False), (16, 2, True),
+                                               (1, 2, False)])
 def test_plan_pruned_equals_per_pair_pruned(ctx, topk, rule, device):
     """The batched pruned run (lists, recursion, device-side fallback, all in
     one graph) gives every pair the rows of stm_match_pruned bit for bit; with
@@ -498,7 +530,7 @@ def test_plan_pruned_equals_per_pair_pruned(ctx, topk, rule, device):
         np.testing.assert_array_equal(fb, ref["fell_back"])
         fell_total += int(fb.sum())
     say(f"  plan top-{topk} rule {rule}: {plan.n_rows} rows identical, {fell_total} answered by the fallback")
-    if topk == 1:
+    if topk == 1 and rule == 0:
         assert fell_total > 0
     plan.close()
     pr.close()
