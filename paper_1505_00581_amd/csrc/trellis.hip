@@ -18,8 +18,9 @@
 // One launch per step i computes V_i from V_{i-1} for every model: a
 // workgroup takes one tile, a rectangle of rows [r0, r1) by columns [c0, c1)
 // holding at most 1024 cells (narrow bands: up to 64 consecutive rows whose
-// successors span at most 128 nodes; wide bands: 8 rows by a 128-column
-// window), thread t taking cells t, t + 256, ...  The predecessors of the
+// successors span at most 128 nodes; wide bands: 32 rows by a 32-column
+// window, so that a staged predecessor serves 32 rows and 32 columns), thread
+// t taking cells t, t + 256, ...  The predecessors of the
 // tile's rows, a contiguous node range, are staged 32 at a time in LDS: the
 // previous values with their directions va[k][r] (+inf where k is no
 // predecessor of r) and the directions C[k][c] of the window's columns.  A
@@ -244,24 +245,36 @@ __global__ __launch_bounds__(kThreads) void k_trellis_step(TrellisRun a, int32_t
     whi[j] = __builtin_amdgcn_readfirstlane(hi);
   }
 
+  // staging: one wave per predecessor row of a table at a time, so that the
+  // predecessor k and its band offsets are wave-uniform (scalar loads) and a
+  // lane takes one row (va) or one of 64 columns (ct) of the tile
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int cgroups = (CW + 63) >> 6;  // 64-column groups of the window: 1 or 2
   for (int32_t k0 = tl.k0; k0 < tl.k1; k0 += kChunk) {
     const int32_t nk = min(kChunk, tl.k1 - k0);
-    for (int idx = tid; idx < kChunk * R; idx += kThreads) {
-      const int kk = idx / R, row = idx - kk * R;
-      const int32_t k = k0 + kk;
-      float2 v = make_float2(INF, 0.f);
-      if (kk < nk && k >= sh.plo[row] && k < sh.phi[row]) {
-        const long long off = b.rowoff[k] + (tl.r0 + row - b.s_lo[k]);
-        v = make_float2(Vp[off], b.A[off]);
+    for (int kk = wv; kk < kChunk; kk += kThreads / 64) {
+      if (lane < R) {
+        const int32_t k = k0 + kk;
+        float2 v = make_float2(INF, 0.f);
+        if (kk < nk && k >= sh.plo[lane] && k < sh.phi[lane]) {
+          const long long off = b.rowoff[k] + (tl.r0 + lane - b.s_lo[k]);
+          v = make_float2(Vp[off], b.A[off]);
+        }
+        sh.va[kk][lane] = v;
       }
-      sh.va[kk][row] = v;
     }
-    for (int idx = tid; idx < kChunk * CW; idx += kThreads) {
-      const int kk = idx / CW, col = idx - kk * CW;
-      const int32_t k = k0 + kk, c = tl.c0 + col;
-      float v = 0.f;
-      if (kk < nk && c >= b.q_lo[k] && c < b.q_hi[k]) v = b.C[b.qoff[k] + (c - b.q_lo[k])];
-      sh.ct[kk][col] = v;
+    for (int it = wv; it < kChunk * cgroups; it += kThreads / 64) {
+      const int kk = cgroups == 2 ? it >> 1 : it;
+      const int col = (it - kk * cgroups) * 64 + lane;
+      if (col < CW) {
+        const int32_t k = k0 + kk, c = tl.c0 + col;
+        float v = 0.f;
+        if (kk < nk) {
+          const int32_t qlo = b.q_lo[k], qhi = b.q_hi[k];
+          if (c >= qlo && c < qhi) v = b.C[b.qoff[k] + (c - qlo)];
+        }
+        sh.ct[kk][col] = v;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -272,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_trellis_step(TrellisRun a, int32_t
       const float* ccol = &sh.ct[0][cc[j]];
       float bj = best[j];
       int32_t kk = lo;
-      for (; kk + 3 < hi; kk += 4) {
+      for (; kk + 7 < hi; kk += 8) {
         const float2 v0 = vcol[kk * kTrellisTileRows], v1 = vcol[(kk + 1) * kTrellisTileRows];
         const float2 v2 = vcol[(kk + 2) * kTrellisTileRows], v3 = vcol[(kk + 3) * kTrellisTileRows];
         const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[kk * kTrellisTileCols], bm[j], be[j], th, same[j], w);
@@ -280,6 +293,23 @@ __global__ __launch_bounds__(kThreads) void k_trellis_step(TrellisRun a, int32_t
         const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(kk + 2) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
         const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(kk + 3) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
         bj = fminf(fminf(bj, fminf(fminf(t0, t1), t2)), t3);
+        const float2 v4 = vcol[(kk + 4) * kTrellisTileRows], v5 = vcol[(kk + 5) * kTrellisTileRows];
+        const float2 v6 = vcol[(kk + 6) * kTrellisTileRows], v7 = vcol[(kk + 7) * kTrellisTileRows];
+        const float t4 = relax<DEGEN>(v4.x, v4.y, ccol[(kk + 4) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
+        const float t5 = relax<DEGEN>(v5.x, v5.y, ccol[(kk + 5) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
+        const float t6 = relax<DEGEN>(v6.x, v6.y, ccol[(kk + 6) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
+        const float t7 = relax<DEGEN>(v7.x, v7.y, ccol[(kk + 7) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
+        bj = fminf(fminf(bj, fminf(fminf(t4, t5), t6)), t7);
+      }
+      if (kk + 3 < hi) {
+        const float2 v0 = vcol[kk * kTrellisTileRows], v1 = vcol[(kk + 1) * kTrellisTileRows];
+        const float2 v2 = vcol[(kk + 2) * kTrellisTileRows], v3 = vcol[(kk + 3) * kTrellisTileRows];
+        const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[kk * kTrellisTileCols], bm[j], be[j], th, same[j], w);
+        const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(kk + 1) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
+        const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(kk + 2) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
+        const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(kk + 3) * kTrellisTileCols], bm[j], be[j], th, same[j], w);
+        bj = fminf(fminf(bj, fminf(fminf(t0, t1), t2)), t3);
+        kk += 4;
       }
       for (; kk < hi; ++kk) {
         const float2 v0 = vcol[kk * kTrellisTileRows];
