@@ -435,10 +435,12 @@ def bench_trellis(ctx, steps: int, t_values=(10, 0), model_counts=(1, 50)):
     """The paper's own problem (Table 2's whole video, Fig. 7's T sweep): M=30
     models against every node of a 723-frame video of 754 points, one trellis
     per model on the banded layout (stm_trellis_*), at T = 10 and with no
-    closeness limit, for 1 and for 50 models.  A run is the unary tables, one
-    launch per step for all models, the optimum, backtracking and the FP64
-    re-score; the trellis object (band, tiles, direction tables) is built once
-    and timed apart.  The paper's GTX580 figures are context only."""
+    closeness limit, for 1 and for 50 models.  A run is the unary tables, the
+    recursion of all models (one launch for every step when the band fits a
+    workgroup's LDS, as at T = 10, timed beside one launch per step; else one
+    launch per step), the optimum, backtracking and the FP64 re-score; the
+    trellis object (band, tiles, direction tables) is built once and timed
+    apart.  The paper's GTX580 figures are context only."""
     import torch
 
     import paper_1505_00581_amd as stm
@@ -473,18 +475,32 @@ def bench_trellis(ctx, steps: int, t_values=(10, 0), model_counts=(1, 50)):
             ach = info["feasible_relax"] * OPS_PER_RELAX / (dp_ms / 1e3) / 1e12
             e32 = res["energy32"].cpu().numpy()
             tr.close()
+            stepwise_ms = None
+            if info["fused"]:
+                sw = stm.Trellis(ctx, dms[:nm], ds, p, stepwise=True)
+                r2 = sw.run()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    sw.run(r2)
+                torch.cuda.synchronize()
+                stepwise_ms = round(1e3 * (time.perf_counter() - t0) / steps, 3)
+                sw.close()
             row = dict(T=int(T), models=nm, ms_per_run=round(ms, 3), ms_per_frame=round(ms / s.n_frames, 5),
                        build_ms=round(build_ms, 2), recursion_ms=round(dp_ms, 3),
+                       one_launch=bool(info["fused"]), stepwise_ms_per_run=stepwise_ms,
                        cells_per_step=info["cells_per_step"], tiles_per_step=info["tiles"],
                        feasible_relax=info["feasible_relax"],
                        feasible_relax_per_s=round(info["feasible_relax"] / (ms / 1e3), 1),
                        roofline=dict(bound="alu", achieved=round(ach, 3), peak=round(VALU_PEAK_OPS / 1e12, 3),
                                      unit="TOP/s", frac=round(ach * 1e12 / VALU_PEAK_OPS, 4),
                                      ops_per_relax=OPS_PER_RELAX,
-                                     kernel="k_trellis_first + k_trellis_step x (M-2) + k_trellis_final"),
+                                     kernel=("k_trellis_fused + k_trellis_final" if info["fused"] else
+                                             "k_trellis_first + k_trellis_step x (M-2) + k_trellis_final")),
                        feasible=int(np.isfinite(e32).sum()))
             out.append(row)
-            log(f"  trellis T={T} models={nm}: {ms:.3f} ms per run ({ms / s.n_frames:.5f} ms/frame), "
+            log(f"  trellis T={T} models={nm}: {ms:.3f} ms per run ({ms / s.n_frames:.5f} ms/frame"
+                + (f"; one launch per step: {stepwise_ms:.3f} ms" if stepwise_ms else "") + "), "
                 f"build {build_ms:.1f} ms, recursion {dp_ms:.3f} ms, {info['feasible_relax']:.3e} relaxations, "
                 f"{row['roofline']['frac']:.3f} of the VALU ceiling")
     return dict(workload="the paper's whole-video trellis: M=30 models (160x120, frames 0..45) against all "

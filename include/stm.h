@@ -104,6 +104,10 @@ extern "C" {
                                  consecutive points.  Consecutive points are then at
                                  most T - 2 frames apart.  No effect with T <= 0;
                                  not with STM_DUMMY (STM_EUNSUPPORTED).             */
+#define STM_TRELLIS_STEPWISE 0x20u  /* trellis (stm_trellis_*) only: one launch per
+                                 step even where the band fits one workgroup's LDS
+                                 and all steps would run in one launch; the two give
+                                 the same bits                                      */
 
 /* Node id of a dummy assignment in assignment rows (STM_DUMMY); -1 marks the
  * rows of infeasible offsets. */
@@ -381,8 +385,10 @@ STM_API int stm_match_batch(stm_ctx* ctx, const stm_points* models, int32_t n_mo
  * A trellis object holds n_models models against the nodes [node_begin,
  * node_end) of one scene: the band, its tiles, the direction tables and the
  * value tables (sum over models of (M - 1) x cells floats).  A run solves
- * every model: the unary tables, one launch per step of the min-sum recursion
- * (forward form of Eq. 10-11) over all models, the optimum and backtracking
+ * every model: the unary tables, the min-sum recursion (forward form of Eq.
+ * 10-11) over all models (one launch for all steps, one workgroup per model,
+ * when the band fits a workgroup's LDS; else one launch per step), the
+ * optimum and backtracking
  * (Eq. 12-13) on the device, and the FP64 re-score (Eq. 1).
  * Outputs: energy32, energy64, energy_u64 [n_models] (nullable: the FP64 ones)
  * and assign [sum of model sizes] (model q's points from the sum of the sizes
@@ -391,8 +397,9 @@ STM_API int stm_match_batch(stm_ctx* ctx, const stm_points* models, int32_t n_mo
  * step, the lowest node inside each minimum.
  * params: lambda1..3 and T as for stm_match; window and k_max are not used;
  * flags: STM_DEVICE_PTRS (device inputs, referenced by the object and the
- * scene not copied; device outputs; runs queued on `hip_stream`) and
- * STM_CLOSENESS_SPAN; STM_UNARY_BF16, STM_K_DENSITY and STM_DUMMY give
+ * scene not copied; device outputs; runs queued on `hip_stream`),
+ * STM_CLOSENESS_SPAN and STM_TRELLIS_STEPWISE; STM_UNARY_BF16, STM_K_DENSITY
+ * and STM_DUMMY give
  * STM_EUNSUPPORTED.  Errors as stm_match, plus STM_EINVAL for an empty or
  * out-of-range node range, STM_ENOMEM when the value tables do not fit. */
 typedef struct stm_trellis stm_trellis;
@@ -401,11 +408,13 @@ STM_API int stm_trellis_create(stm_ctx* ctx, const stm_points* models, int32_t n
 STM_API void stm_trellis_destroy(stm_trellis* trellis);
 STM_API int stm_trellis_run(stm_trellis* trellis, float* energy32, double* energy64, double* energy_u64,
                             int32_t* assign, void* hip_stream);
-/* info [9], host memory: cells per step, two-step direction pairs, tiles per
+/* info [10], host memory: cells per step, two-step direction pairs, tiles per
  * step launch, 1 if the degenerate variant runs (coincident points), then the
  * work of one run over all models: dense cells (M - 1) n^2, feasible cells
  * (M - 1) x band cells, dense relaxations (M - 2) n^3, feasible relaxations
- * (admissible triples), and the sum of the model sizes. */
+ * (admissible triples), the sum of the model sizes, and 1 if every step runs
+ * in one launch (one workgroup per model, the band in LDS), 0 if each step is
+ * a launch of its own. */
 STM_API int stm_trellis_info(const stm_trellis* trellis, int64_t* info);
 /* One-shot: create, run once, destroy (waits for the run). */
 STM_API int stm_match_trellis(stm_ctx* ctx, const stm_points* models, int32_t n_models, const stm_points* scene,

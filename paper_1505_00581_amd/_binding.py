@@ -24,6 +24,7 @@ STM_UNARY_BF16 = 0x2
 STM_K_DENSITY = 0x4
 STM_DUMMY = 0x8
 STM_CLOSENESS_SPAN = 0x10
+STM_TRELLIS_STEPWISE = 0x20  # trellis: one launch per step even where the band fits LDS
 STM_DUMMY_NODE = -2  # assignment value of a dummy (unmatched model point)
 STM_UNCHAINED_NODE = -3  # assignment value of a point in no kept chain (stm_match_chains)
 STM_NOALLOC_SCRATCH_BYTES = 256 << 20  # fixed device array of stm_match_noalloc
@@ -446,7 +447,8 @@ class Trellis:
     node of scene nodes [node_begin, node_end), the paper's own problem.
     Device point sets (DevicePoints) are referenced and must outlive it."""
 
-    def __init__(self, ctx: Context, models, scene, params, node_begin: int = 0, node_end=None):
+    def __init__(self, ctx: Context, models, scene, params, node_begin: int = 0, node_end=None,
+                 stepwise: bool = False):
         self._lib = ctx._lib
         self.ctx = ctx
         self.device = _is_device(scene)
@@ -457,6 +459,8 @@ class Trellis:
         self.assign_offsets = np.concatenate([[0], np.cumsum(self.msizes)]).astype(np.int64)
         e = int(scene.t.shape[0]) if node_end is None else int(node_end)
         pp = _params(params, self.device)
+        if stepwise:
+            pp.flags |= STM_TRELLIS_STEPWISE
         h = ctypes.c_void_p()
         _check(self._lib.stm_trellis_create(ctx.handle, ctypes.addressof(self._models), len(models),
                                             ctypes.byref(self._scene), int(node_begin), e, ctypes.byref(pp),
@@ -464,11 +468,11 @@ class Trellis:
         self.handle = h
 
     def info(self) -> dict:
-        v = np.zeros(9, np.int64)
+        v = np.zeros(10, np.int64)
         _check(self._lib.stm_trellis_info(self.handle, v.ctypes.data))
         return dict(cells_per_step=int(v[0]), pairs=int(v[1]), tiles=int(v[2]), degenerate=bool(v[3]),
                     dense_cells=int(v[4]), feasible_cells=int(v[5]), dense_relax=int(v[6]),
-                    feasible_relax=int(v[7]), points=int(v[8]))
+                    feasible_relax=int(v[7]), points=int(v[8]), fused=bool(v[9]))
 
     def run(self, out=None):
         """Solves every model.  Returns dict(energy32, energy64, energy_u64

@@ -338,6 +338,7 @@ struct TrellisRun {
   int32_t n;            // block nodes
   int32_t node0;        // scene id of the block's first node
   long long Q;          // cells per step
+  long long QC;         // two-step direction pairs
   int32_t span_lim;     // span_limit of the search parameters
   float lambda1, lambda2, w;
   float* e32;           // [n_models]
@@ -351,8 +352,13 @@ hipError_t launch_trellis_band(const int32_t* t, int32_t n, const SearchParams& 
 hipError_t launch_trellis_dirs(const TrellisBand& b, int32_t n, const float2* xy, const int32_t* t, int32_t span_lim,
                                int32_t* flag, hipStream_t st);
 // Steps 1..M-1 of every model, then the optimum and backtracking (degen: the
-// variant that handles coincident points).
-hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_max, bool degen, hipStream_t st);
+// variant that handles coincident points; fused: every step in one workgroup
+// per model, for bands that trellis_fits_fused accepts).
+hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_max, bool degen, bool fused,
+                              hipStream_t st);
+// Whether a band of n nodes, Q cells and QC two-step pairs fits one
+// workgroup's LDS for the fused run.
+bool trellis_fits_fused(long long Q, long long QC, int32_t n);
 
 // ---- learned candidate pruner -------------------------------------------------------
 

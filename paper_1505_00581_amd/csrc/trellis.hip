@@ -52,6 +52,17 @@ __device__ __forceinline__ int32_t lower_bound64(const int32_t* __restrict__ a, 
   return lo;
 }
 
+// A cell's value at step 1, l1 U_0(r) + l1 U_1(c) + l2 |dt_model - dt_scene|, and
+// at a later step, l1 U_i(c) + q_w |dt_model - dt_scene| + the minimum over the
+// predecessors; the roundings are spelled out so that every kernel that forms a
+// value gives the same bits.
+__device__ __forceinline__ float first_value(const TrellisRun& a, float u0, float u1, int32_t dtm, int32_t dts) {
+  return fmaf(a.lambda2, fabsf(static_cast<float>(dtm - dts)), fmaf(a.lambda1, u1, __fmul_rn(a.lambda1, u0)));
+}
+__device__ __forceinline__ float step_value(float cu, float qw, int32_t dtm, int32_t dts, float best) {
+  return fmaf(qw, fabsf(static_cast<float>(dtm - dts)), cu) + best;
+}
+
 // ---- the band of a scene block -------------------------------------------------
 __global__ __launch_bounds__(256) void k_trellis_band(const int32_t* __restrict__ t, int32_t n, SearchParams sp,
                                                       TrellisBand b) {
@@ -146,14 +157,10 @@ __global__ __launch_bounds__(64) void k_trellis_first(TrellisRun a) {
   if (lo >= hi) return;
   const float* U0 = md.U;
   const float* U1 = md.U + a.n;
-  const float cu0 = a.lambda1 * U0[r];
   const int32_t dtm = md.m.t[1] - md.m.t[0];
   const int32_t tr = a.t[r];
   float* out = md.V + a.band.rowoff[r] - lo;
-  for (int32_t c = lo + threadIdx.x; c < hi; c += 64) {
-    const float q = a.lambda2 * fabsf(static_cast<float>(dtm - (a.t[c] - tr)));
-    out[c] = (cu0 + a.lambda1 * U1[c]) + q;
-  }
+  for (int32_t c = lo + threadIdx.x; c < hi; c += 64) out[c] = first_value(a, U0[r], U1[c], dtm, a.t[c] - tr);
 }
 
 struct StepShared {
@@ -195,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_trellis_step(TrellisRun a, int32_t
   }
   if (tid < CW) {
     const int32_t c = tl.c0 + tid;
-    sh.cu[tid] = a.lambda1 * Ui[c];
+    sh.cu[tid] = __fmul_rn(a.lambda1, Ui[c]);
     sh.tc[tid] = a.t[c];
   }
   if (tid < 64) {  // R <= 64: one wave scans the counts
@@ -325,9 +332,117 @@ __global__ __launch_bounds__(kThreads) void k_trellis_step(TrellisRun a, int32_t
     const int32_t cid = tid + kThreads * j;
     if (cid < ncell) {
       const int32_t r = tl.r0 + rr[j], c = tl.c0 + cc[j];
-      const float q = qw * fabsf(static_cast<float>(dtm - (sh.tc[cc[j]] - sh.tr[rr[j]])));
-      Vi[b.rowoff[r] + (c - b.s_lo[r])] = (sh.cu[cc[j]] + q) + best[j];
+      Vi[b.rowoff[r] + (c - b.s_lo[r])] = step_value(sh.cu[cc[j]], qw, dtm, sh.tc[cc[j]] - sh.tr[rr[j]], best[j]);
     }
+  }
+}
+
+// ---- small bands: every step in one workgroup per model ---------------------------
+// When the band's cells, the two-step pairs and the per-node offsets fit one
+// workgroup's LDS (the whole video at T = 10: 7.5k cells, 14k pairs), one
+// workgroup per model runs steps 1..M-1 with V_{i-1}, A, C and the offsets in
+// LDS and a workgroup barrier between steps, instead of a launch per step whose
+// dependent global reads make up most of its time.  Every term, and the order
+// of the operations that form a cell's value, is that of k_trellis_first and
+// k_trellis_step, so both give the same bits.
+constexpr int kFusedThreads = 1024;
+constexpr int kFusedSlots = 8;                                   // cells per thread
+constexpr int kFusedLds = 160 * 1024 - 512;                      // bytes of the LDS pool
+
+constexpr long long fused_bytes(long long Q, long long QC, long long n) {
+  return 8 * n + 8 * n + 4 * Q + 4 * Q + 4 * QC + 2 * Q;
+}
+
+template <bool DEGEN>
+__global__ __launch_bounds__(kFusedThreads) void k_trellis_fused(TrellisRun a) {
+  __shared__ __align__(16) unsigned char pool[kFusedLds];
+  const TrellisModel md = a.models[blockIdx.x];
+  const int32_t M = md.m.M;
+  const TrellisBand& b = a.band;
+  const int32_t n = a.n, Q = static_cast<int32_t>(a.Q), QC = static_cast<int32_t>(a.QC);
+  const int tid = threadIdx.x;
+  const float INF = __builtin_inff();
+  int2* kin = reinterpret_cast<int2*>(pool);           // (rowoff - s_lo, qoff - q_lo) of node k
+  int2* prg = kin + n;                                 // predecessors [p_lo, p_hi) of node r
+  float* V = reinterpret_cast<float*>(prg + n);        // V_{i-1} of every cell
+  float* A = V + Q;                                    // A(r, c) of every cell
+  float* C = A + Q;                                    // C(k, c) of every two-step pair
+  int16_t* crow = reinterpret_cast<int16_t*>(C + QC);  // row of every cell
+  for (int32_t k = tid; k < n; k += kFusedThreads) {
+    const int32_t r0 = static_cast<int32_t>(b.rowoff[k]), r1 = static_cast<int32_t>(b.rowoff[k + 1]);
+    kin[k] = make_int2(r0 - b.s_lo[k], static_cast<int32_t>(b.qoff[k]) - b.q_lo[k]);
+    prg[k] = make_int2(b.p_lo[k], b.p_hi[k]);
+    for (int32_t q = r0; q < r1; ++q) crow[q] = static_cast<int16_t>(k);
+  }
+  for (int32_t q = tid; q < Q; q += kFusedThreads) A[q] = b.A[q];
+  for (int32_t q = tid; q < QC; q += kFusedThreads) C[q] = b.C[q];
+  __syncthreads();
+
+  // the thread's cells and step 1: V_1(r, c) = l1 (U_0(r) + U_1(c)) + l2 |dt|
+  int32_t cr[kFusedSlots], cc[kFusedSlots], lo[kFusedSlots], hi[kFusedSlots], dt[kFusedSlots];
+  float arc[kFusedSlots];
+  bool same[kFusedSlots];
+  const int32_t dtm1 = md.m.t[1] - md.m.t[0];
+#pragma unroll
+  for (int j = 0; j < kFusedSlots; ++j) {
+    const int32_t q = tid + kFusedThreads * j;
+    const bool valid = q < Q;
+    const int32_t r = valid ? crow[q] : 0;
+    const int32_t c = valid ? q - kin[r].x : 0;  // s_lo[r] + (q - rowoff[r])
+    const int2 p = prg[r];
+    cr[j] = r;
+    cc[j] = c;
+    lo[j] = valid ? p.x : 0;
+    hi[j] = valid ? p.y : 0;
+    dt[j] = a.t[c] - a.t[r];
+    arc[j] = valid ? A[q] : 0.f;
+    if (DEGEN) {
+      const float2 xr = a.xy[r], xc = a.xy[c];
+      same[j] = xr.x == xc.x && xr.y == xc.y;
+    } else {
+      same[j] = false;
+    }
+    if (valid) {
+      const float v = first_value(a, md.U[r], md.U[n + c], dtm1, dt[j]);
+      V[q] = v;
+      md.V[q] = v;
+    }
+  }
+  __syncthreads();
+
+  for (int32_t i = 2; i < M; ++i) {
+    const float2 th = md.theta[i];
+    const int32_t dtm = md.m.t[i] - md.m.t[i - 1];
+    const float qw = a.lambda2 * (i <= M - 2 ? 2.f : 1.f);
+    const float* Ui = md.U + (long long)i * n;
+    float* Vi = md.V + (long long)(i - 1) * a.Q;
+    float nv[kFusedSlots];
+#pragma unroll
+    for (int j = 0; j < kFusedSlots; ++j) {
+      nv[j] = INF;
+      if (tid + kFusedThreads * j < Q) {
+        float bm, be;
+        cell_brackets(th, -arc[j], bm, be);
+        const int32_t r = cr[j], c = cc[j];
+        float best = INF;
+        for (int32_t k = lo[j]; k < hi[j]; ++k) {
+          const int2 kk = kin[k];
+          const int32_t off = kk.x + r;  // cell (k, r)
+          best = fminf(best, relax<DEGEN>(V[off], A[off], C[kk.y + c], bm, be, th, same[j], a.w));
+        }
+        nv[j] = step_value(__fmul_rn(a.lambda1, Ui[c]), qw, dtm, dt[j], best);
+      }
+    }
+    __syncthreads();  // every read of V_{i-1} done
+#pragma unroll
+    for (int j = 0; j < kFusedSlots; ++j) {
+      const int32_t q = tid + kFusedThreads * j;
+      if (q < Q) {
+        V[q] = nv[j];
+        Vi[q] = nv[j];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -440,9 +555,22 @@ hipError_t launch_trellis_dirs(const TrellisBand& b, int32_t n, const float2* xy
   return hipGetLastError();
 }
 
-hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_max, bool degen, hipStream_t st) {
+bool trellis_fits_fused(long long Q, long long QC, int32_t n) {
+  return Q > 0 && Q <= (long long)kFusedThreads * kFusedSlots && n <= 32767 && fused_bytes(Q, QC, n) <= kFusedLds;
+}
+
+hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_max, bool degen, bool fused,
+                              hipStream_t st) {
   if (a.n_models <= 0) return hipSuccess;
-  if (a.Q > 0) {
+  if (fused) {
+    if (!trellis_fits_fused(a.Q, a.QC, a.n)) return hipErrorInvalidValue;
+    if (degen)
+      hipLaunchKernelGGL(k_trellis_fused<true>, dim3(a.n_models), dim3(kFusedThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_trellis_fused<false>, dim3(a.n_models), dim3(kFusedThreads), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else if (a.Q > 0) {
     hipLaunchKernelGGL(k_trellis_first, dim3(a.n, a.n_models), dim3(64), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -35,6 +35,7 @@ struct stm_trellis {
   stm::PairDev* pairs_dev = nullptr;
   int2* items_dev = nullptr;
   bool degen = false;
+  bool fused = false;  // every step in one launch (the band in LDS)
   int64_t work[4] = {0, 0, 0, 0};
   float* o_e32 = nullptr;
   double* o_e64 = nullptr;
@@ -98,6 +99,7 @@ int tr_enqueue(stm_trellis* p, float* e32, double* e64, double* eu, int32_t* as,
   a.n = n;
   a.node0 = p->node0;
   a.Q = p->Q;
+  a.QC = p->QC;
   a.span_lim = stm::span_limit(p->sp);
   a.lambda1 = static_cast<float>(p->params.lambda1);
   a.lambda2 = static_cast<float>(p->params.lambda2);
@@ -105,7 +107,7 @@ int tr_enqueue(stm_trellis* p, float* e32, double* e64, double* eu, int32_t* as,
   a.e32 = e32;
   a.assign = as;
   if (timed) STM_HIP(hipEventRecord(p->ev_k0, st));
-  STM_HIP(stm::launch_trellis_run(a, p->n_tiles, p->m_max, p->degen, st));
+  STM_HIP(stm::launch_trellis_run(a, p->n_tiles, p->m_max, p->degen, p->fused, st));
   if (timed) STM_HIP(hipEventRecord(p->ev_k1, st));
   STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_models, p->sp, p->params.lambda1,
                                     p->params.lambda2, p->params.lambda3, 0.0, as, e64, eu, st));
@@ -115,7 +117,7 @@ int tr_enqueue(stm_trellis* p, float* e32, double* e64, double* eu, int32_t* as,
 // Tiles of a step from the band's ranges (host copies): narrow bands take up
 // to 64 consecutive rows whose successors span at most 128 nodes and hold at
 // most 1024 cells; a row with more than 128 successors starts a block of up to
-// 8 rows cut into 128-column windows.  Tiles without cells are left out.
+// 32 rows cut into 32-column windows.  Tiles without cells are left out.
 std::vector<stm::TrellisTile> make_tiles(const std::vector<int32_t>& slo, const std::vector<int32_t>& shi,
                                          const std::vector<int32_t>& plo, const std::vector<int32_t>& phi) {
   constexpr int kRows = stm::kTrellisTileRows, kCols = stm::kTrellisTileCols, kCells = stm::kTrellisTileCells;
@@ -159,8 +161,9 @@ std::vector<stm::TrellisTile> make_tiles(const std::vector<int32_t>& slo, const 
 int check_trellis_params(const stm_params* p) {
   if (!p) return fail(STM_EINVAL, "null params");
   if (p->flags & (STM_UNARY_BF16 | STM_K_DENSITY | STM_DUMMY))
-    return fail(STM_EUNSUPPORTED, "the trellis takes STM_DEVICE_PTRS and STM_CLOSENESS_SPAN only");
-  if (p->flags & ~(STM_DEVICE_PTRS | STM_CLOSENESS_SPAN)) return fail(STM_EUNSUPPORTED, "unknown flag");
+    return fail(STM_EUNSUPPORTED, "the trellis takes STM_DEVICE_PTRS, STM_CLOSENESS_SPAN and STM_TRELLIS_STEPWISE only");
+  if (p->flags & ~(STM_DEVICE_PTRS | STM_CLOSENESS_SPAN | STM_TRELLIS_STEPWISE))
+    return fail(STM_EUNSUPPORTED, "unknown flag");
   return STM_OK;
 }
 
@@ -295,6 +298,7 @@ int stm_trellis_create(stm_ctx* ctx, const stm_points* models, int32_t n_models,
   TR_HIP(hipStreamSynchronize(st));
   p->Q = ends[0];
   p->QC = ends[1];
+  p->fused = !(params->flags & STM_TRELLIS_STEPWISE) && stm::trellis_fits_fused(p->Q, p->QC, n);
   const std::vector<stm::TrellisTile> tiles = make_tiles(slo, shi, plo, phi);
   p->n_tiles = static_cast<int32_t>(tiles.size());
   TR_ALLOC(p->tiles, stm::TrellisTile, std::max<size_t>(1, tiles.size()));
@@ -399,6 +403,7 @@ int stm_trellis_info(const stm_trellis* trellis, int64_t* info) {
   info[3] = trellis->degen ? 1 : 0;
   for (int k = 0; k < 4; ++k) info[4 + k] = trellis->work[k];
   info[8] = trellis->m_total;
+  info[9] = trellis->fused ? 1 : 0;
   return STM_OK;
 }
 

@@ -10,8 +10,9 @@ infeasible cases, coincident points), the paper's video of 754 points in 723
 frames at T = 10 (all 50 models in one object, sampled models against the
 oracle, properties for all), no closeness limit on a 180-node block (wide
 tiles) and on the whole video (properties), a 60-node block equal bit for
-bit to the windowed kernel on the same lists, host = device pointers, and
-the refused arguments.
+bit to the windowed kernel on the same lists, host = device pointers, the
+one-launch run of bands that fit LDS equal bit for bit to one launch per
+step, and the refused arguments.
 """
 import dataclasses
 import sys
@@ -203,6 +204,44 @@ def test_refused_arguments(ctx, video):
         with pytest.raises(stm.StmError) as ei:
             stm.Trellis(ctx, [m], s, q)
         assert ei.value.code == stm.STM_EUNSUPPORTED
+
+
+def _same_runs(a, b):
+    for k in ("energy32", "energy64", "energy_u64", "assign"):
+        np.testing.assert_array_equal(to_np(a[k]), to_np(b[k]), err_msg=k)
+
+
+def test_fused_run_equals_stepwise_launches(ctx, video):
+    """Bands that fit one workgroup's LDS run every step in one launch; the
+    same trellis with one launch per step (STM_TRELLIS_STEPWISE) gives the
+    same bits: the whole video at T = 10 (50 models, both closeness readings),
+    tiny blocks with coincident points (the degenerate variant), and a block
+    too large for LDS takes the per-step launches either way."""
+    s = video.scenes[0]
+    for p in (video.params, dataclasses.replace(video.params, closeness_span=True)):
+        a = stm.Trellis(ctx, video.models, s, p)
+        b = stm.Trellis(ctx, video.models, s, p, stepwise=True)
+        assert a.info()["fused"] and not b.info()["fused"]
+        _same_runs(a.run(), b.run())
+        a.close()
+        b.close()
+    degen = 0
+    for seed in range(30):
+        m, sc = _tiny(4200 + seed, n_frames=8, per_frame=(1, 3), int_grid=10)
+        p = synth.Params(T=5)
+        a = stm.Trellis(ctx, [m], sc, p)
+        b = stm.Trellis(ctx, [m], sc, p, stepwise=True)
+        ia = a.info()
+        assert ia["fused"] == (ia["cells_per_step"] > 0)
+        degen += ia["degenerate"]
+        _same_runs(a.run(), b.run())
+        a.close()
+        b.close()
+    assert degen > 5
+    big = stm.Trellis(ctx, video.models[:2], s, dataclasses.replace(video.params, T=0))
+    assert not big.info()["fused"]
+    big.close()
+    say(f"  fused = stepwise on the video (both readings) and 30 tiny blocks ({degen} degenerate)")
 
 
 def test_graph_replays_equal_direct_launches(ctx, video):
