@@ -21,7 +21,7 @@
 // successors span at most 128 nodes; wide bands: 32 rows by a 32-column
 // window, so that a staged predecessor serves 32 rows and 32 columns), thread
 // t taking cells t, t + 256, ...  The predecessors of the
-// tile's rows, a contiguous node range, are staged 32 at a time in LDS: the
+// tile's rows, a contiguous node range, are staged 24 at a time in LDS: the
 // previous values with their directions va[k][r] (+inf where k is no
 // predecessor of r) and the directions C[k][c] of the window's columns.  A
 // wave runs over the union of its lanes' predecessor ranges; a lane outside
@@ -40,7 +40,10 @@ namespace {
 
 constexpr int kThreads = 256;                    // threads of a step workgroup
 constexpr int kSlots = kTrellisTileCells / kThreads;  // cells per thread
-constexpr int kChunk = 32;                       // predecessors staged in LDS at a time
+// predecessors staged in LDS at a time: 24 leaves room for five workgroups per
+// CU (42.6 ms against 47.5 at 32 on the whole video without a closeness
+// limit, 50 models)
+constexpr int kChunk = 24;
 
 // First index of the ascending a[0..n) whose value is >= x (n if none).
 __device__ __forceinline__ int32_t lower_bound64(const int32_t* __restrict__ a, int32_t n, long long x) {

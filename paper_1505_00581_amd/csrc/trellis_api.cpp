@@ -122,7 +122,7 @@ std::vector<stm::TrellisTile> make_tiles(const std::vector<int32_t>& slo, const 
                                          const std::vector<int32_t>& plo, const std::vector<int32_t>& phi) {
   constexpr int kRows = stm::kTrellisTileRows, kCols = stm::kTrellisTileCols, kCells = stm::kTrellisTileCells;
   // rows wider than kCols: kWideRows rows by kWideCols-column windows.  Staging
-  // 32 predecessors loads 32 (rows + columns) values for 32 rows x columns
+  // k predecessors loads k (rows + columns) values for k rows x columns
   // relaxations, fewest for a square window (32 x 32: 48.5 -> 47.6 ms on the
   // whole-video trellis without a closeness limit, against 16 x 64; 8 x 128
   // took 58 ms)
