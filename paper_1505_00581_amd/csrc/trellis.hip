@@ -21,7 +21,7 @@
 // successors span at most 128 nodes; wide bands: 32 rows by a 32-column
 // window, so that a staged predecessor serves 32 rows and 32 columns), thread
 // t taking cells t, t + 256, ...  The predecessors of the
-// tile's rows, a contiguous node range, are staged 24 at a time in LDS: the
+// tile's rows, a contiguous node range, are staged 20 or 24 at a time in LDS: the
 // previous values with their directions va[k][r] (+inf where k is no
 // predecessor of r) and the directions C[k][c] of the window's columns.  A
 // wave runs over the union of its lanes' predecessor ranges; a lane outside
@@ -40,10 +40,14 @@ namespace {
 
 constexpr int kThreads = 256;                    // threads of a step workgroup
 constexpr int kSlots = kTrellisTileCells / kThreads;  // cells per thread
-// predecessors staged in LDS at a time: 24 leaves room for five workgroups per
-// CU (42.6 ms against 47.5 at 32 on the whole video without a closeness
-// limit, 50 models)
-constexpr int kChunk = 24;
+// Predecessors staged in LDS at a time and the occupancy target of a step
+// launch: launches of many workgroups (several per CU) take 20 at a time at six
+// waves per SIMD (80 registers), smaller ones 24 at five; on the whole video
+// without a closeness limit 40.2 ms for 50 models against 42.6 (24) and 47.5
+// (32 at four waves), and 7.8 ms for one model against 8.5 (20 at six).
+constexpr int kChunkWide = 20, kWavesWide = 6;    // launches of >= kManyTiles workgroups
+constexpr int kChunkSmall = 24, kWavesSmall = 5;
+constexpr int kManyTiles = 1024;
 
 // First index of the ascending a[0..n) whose value is >= x (n if none).
 __device__ __forceinline__ int32_t lower_bound64(const int32_t* __restrict__ a, int32_t n, long long x) {
@@ -166,9 +170,10 @@ __global__ __launch_bounds__(64) void k_trellis_first(TrellisRun a) {
   for (int32_t c = lo + threadIdx.x; c < hi; c += 64) out[c] = first_value(a, U0[r], U1[c], dtm, a.t[c] - tr);
 }
 
+template <int KC>
 struct StepShared {
-  float2 va[kChunk][kTrellisTileRows];  // (V_{i-1}(k, r), A(k, r)); +inf where k is no predecessor of r
-  float ct[kChunk][kTrellisTileCols];   // C(k, c)
+  float2 va[KC][kTrellisTileRows];  // (V_{i-1}(k, r), A(k, r)); +inf where k is no predecessor of r
+  float ct[KC][kTrellisTileCols];   // C(k, c)
   int32_t plo[kTrellisTileRows], phi[kTrellisTileRows], slo[kTrellisTileRows], tr[kTrellisTileRows];
   int32_t cstart[kTrellisTileRows + 1];  // first tile cell of each row
   int16_t crow[kTrellisTileCells];       // row of each tile cell
@@ -177,9 +182,11 @@ struct StepShared {
 };
 
 // V_i for the tile blockIdx.x of model blockIdx.y (skipped when i >= M).
-template <bool DEGEN>
-__global__ __launch_bounds__(kThreads) void k_trellis_step(TrellisRun a, int32_t i) {
-  __shared__ StepShared sh;
+template <bool DEGEN, int KC, int WAVES>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WAVES)))
+void k_trellis_step(TrellisRun a, int32_t i) {
+  constexpr int kChunk = KC;
+  __shared__ StepShared<KC> sh;
   const TrellisModel md = a.models[blockIdx.y];
   const int32_t M = md.m.M;
   if (i >= M) return;
@@ -578,10 +585,16 @@ hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_ma
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int32_t i = 2; i < m_max && n_tiles > 0; ++i) {
-      if (degen)
-        hipLaunchKernelGGL(k_trellis_step<true>, dim3(n_tiles, a.n_models), dim3(kThreads), 0, st, a, i);
+      const dim3 grid(n_tiles, a.n_models);
+      const bool many = (long long)n_tiles * a.n_models >= kManyTiles;
+      if (degen && many)
+        hipLaunchKernelGGL((k_trellis_step<true, kChunkWide, kWavesWide>), grid, dim3(kThreads), 0, st, a, i);
+      else if (degen)
+        hipLaunchKernelGGL((k_trellis_step<true, kChunkSmall, kWavesSmall>), grid, dim3(kThreads), 0, st, a, i);
+      else if (many)
+        hipLaunchKernelGGL((k_trellis_step<false, kChunkWide, kWavesWide>), grid, dim3(kThreads), 0, st, a, i);
       else
-        hipLaunchKernelGGL(k_trellis_step<false>, dim3(n_tiles, a.n_models), dim3(kThreads), 0, st, a, i);
+        hipLaunchKernelGGL((k_trellis_step<false, kChunkSmall, kWavesSmall>), grid, dim3(kThreads), 0, st, a, i);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }

@@ -244,6 +244,32 @@ def test_fused_run_equals_stepwise_launches(ctx, video):
     say(f"  fused = stepwise on the video (both readings) and 30 tiny blocks ({degen} degenerate)")
 
 
+def test_step_launch_variants_agree(ctx, video):
+    """Step launches of many workgroups stage fewer predecessors at a time at a
+    higher occupancy than small ones; the terms and minima are the same, so a
+    model's rows from a 50-model run (the wide variant) equal those of a run
+    of that model alone (the small variant) bit for bit."""
+    import torch
+    s = video.scenes[0]
+    ds = stm.DevicePoints.from_host(s)
+    dms = [stm.DevicePoints.from_host(m) for m in video.models]
+    p = dataclasses.replace(video.params, T=0)
+    tr = stm.Trellis(ctx, dms, ds, p)
+    assert tr.info()["tiles"] * len(dms) >= 1024
+    out = tr.run()
+    torch.cuda.synchronize()
+    for q in (0, 7, 49):
+        one = stm.Trellis(ctx, [dms[q]], ds, p)
+        assert one.info()["tiles"] < 1024
+        r = one.run()
+        torch.cuda.synchronize()
+        assert to_np(r["energy32"])[0] == to_np(out["energy32"])[q]
+        assert to_np(r["energy64"])[0] == to_np(out["energy64"])[q]
+        np.testing.assert_array_equal(to_np(one.model_rows(r, 0)), to_np(tr.model_rows(out, q)))
+        one.close()
+    tr.close()
+
+
 def test_graph_replays_equal_direct_launches(ctx, video):
     # runs into the same outputs replay one captured graph; a profiled run
     # launches the kernels directly: every replay, with eager work and
