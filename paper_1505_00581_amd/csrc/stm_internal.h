@@ -413,7 +413,7 @@ struct PrunerInfer {
   const float* A;       // [M][128] model projection W1[:, 0:D] (D f) + b1
   const float* B;       // [S][128] scene projection W1[:, D:2D] (D g)
   int topk;
-  int rule;             // 0: top-k by score; 1: nearest frames first, score inside
+  int rule;             // 0: top-k by score; 1: nearest frames first, score inside; 2: nearest frames, then slot
   int32_t* cand;        // [n_groups][topk]
   int32_t* count;       // [n_groups]
   float* scores;        // [n_groups][64], nullable
