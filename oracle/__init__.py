@@ -84,12 +84,14 @@ def _dummy(params):
     return (0, 0.0) if w is None else (1, float(w))
 
 
-def _span(params) -> int:
-    """1 for the span reading of temporal closeness (params.closeness_span)."""
+def _readings(params) -> int:
+    """Bits of the alternative readings: 1 the span reading of temporal
+    closeness (params.closeness_span), 2 unsigned triangle angles
+    (params.angle_unsigned)."""
     span = int(bool(getattr(params, "closeness_span", False)))
     if span and getattr(params, "w_dummy", None) is not None:
         raise ValueError("the span reading of closeness is not defined with dummies")
-    return span
+    return span | (2 if getattr(params, "angle_unsigned", False) else 0)
 
 
 def match(model, scene, params, taus=None, n_threads: int = 0):
@@ -111,7 +113,7 @@ def match(model, scene, params, taus=None, n_threads: int = 0):
             _f32(scene.desc)]
     rc = lib.oracle_match(M, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n, scene.n_frames,
                           _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]), model.dim,
-                          params.lambda1, params.lambda2, params.lambda3, params.T, _span(params),
+                          params.lambda1, params.lambda2, params.lambda3, params.T, _readings(params),
                           params.window, params.k_max, int(params.k_density), *_dummy(params),
                           _ptr(taus), n,
                           _ptr(e), _ptr(eu), _ptr(z), _ptr(c), n_threads)
@@ -139,7 +141,7 @@ def match_lists(model, scene, params, lists, counts, n_threads: int = 0):
     rc = lib.oracle_match_lists(M, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n,
                                 scene.n_frames, _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]),
                                 model.dim, params.lambda1, params.lambda2, params.lambda3, params.T,
-                                _span(params), K, *_dummy(params), _ptr(lists), _ptr(counts), n, _ptr(e), _ptr(eu),
+                                _readings(params), K, *_dummy(params), _ptr(lists), _ptr(counts), n, _ptr(e), _ptr(eu),
                                 _ptr(z),
                                 n_threads)
     if rc != 0:
@@ -174,7 +176,7 @@ def energies(model, scene, params, assign):
             _f32(scene.desc)]
     lib.oracle_energies(model.n, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), scene.n,
                         scene.n_frames, _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]), model.dim,
-                        params.lambda1, params.lambda2, params.lambda3, params.T, _span(params),
+                        params.lambda1, params.lambda2, params.lambda3, params.T, _readings(params),
                         *_dummy(params), _ptr(z), n,
                         _ptr(e), _ptr(eu))
     return e, eu

@@ -125,13 +125,22 @@ def delta(t_p: int, t_q: int, tp_p: int, tp_q: int) -> float:
     return float(abs((int(t_p) - int(t_q)) - (int(tp_p) - int(tp_q))))
 
 
-def triangle_cost(model, scene, i: int, zi: int, zj: int, zk: int, lambda3: float) -> float:
+def angle_unsigned(params) -> bool:
+    """True for the unsigned reading of the triangle angles (flag
+    STM_ANGLE_UNSIGNED): each angle is the magnitude of the oriented one, in
+    [0, pi], so a triangle and its mirror image have the same angles."""
+    return bool(getattr(params, "angle_unsigned", False))
+
+
+def triangle_cost(model, scene, i: int, zi: int, zj: int, zk: int, lambda3: float,
+                  unsigned: bool = False) -> float:
     """D(z_i, z_{i-1}, z_{i-2}) = D^t + lambda3 D^g for the hyperedge
     (i, j, k) = (i, i-1, i-2) of the chain (Eq. 3, Eq. 9).
 
     D^t = Delta(i, j) + Delta(j, k) (Eq. 4).
     D^g = L2 norm of the wrapped differences of the angle at j and the angle
-    at i between model and scene triangles (Eq. 6).
+    at i between model and scene triangles (Eq. 6); with `unsigned`, of the
+    differences of their magnitudes.
 
     READING for dummies (the paper defines only U for them, Eq. 2): a Delta
     term counts only when both of its points are scene points, D^g only when
@@ -146,8 +155,13 @@ def triangle_cost(model, scene, i: int, zi: int, zj: int, zk: int, lambda3: floa
     if DUMMY in (zi, zj, zk):
         return dt
     p, q = model.xy.astype(np.float64), scene.xy.astype(np.float64)
-    d_mid = wrap(ang(p[i], p[j], p[k]) - ang(q[zi], q[zj], q[zk]))
-    d_end = wrap(ang(p[j], p[i], p[k]) - ang(q[zj], q[zi], q[zk]))
+    a_mid = (ang(p[i], p[j], p[k]), ang(q[zi], q[zj], q[zk]))
+    a_end = (ang(p[j], p[i], p[k]), ang(q[zj], q[zi], q[zk]))
+    if unsigned:
+        a_mid = (abs(a_mid[0]), abs(a_mid[1]))
+        a_end = (abs(a_end[0]), abs(a_end[1]))
+    d_mid = wrap(a_mid[0] - a_mid[1])
+    d_end = wrap(a_end[0] - a_end[1])
     return dt + lambda3 * math.sqrt(d_mid * d_mid + d_end * d_end)
 
 
@@ -162,7 +176,8 @@ def energy(model, scene, z, params) -> float:
     consecutive points breaks causality or closeness (Eq. 7, Eq. 8).  READING:
     the constraints bind consecutive points that are both scene points; a
     dummy on either side lifts them.  With params.closeness_span, closeness is
-    the span of each triangle instead (span_ok, Section 3.4)."""
+    the span of each triangle instead (span_ok, Section 3.4); with
+    params.angle_unsigned, D^g compares the magnitudes of the angles."""
     M = len(z)
     if DUMMY in list(z) and w_dummy(params) is None:
         return INF
@@ -183,7 +198,7 @@ def energy(model, scene, z, params) -> float:
             if not admissible(int(scene.t[z[i - 1]]), int(scene.t[z[i]]), params.T):
                 return INF
     eu = sum(unary_of(model, scene, i, z[i], params) for i in range(M))
-    ed = sum(triangle_cost(model, scene, i, z[i], z[i - 1], z[i - 2], params.lambda3)
+    ed = sum(triangle_cost(model, scene, i, z[i], z[i - 1], z[i - 2], params.lambda3, angle_unsigned(params))
              for i in range(2, M))
     return params.lambda1 * eu + params.lambda2 * ed
 

@@ -37,6 +37,9 @@
 #endif
 
 #define ORACLE_PI 3.14159265358979323846
+/* bits of the `readings` argument: alternative readings of the paper */
+#define ORACLE_SPAN 1     /* closeness as the span of each triangle (Eq. 14) */
+#define ORACLE_UNSIGNED 2 /* unsigned triangle angles (Eq. 6) */
 #define ORACLE_EPS (-2) /* the dummy value epsilon in assignments */
 
 typedef struct {
@@ -48,6 +51,7 @@ typedef struct {
   int32_t dummy; /* dummy assignments enabled */
   double wd;     /* W^d, the unary cost of a dummy (Eq. 2) */
   int32_t span;  /* closeness as the span of each triangle (see triple_ok) */
+  int32_t uns;   /* unsigned triangle angles (see triangle_cost) */
 } problem;
 
 /* Oriented angle at vertex b of triangle (a, b, c), ray b->a to ray b->c;
@@ -112,6 +116,11 @@ static double triangle_cost(const problem* p, int i, int32_t zi, int32_t zj, int
   double mid_s = ang(s[2 * zi], s[2 * zi + 1], s[2 * zj], s[2 * zj + 1], s[2 * zk], s[2 * zk + 1]);
   double end_m = ang(m[2 * j], m[2 * j + 1], m[2 * i], m[2 * i + 1], m[2 * k], m[2 * k + 1]);
   double end_s = ang(s[2 * zj], s[2 * zj + 1], s[2 * zi], s[2 * zi + 1], s[2 * zk], s[2 * zk + 1]);
+  if (p->uns) {
+    /* READING (unsigned angles): the magnitudes of the oriented angles, so a
+     * triangle and its mirror image have the same angles */
+    mid_m = fabs(mid_m); mid_s = fabs(mid_s); end_m = fabs(end_m); end_s = fabs(end_s);
+  }
   double d1 = wrap(mid_m - mid_s), d2 = wrap(end_m - end_s);
   return dt + p->lambda3 * sqrt(d1 * d1 + d2 * d2);
 }
@@ -324,12 +333,14 @@ done:
 static problem make_problem(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                             int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
                             int32_t dim, double l1, double l2, double l3, int32_t T, int32_t W, int32_t K,
-                            int32_t k_density, int32_t dummy, double wd, int32_t span) {
+                            int32_t k_density, int32_t dummy, double wd, int32_t readings) {
   problem p;
   p.M = M; p.S = S; p.F = F; p.dim = dim;
   p.mxy = mxy; p.mt = mt; p.mdesc = mdesc; p.sxy = sxy; p.st = st; p.sdesc = sdesc;
   p.lambda1 = l1; p.lambda2 = l2; p.lambda3 = l3; p.T = T; p.W = W; p.K = K; p.k_density = k_density;
-  p.dummy = dummy; p.wd = wd; p.span = span;
+  p.dummy = dummy; p.wd = wd;
+  p.span = readings & ORACLE_SPAN;
+  p.uns = (readings & ORACLE_UNSIGNED) != 0;
   return p;
 }
 
@@ -339,11 +350,11 @@ static problem make_problem(int32_t M, const float* mxy, const int32_t* mt, cons
  * Returns 0, or -5 if a re-evaluated optimum disagreed with the recursion. */
 int oracle_match(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                  int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
-                 int32_t dim, double l1, double l2, double l3, int32_t T, int32_t span, int32_t W, int32_t K,
+                 int32_t dim, double l1, double l2, double l3, int32_t T, int32_t readings, int32_t W, int32_t K,
                  int32_t k_density, int32_t dummy, double wd, const int32_t* taus, int32_t n_tau,
                  double* energy, double* energy_u, int32_t* assign, long long* counts, int32_t n_threads) {
   problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, W, K, k_density,
-                           dummy, wd, span);
+                           dummy, wd, readings);
   long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
   int rc = 0;
 #ifdef _OPENMP
@@ -365,11 +376,11 @@ int oracle_match(int32_t M, const float* mxy, const int32_t* mt, const float* md
  * offsets matter only through the lists.  Returns as oracle_match. */
 int oracle_match_lists(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                        int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
-                       int32_t dim, double l1, double l2, double l3, int32_t T, int32_t span, int32_t K,
+                       int32_t dim, double l1, double l2, double l3, int32_t T, int32_t readings, int32_t K,
                        int32_t dummy, double wd, const int32_t* lists, const int32_t* counts_in,
                        int32_t n_tau, double* energy, double* energy_u, int32_t* assign, int32_t n_threads) {
   problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, K, 0, dummy, wd,
-                           span);
+                           readings);
   int rc = 0;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -387,10 +398,10 @@ int oracle_match_lists(int32_t M, const float* mxy, const int32_t* mt, const flo
  * energy_u nullable. */
 void oracle_energies(int32_t M, const float* mxy, const int32_t* mt, const float* mdesc,
                      int32_t S, int32_t F, const float* sxy, const int32_t* st, const float* sdesc,
-                     int32_t dim, double l1, double l2, double l3, int32_t T, int32_t span, int32_t dummy,
+                     int32_t dim, double l1, double l2, double l3, int32_t T, int32_t readings, int32_t dummy,
                      double wd, const int32_t* z, int32_t n, double* energy, double* energy_u) {
   problem p = make_problem(M, mxy, mt, mdesc, S, F, sxy, st, sdesc, dim, l1, l2, l3, T, 0, 1, 0, dummy, wd,
-                           span);
+                           readings);
   for (int32_t j = 0; j < n; ++j)
     energy[j] = oracle_energy(&p, z + (size_t)j * M, energy_u ? energy_u + j : NULL);
 }

@@ -56,6 +56,7 @@ class Params:
     unary_bf16: bool = False  # unary table from BF16 descriptors on MFMA
     w_dummy: float | None = None  # W^d: unary cost of a dummy assignment (Eq. 2); None = no dummies
     closeness_span: bool = False  # closeness as the triangle span t'(z_i) - t'(z_{i-2}) < T (Eq. 14)
+    angle_unsigned: bool = False  # triangle angles as magnitudes in [0, pi] (Eq. 6, alternative reading)
 
 
 @dataclasses.dataclass
