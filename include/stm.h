@@ -104,6 +104,15 @@ extern "C" {
                                  consecutive points.  Consecutive points are then at
                                  most T - 2 frames apart.  No effect with T <= 0;
                                  not with STM_DUMMY (STM_EUNSUPPORTED).             */
+#define STM_ANGLE_UNSIGNED 0x40u  /* the angles of Eq. 6 read as magnitudes in [0, pi]
+                                 (unoriented), so that a triangle and its mirror
+                                 image match; the default reads them oriented
+                                 (atan2 of cross and dot products).  Exact path,
+                                 lists and plans (stm_match, stm_match_lists,
+                                 stm_match_batch, stm_plan_*, stm_match_noalloc,
+                                 stm_match_chains);
+                                 not with STM_DUMMY, the pruner or the trellis
+                                 (STM_EUNSUPPORTED)                                 */
 #define STM_TRELLIS_STEPWISE 0x20u  /* trellis (stm_trellis_*) only: one launch per
                                  step even where the band fits one workgroup's LDS
                                  and all steps would run in one launch; the two give

@@ -333,7 +333,7 @@ struct DPResult {
 
 // Forward pass of one matching by the whole workgroup (NW waves): writes the
 // value tables of steps 1..M-2 to vtm and returns the optimum to every thread.
-template <int NW, bool DEGEN, int KL, bool DUMMY = false, bool PACKED = false>
+template <int NW, bool DEGEN, int KL, bool DUMMY = false, bool PACKED = false, bool UNS = false>
 __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchView& a, float* vtm) {
   static_assert(KL == 16 || KL == 32 || KL == 64, "list capacity");
   static_assert(!DUMMY || KL == kMaxList, "dummies use the 64-slot layout");
@@ -550,7 +550,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           if (!DEGEN && same && valid) sh.flag = 1;
           anew = neg_dir<DEGEN>(xr, xa);
           float bm, be;
-          cell_brackets(th, -anew, bm, be);
+          cell_consts<UNS>(th, anew, bm, be);
           const float2* vcol = sh.va + r;
           const float* ccol = sh.ct + col;
           const int len = hi - lo;
@@ -562,7 +562,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           for (int j = 0; j < longest; ++j) {
             const int kk = min(lo + min(j, last), KL - 1);
             const float2 v0 = vcol[kk * KL];
-            const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[kk * KL], bm, be, th, same, w);
+            const float t0 = relax<DEGEN, UNS>(v0.x, v0.y, ccol[kk * KL], bm, be, th, same, w);
             best = fminf(best, j < len ? t0 : INF);
           }
           const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
@@ -584,7 +584,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           if (!DEGEN && same && valid) sh.flag = 1;
           anew = neg_dir<DEGEN>(xr, xa);
           float bm, be;
-          cell_brackets(th, -anew, bm, be);
+          cell_consts<UNS>(th, anew, bm, be);
           const float2* vcol = sh.va + r;
           const float* ccol = sh.ct + col;
           float best = INF;
@@ -597,32 +597,32 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           for (; kEight && k + 7 < c.hi; k += 8) {
             const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
             const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
-            const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
-            const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
-            const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
-            const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
+            const float t0 = relax<DEGEN, UNS>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
+            const float t1 = relax<DEGEN, UNS>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
+            const float t2 = relax<DEGEN, UNS>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
+            const float t3 = relax<DEGEN, UNS>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
             best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
             const float2 v4 = vcol[(k + 4) * KL], v5 = vcol[(k + 5) * KL];
             const float2 v6 = vcol[(k + 6) * KL], v7 = vcol[(k + 7) * KL];
-            const float t4 = relax<DEGEN>(v4.x, v4.y, ccol[(k + 4) * KL], bm, be, th, same, w);
-            const float t5 = relax<DEGEN>(v5.x, v5.y, ccol[(k + 5) * KL], bm, be, th, same, w);
-            const float t6 = relax<DEGEN>(v6.x, v6.y, ccol[(k + 6) * KL], bm, be, th, same, w);
-            const float t7 = relax<DEGEN>(v7.x, v7.y, ccol[(k + 7) * KL], bm, be, th, same, w);
+            const float t4 = relax<DEGEN, UNS>(v4.x, v4.y, ccol[(k + 4) * KL], bm, be, th, same, w);
+            const float t5 = relax<DEGEN, UNS>(v5.x, v5.y, ccol[(k + 5) * KL], bm, be, th, same, w);
+            const float t6 = relax<DEGEN, UNS>(v6.x, v6.y, ccol[(k + 6) * KL], bm, be, th, same, w);
+            const float t7 = relax<DEGEN, UNS>(v7.x, v7.y, ccol[(k + 7) * KL], bm, be, th, same, w);
             best = fminf(fminf(best, fminf(fminf(t4, t5), t6)), t7);
           }
           if (k + 3 < c.hi) {
             const float2 v0 = vcol[k * KL], v1 = vcol[(k + 1) * KL];
             const float2 v2 = vcol[(k + 2) * KL], v3 = vcol[(k + 3) * KL];
-            const float t0 = relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
-            const float t1 = relax<DEGEN>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
-            const float t2 = relax<DEGEN>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
-            const float t3 = relax<DEGEN>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
+            const float t0 = relax<DEGEN, UNS>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w);
+            const float t1 = relax<DEGEN, UNS>(v1.x, v1.y, ccol[(k + 1) * KL], bm, be, th, same, w);
+            const float t2 = relax<DEGEN, UNS>(v2.x, v2.y, ccol[(k + 2) * KL], bm, be, th, same, w);
+            const float t3 = relax<DEGEN, UNS>(v3.x, v3.y, ccol[(k + 3) * KL], bm, be, th, same, w);
             best = fminf(fminf(best, fminf(fminf(t0, t1), t2)), t3);
             k += 4;
           }
           for (; k < c.hi; ++k) {
             const float2 v0 = vcol[k * KL];
-            best = fminf(best, relax<DEGEN>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w));
+            best = fminf(best, relax<DEGEN, UNS>(v0.x, v0.y, ccol[k * KL], bm, be, th, same, w));
           }
           const float q = qw * fabsf(static_cast<float>(dtm - (tp - tr)));
           vnew = (sh.cu[s0][col] + q) + best;
@@ -749,7 +749,7 @@ __device__ __forceinline__ LaneCand lane_cand(const MatchView& a, int j, int lan
   return L;
 }
 
-template <bool DEGEN, bool DUMMY = false>
+template <bool DEGEN, bool DUMMY = false, bool UNS = false>
 __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int c, int lane,
                                int32_t* out) {
   const int M = a.m.M, Kc = a.sp.K, VS = a.vs;
@@ -796,9 +796,9 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
         const float2 th = ro(a.theta + i);
         const bool same = xa.x == xr.x && xa.y == xr.y;
         float bm, be;
-        cell_brackets(th, -neg_dir<DEGEN>(xr, xa), bm, be);
+        cell_consts<UNS>(th, neg_dir<DEGEN>(xr, xa), bm, be);
         if (lane < nk && admissible(Lk.t, tr, T) && span_ok(Lk.t, tc, TS))
-          tot = relax<DEGEN>(vcol, neg_dir<DEGEN>(Lk.xy, xr), neg_dir<DEGEN>(Lk.xy, xa), bm, be, th, same, a.w);
+          tot = relax<DEGEN, UNS>(vcol, neg_dir<DEGEN>(Lk.xy, xr), neg_dir<DEGEN>(Lk.xy, xa), bm, be, th, same, a.w);
       }
     }
     int bk = lane;
@@ -844,14 +844,14 @@ __device__ __forceinline__ float* scratch_of(const DPLaunch& a, int tl) {
   return a.vt + (long long)tl * (a.m.M - 2) * vs * vs;
 }
 
-template <int NW, bool DEGEN, int KL, bool DUMMY = false, bool PACKED = false>
+template <int NW, bool DEGEN, int KL, bool DUMMY = false, bool PACKED = false, bool UNS = false>
 __global__ __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu(KL == kMaxList && NW == 8 ? 4 : 1)))
 void k_dp(DPLaunch a) {
   __shared__ DPShared<NW, KL, DUMMY, PACKED> sh;
   const int tl = blockIdx.x;
   if (DEGEN && a.degen[tl] == 0) return;
-  const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY, PACKED>(sh, view_of(a, tl), scratch_of(a, tl));
+  const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY, PACKED, UNS>(sh, view_of(a, tl), scratch_of(a, tl));
   if (threadIdx.x == 0) {
     constexpr int RS = KL + (DUMMY ? 1 : 0);
     a.e32[tl] = r.v;
@@ -874,6 +874,9 @@ __global__ __launch_bounds__(64) void k_backtrack(DPLaunch a, int32_t* __restric
   if (a.dummy) {
     if (a.degen[tl]) backtrack_wave<true, true>(v, vt, l2.x, l2.y, lane, out);
     else backtrack_wave<false, true>(v, vt, l2.x, l2.y, lane, out);
+  } else if (a.sp.uns) {
+    if (a.degen[tl]) backtrack_wave<true, false, true>(v, vt, l2.x, l2.y, lane, out);
+    else backtrack_wave<false, false, true>(v, vt, l2.x, l2.y, lane, out);
   } else {
     if (a.degen[tl]) backtrack_wave<true>(v, vt, l2.x, l2.y, lane, out);
     else backtrack_wave<false>(v, vt, l2.x, l2.y, lane, out);
@@ -917,7 +920,7 @@ __device__ __forceinline__ MatchView view_of(const BatchLaunch& b, const PairDev
 // the LDS of one matching would allow three, but at 80 registers the kernel
 // spills and runs slower (1.3% on the realistic workload, 3.9% on the batched
 // one).
-template <int NW, bool DEGEN, int KL = kMaxList, bool DUMMY = false, bool PACKED = false>
+template <int NW, bool DEGEN, int KL = kMaxList, bool DUMMY = false, bool PACKED = false, bool UNS = false>
 __global__ __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu(DUMMY || PACKED ? 4 : (NW >= 8 ? 4 : 3))))
 void k_dp_persistent(BatchLaunch b) {
@@ -941,7 +944,7 @@ void k_dp_persistent(BatchLaunch b) {
       const int2 it = b.items[item];
       const PairDev pd = b.pairs[it.x];
       const MatchView mv = view_of(b, pd, it.y);
-      const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY, PACKED>(sh, mv, vwg + slot * b.vt_stride);
+      const DPResult r = dp_forward<NW, DEGEN, KL, DUMMY, PACKED, UNS>(sh, mv, vwg + slot * b.vt_stride);
       if (threadIdx.x == 0) {
         if (!DEGEN && r.flag) {
           b.degen_items[atomicAdd(b.degen_count, 1)] = item;
@@ -962,7 +965,7 @@ void k_dp_persistent(BatchLaunch b) {
         int32_t* out = b.assign + pd.assign0 + (long long)it.y * pd.m.M;
         const int idx = bt_idx[wv];
         if (idx >= 0) {
-          backtrack_wave<DEGEN, DUMMY>(view_of(b, pd, it.y), vwg + wv * b.vt_stride, idx / RS, idx % RS, lane,
+          backtrack_wave<DEGEN, DUMMY, UNS>(view_of(b, pd, it.y), vwg + wv * b.vt_stride, idx / RS, idx % RS, lane,
                                        out);
         } else {
           for (int i = lane; i < pd.m.M; i += 64) out[i] = -1;
@@ -1083,10 +1086,16 @@ __device__ void rescore_wave(const ModelView& m, const SceneView& s, const Searc
       const long dt2 = (long)(ro(m.t + (i - 1)) - ro(m.t + (i - 2))) - (long)(ro(s.t + nj) - ro(s.t + nk));
       const float2 pi = ro(m.xy + i), pj = ro(m.xy + (i - 1)), pk = ro(m.xy + (i - 2));
       const float2 qi = ro(s.xy + n), qj = ro(s.xy + nj), qk = ro(s.xy + nk);
-      const double mid_m = ang64(pi.x, pi.y, pj.x, pj.y, pk.x, pk.y);
-      const double mid_s = ang64(qi.x, qi.y, qj.x, qj.y, qk.x, qk.y);
-      const double end_m = ang64(pj.x, pj.y, pi.x, pi.y, pk.x, pk.y);
-      const double end_s = ang64(qj.x, qj.y, qi.x, qi.y, qk.x, qk.y);
+      double mid_m = ang64(pi.x, pi.y, pj.x, pj.y, pk.x, pk.y);
+      double mid_s = ang64(qi.x, qi.y, qj.x, qj.y, qk.x, qk.y);
+      double end_m = ang64(pj.x, pj.y, pi.x, pi.y, pk.x, pk.y);
+      double end_s = ang64(qj.x, qj.y, qi.x, qi.y, qk.x, qk.y);
+      if (sp.uns) {  // the unsigned reading: magnitudes of the angles
+        mid_m = fabs(mid_m);
+        mid_s = fabs(mid_s);
+        end_m = fabs(end_m);
+        end_s = fabs(end_s);
+      }
       const double d1 = wrap64(mid_m - mid_s), d2 = wrap64(end_m - end_s);
       sd += (double)(dt1 < 0 ? -dt1 : dt1) + (double)(dt2 < 0 ? -dt2 : dt2) +
             l3 * sqrt(d1 * d1 + d2 * d2);
@@ -1134,6 +1143,10 @@ hipError_t launch_dp_waves(const DPLaunch& a, hipStream_t st) {
     hipLaunchKernelGGL((k_dp<8, DEGEN, 64, true>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
     return hipGetLastError();
   }
+  if (a.sp.uns) {  // unsigned angles: one variant, 8 waves, the 64-slot layout and dense schedules
+    hipLaunchKernelGGL((k_dp<8, DEGEN, 64, false, false, true>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.packed && a.sp.K > 32) {  // sparse scenes, long lists: packed schedules
     hipLaunchKernelGGL((k_dp<8, DEGEN, 64, false, true>), dim3(a.n_tau), dim3(8 * 64), 0, st, a);
     return hipGetLastError();
@@ -1169,6 +1182,11 @@ template <bool DEGEN>
 hipError_t launch_persistent_variant(const BatchLaunch& b, int n_wg, hipStream_t st) {
   if (b.dummy) {  // dummies: 8 waves whatever the tuning says
     hipLaunchKernelGGL((k_dp_persistent<8, DEGEN, kMaxList, true>), dim3(n_wg), dim3(8 * 64), 0, st, b);
+    return hipGetLastError();
+  }
+  if (b.sp.uns) {  // unsigned angles: one variant, 8 waves, dense schedules
+    hipLaunchKernelGGL((k_dp_persistent<8, DEGEN, kMaxList, false, false, true>), dim3(n_wg), dim3(8 * 64), 0, st,
+                       b);
     return hipGetLastError();
   }
   if (b.packed) {  // sparse scenes: packed schedules, 8 waves

@@ -69,13 +69,40 @@ __device__ __forceinline__ void cell_brackets(float2 th, float phi, float& bm, f
   be = wrap_pi(th.y + phi);
 }
 
+// The per-cell constants of relax from the cell's stored direction anew =
+// -phi(z_{i-1} -> z_i): the brackets above (oriented angles), or with unsigned
+// angles pi + anew and anew, from which the scene triangle's angles at z_{i-1}
+// and z_i are wrap(pi + anew - A) and wrap(anew - C).
+template <bool UNS>
+__device__ __forceinline__ void cell_consts(float2 th, float anew, float& bm, float& be) {
+  if constexpr (UNS) {
+    bm = kPi + anew;
+    be = anew;
+  } else {
+    cell_brackets(th, -anew, bm, be);
+  }
+}
+
 // One relaxation term V_{i-1}(a_{i-2}, a_{i-1}) + l2 l3 D^g_i.  A = -phi(z_{i-2}
-// -> z_{i-1}), C = -phi(z_{i-2} -> z_i); same_rc: z_{i-1} and z_i coincide.
-// The forward pass and backtracking both evaluate terms through this function,
-// so they agree bit for bit.
-template <bool DEGEN>
+// -> z_{i-1}), C = -phi(z_{i-2} -> z_i); same_rc: z_{i-1} and z_i coincide; bm,
+// be from cell_consts<UNS>.  UNS: the unsigned reading of the angles, each
+// difference taken between the magnitudes of the model's and the scene's
+// angle.  The forward pass and backtracking both evaluate terms through this
+// function, so they agree bit for bit.
+template <bool DEGEN, bool UNS = false>
 __device__ __forceinline__ float relax(float v, float A, float C, float bm, float be, float2 th,
                                        bool same_rc, float w) {
+  if constexpr (UNS) {
+    const float am = fabsf(th.x), ae = fabsf(th.y);
+    float z1 = am - fabsf(wrap_pi(bm - A)), z2 = ae - fabsf(wrap_pi(be - C));
+    if (DEGEN) {  // a zero-length side makes the scene's angle 0
+      z1 = (same_rc || isnan(A)) ? am : z1;
+      z2 = (same_rc || isnan(C)) ? ae : z2;
+    }
+    const float t = fmaf(w, __builtin_amdgcn_sqrtf(fmaf(z2, z2, z1 * z1)), v);
+    // +inf marks a triangle the span reading of closeness excludes
+    return C == __builtin_inff() ? __builtin_inff() : t;
+  }
   float x1, x2;
   if (DEGEN) {
     // +inf marks a triangle the span reading of closeness excludes (the fast

@@ -753,6 +753,8 @@ int stm_plan_run_pruned(stm_plan* p, stm_pruner* P, int32_t topk, float* energy3
   if (topk < 1 || topk > 64) return fail(STM_EINVAL, "topk must be in [1, 64]");
   if (p->bf16) return fail(STM_EUNSUPPORTED, "pruned runs of plans with the BF16 unary table are not built");
   if (dummy_on(&p->params)) return fail(STM_EUNSUPPORTED, "pruned runs of plans with dummy assignments are not built");
+  if (p->params.flags & STM_ANGLE_UNSIGNED)
+    return fail(STM_EUNSUPPORTED, "pruned runs of plans with unsigned angles are not built");
   if (p->row_off.back() > 0 && (!energy32 || !assign)) return fail(STM_EINVAL, "energy32 and assign are required");
   STM_HIP(hipSetDevice(p->ctx->device));
   const int kp = std::min<int>(topk, p->params.k_max);

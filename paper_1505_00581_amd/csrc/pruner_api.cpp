@@ -557,6 +557,8 @@ int stm_match_pruned(stm_ctx* ctx, stm_pruner* P, const stm_points* model, const
   if (P->ctx != ctx) return fail(STM_EINVAL, "the pruner belongs to another context");
   if (topk < 1 || topk > kSlots) return fail(STM_EINVAL, "topk must be in [1, 64]");
   if (params && dummy_on(params)) return fail(STM_EUNSUPPORTED, "pruned matching with dummy assignments is not built");
+  if (params && (params->flags & STM_ANGLE_UNSIGNED))
+    return fail(STM_EUNSUPPORTED, "pruned matching with unsigned angles is not built");
   Prepared pr;
   if ((rc = pair_inputs(P, model, scene, params, hip_stream, pr))) return rc;
   if ((rc = check_range(pr, tau_begin, tau_end))) return rc;

@@ -29,6 +29,7 @@ struct ModelView {
 struct SearchParams {
   int32_t T, W, K, kdensity;
   int32_t span;  // closeness as the span of each triangle (Section 3.4, Eq. 14)
+  int32_t uns;   // unsigned triangle angles (the magnitudes of Eq. 6's angles)
 };
 
 // Closeness limit of consecutive points: T of Eq. 8, or under the span reading
