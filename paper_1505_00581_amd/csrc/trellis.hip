@@ -435,6 +435,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_trellis_fused(TrellisRun a) {
         cell_brackets(th, -arc[j], bm, be);
         const int32_t r = cr[j], c = cc[j];
         float best = INF;
+        // unrolled by two (the whole video at T = 10, one model: 0.49 ms per run,
+        // against 0.53 not unrolled and 0.52 by four)
+#pragma unroll 2
         for (int32_t k = lo[j]; k < hi[j]; ++k) {
           const int2 kk = kin[k];
           const int32_t off = kk.x + r;  // cell (k, r)
