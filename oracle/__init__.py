@@ -87,11 +87,15 @@ def _dummy(params):
 def _readings(params) -> int:
     """Bits of the alternative readings: 1 the span reading of temporal
     closeness (params.closeness_span), 2 unsigned triangle angles
-    (params.angle_unsigned)."""
+    (params.angle_unsigned), 4 causality by scene node order
+    (params.causal_node)."""
     span = int(bool(getattr(params, "closeness_span", False)))
     if span and getattr(params, "w_dummy", None) is not None:
         raise ValueError("the span reading of closeness is not defined with dummies")
-    return span | (2 if getattr(params, "angle_unsigned", False) else 0)
+    node = bool(getattr(params, "causal_node", False))
+    if node and span:
+        raise ValueError("node-order causality is taken with the pairwise reading of closeness only")
+    return span | (2 if getattr(params, "angle_unsigned", False) else 0) | (4 if node else 0)
 
 
 def match(model, scene, params, taus=None, n_threads: int = 0):

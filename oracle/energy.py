@@ -111,6 +111,18 @@ def span_ok(tp_first: int, tp_last: int, T: int) -> bool:
     return T <= 0 or int(tp_last) - int(tp_first) < T
 
 
+def causal_node(params) -> bool:
+    """True for causality by scene node order (flag STM_CAUSAL_NODE): z_{i-1} <
+    z_i as node ids, which in a scene sorted by frame allows equal frames."""
+    return bool(getattr(params, "causal_node", False))
+
+
+def admissible_node(z_prev: int, z_cur: int, tp_prev: int, tp_cur: int, T: int) -> bool:
+    """Causality by node order and temporal closeness (Eq. 8) for consecutive
+    model points: z_{i-1} < z_i, scene frames less than T apart."""
+    return z_prev < z_cur and (T <= 0 or tp_cur - tp_prev < T)
+
+
 def admissible(tp_prev: int, tp_cur: int, T: int) -> bool:
     """Causality (Eq. 7) for consecutive model points i-1 < i: the scene frames
     must be strictly increasing.  Temporal closeness (Eq. 8): consecutive scene
@@ -177,7 +189,8 @@ def energy(model, scene, z, params) -> float:
     the constraints bind consecutive points that are both scene points; a
     dummy on either side lifts them.  With params.closeness_span, closeness is
     the span of each triangle instead (span_ok, Section 3.4); with
-    params.angle_unsigned, D^g compares the magnitudes of the angles."""
+    params.angle_unsigned, D^g compares the magnitudes of the angles; with
+    params.causal_node, causality is node order (admissible_node)."""
     M = len(z)
     if DUMMY in list(z) and w_dummy(params) is None:
         return INF
@@ -195,7 +208,10 @@ def energy(model, scene, z, params) -> float:
         for i in range(1, M):
             if z[i - 1] == DUMMY or z[i] == DUMMY:
                 continue
-            if not admissible(int(scene.t[z[i - 1]]), int(scene.t[z[i]]), params.T):
+            tp, tc = int(scene.t[z[i - 1]]), int(scene.t[z[i]])
+            ok = (admissible_node(int(z[i - 1]), int(z[i]), tp, tc, params.T) if causal_node(params)
+                  else admissible(tp, tc, params.T))
+            if not ok:
                 return INF
     eu = sum(unary_of(model, scene, i, z[i], params) for i in range(M))
     ed = sum(triangle_cost(model, scene, i, z[i], z[i - 1], z[i - 2], params.lambda3, angle_unsigned(params))

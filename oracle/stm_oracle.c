@@ -40,6 +40,7 @@
 /* bits of the `readings` argument: alternative readings of the paper */
 #define ORACLE_SPAN 1     /* closeness as the span of each triangle (Eq. 14) */
 #define ORACLE_UNSIGNED 2 /* unsigned triangle angles (Eq. 6) */
+#define ORACLE_NODE 4     /* causality by scene node order (Eq. 7 alternative) */
 #define ORACLE_EPS (-2) /* the dummy value epsilon in assignments */
 
 typedef struct {
@@ -52,6 +53,7 @@ typedef struct {
   double wd;     /* W^d, the unary cost of a dummy (Eq. 2) */
   int32_t span;  /* closeness as the span of each triangle (see triple_ok) */
   int32_t uns;   /* unsigned triangle angles (see triangle_cost) */
+  int32_t node;  /* causality by node order (see pair_ok) */
 } problem;
 
 /* Oriented angle at vertex b of triangle (a, b, c), ray b->a to ray b->c;
@@ -81,6 +83,9 @@ static double delta(int32_t tp, int32_t tq, int32_t sp, int32_t sq) {
  * either side.  Under the span reading only causality binds the pair. */
 static int pair_ok(const problem* p, int32_t zprev, int32_t zcur) {
   if (zprev == ORACLE_EPS || zcur == ORACLE_EPS) return 1;
+  /* READING (node order): z_{i-1} < z_i as scene node ids, which in a scene
+   * sorted by frame allows equal frames; closeness as Eq. 8 */
+  if (p->node) return zprev < zcur && (p->T <= 0 || p->st[zcur] - p->st[zprev] < p->T);
   if (p->span) return p->st[zprev] < p->st[zcur];
   return admissible(p->st[zprev], p->st[zcur], p->T);
 }
@@ -98,6 +103,7 @@ static int triple_ok(const problem* p, int32_t zk, int32_t zi) {
  * pairwise constraints, or under the span reading causality with a gap of at
  * most T - 2 (a triangle holding the pair spans at least one more frame). */
 static int cell_ok(const problem* p, int32_t zprev, int32_t zcur) {
+  if (p->node) return pair_ok(p, zprev, zcur);
   if (!p->span) return admissible(p->st[zprev], p->st[zcur], p->T);
   if (!(p->st[zprev] < p->st[zcur])) return 0;
   return p->T <= 0 || p->st[zcur] - p->st[zprev] <= p->T - 2;
@@ -341,6 +347,7 @@ static problem make_problem(int32_t M, const float* mxy, const int32_t* mt, cons
   p.dummy = dummy; p.wd = wd;
   p.span = readings & ORACLE_SPAN;
   p.uns = (readings & ORACLE_UNSIGNED) != 0;
+  p.node = (readings & ORACLE_NODE) != 0;
   return p;
 }
 

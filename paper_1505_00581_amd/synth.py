@@ -57,6 +57,7 @@ class Params:
     w_dummy: float | None = None  # W^d: unary cost of a dummy assignment (Eq. 2); None = no dummies
     closeness_span: bool = False  # closeness as the triangle span t'(z_i) - t'(z_{i-2}) < T (Eq. 14)
     angle_unsigned: bool = False  # triangle angles as magnitudes in [0, pi] (Eq. 6, alternative reading)
+    causal_node: bool = False  # causality as node order z_{i-1} < z_i (Eq. 7, alternative reading)
 
 
 @dataclasses.dataclass
