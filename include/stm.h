@@ -113,6 +113,15 @@ extern "C" {
                                  stm_match_chains);
                                  not with STM_DUMMY, the pruner or the trellis
                                  (STM_EUNSUPPORTED)                                 */
+#define STM_CAUSAL_NODE 0x80u  /* causality (Eq. 7) read as increasing scene node ids,
+                                 z_{i-1} < z_i, which in a scene sorted by frame lets
+                                 consecutive points share a frame; closeness as Eq.
+                                 8.  The default reads strictly increasing frames.
+                                 Exact path and plans on the windowed lists
+                                 (stm_match, stm_match_batch, stm_plan_run,
+                                 stm_match_noalloc, stm_match_chains); not with
+                                 STM_DUMMY, STM_CLOSENESS_SPAN, given lists, the
+                                 pruner or the trellis (STM_EUNSUPPORTED)             */
 #define STM_TRELLIS_STEPWISE 0x20u  /* trellis (stm_trellis_*) only: one launch per
                                  step even where the band fits one workgroup's LDS
                                  and all steps would run in one launch; the two give

@@ -26,6 +26,7 @@ STM_DUMMY = 0x8
 STM_CLOSENESS_SPAN = 0x10
 STM_TRELLIS_STEPWISE = 0x20  # trellis: one launch per step even where the band fits LDS
 STM_ANGLE_UNSIGNED = 0x40  # triangle angles read as magnitudes (params.angle_unsigned)
+STM_CAUSAL_NODE = 0x80  # causality as increasing scene node ids (params.causal_node)
 STM_DUMMY_NODE = -2  # assignment value of a dummy (unmatched model point)
 STM_UNCHAINED_NODE = -3  # assignment value of a point in no kept chain (stm_match_chains)
 STM_NOALLOC_SCRATCH_BYTES = 256 << 20  # fixed device array of stm_match_noalloc
@@ -200,7 +201,8 @@ def _params(params, device: bool) -> _Params:
              | (STM_UNARY_BF16 if getattr(params, "unary_bf16", False) else 0)
              | (STM_DUMMY if wd is not None else 0)
              | (STM_CLOSENESS_SPAN if getattr(params, "closeness_span", False) else 0)
-             | (STM_ANGLE_UNSIGNED if getattr(params, "angle_unsigned", False) else 0))
+             | (STM_ANGLE_UNSIGNED if getattr(params, "angle_unsigned", False) else 0)
+             | (STM_CAUSAL_NODE if getattr(params, "causal_node", False) else 0))
     return _Params(params.lambda1, params.lambda2, params.lambda3, params.T, params.window,
                    params.k_max, flags, 0.0 if wd is None else float(wd))
 

@@ -63,8 +63,10 @@ int check_shapes(const stm_points* m, const stm_points* s, const stm_params* p) 
   if (!finite_lambda(p->lambda1) || !finite_lambda(p->lambda2) || !finite_lambda(p->lambda3))
     return fail(STM_EINVAL, "lambdas must be finite and >= 0");
   if (p->flags & ~(STM_DEVICE_PTRS | STM_UNARY_BF16 | STM_K_DENSITY | STM_DUMMY | STM_CLOSENESS_SPAN |
-                   STM_ANGLE_UNSIGNED))
+                   STM_ANGLE_UNSIGNED | STM_CAUSAL_NODE))
     return fail(STM_EUNSUPPORTED, "unknown flag");
+  if ((p->flags & STM_CAUSAL_NODE) && (p->flags & (STM_DUMMY | STM_CLOSENESS_SPAN)))
+    return fail(STM_EUNSUPPORTED, "node-order causality is built for the pairwise reading without dummies only");
   if ((p->flags & STM_DUMMY) && (p->flags & STM_CLOSENESS_SPAN))
     return fail(STM_EUNSUPPORTED, "the span reading of closeness is not defined with dummies");
   if ((p->flags & STM_DUMMY) && (p->flags & STM_ANGLE_UNSIGNED))

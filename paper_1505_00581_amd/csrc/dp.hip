@@ -143,12 +143,27 @@ __device__ __forceinline__ bool chunk_cell(const Chunk& c, int lane, int& r, int
 // step's cell count, also stored in *ptot.
 __device__ void build_schedule(const int32_t* trow, int nrow, const int32_t* tcol, int ncol,
                                const int32_t* tprev, int nprev, int T, uint2* out, int32_t* nout,
-                               int lane, int16_t* pstart = nullptr, int32_t* ptot = nullptr) {
+                               int lane, int16_t* pstart = nullptr, int32_t* ptot = nullptr,
+                               const CandRange* nodes = nullptr) {
   const int f = lane < nrow ? trow[lane] : 0;
-  const bool start = lane < nrow && (lane == 0 || trow[lane - 1] != f);
+  // node-order causality (nodes: the windowed ranges of the rows', the
+  // columns' and the predecessors' lists): every row is a group of its own,
+  // its columns the nodes above its own within T frames, its predecessors the
+  // nodes below it within T frames
+  const bool start = lane < nrow && (nodes || lane == 0 || trow[lane - 1] != f);
   const unsigned long long starts = __ballot(start);
   int nchunk = 0, nr = 0, nc = 0, clo = 0, chi = 0, lo = 0, hi = 0;
-  if (__popcll(starts) <= 16) {
+  if (nodes) {
+    if (start) {
+      const int nd = cand_node(nodes[0], lane);
+      clo = range_count_le(nodes[1], nd);
+      chi = T > 0 ? count_lt(tcol, ncol, f > 0x7fffffff - T ? 0x7fffffff : f + T) : ncol;
+      if (tprev) {
+        hi = range_count_lt(nodes[2], nd);
+        lo = T > 0 ? count_lt(tprev, nprev, f - T + 1) : 0;
+      }
+    }
+  } else if (__popcll(starts) <= 16) {
     // few frame groups: each lane holds one column and one predecessor frame,
     // and every count is a ballot, one group after the other
     const int32_t tc = lane < ncol ? tcol[lane] : 0x7fffffff;  // frames are < 0x7fffffff
@@ -263,6 +278,7 @@ struct DPShared : DummyShared<KL, DUMMY>, PackedShared<KL, PACKED> {
   uint2 sched[2][KL];   // chunk schedules of the current and the previous step
   int32_t nch[2];
   int32_t ck[4];        //   list lengths
+  CandRange crange[4];  //   the windowed lists' node ranges (node-order causality)
   int32_t flag;         // coincident points seen (fast variant)
   float red_v[NW];
   int32_t red_i[NW];
@@ -376,13 +392,25 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
       return valid;
     }
   };
-  auto schedule = [&](const int32_t* trow, int nrow, const int32_t* tcol, int ncol, const int32_t* tprev, int nprev,
-                      int b) {
+  // sr, sc, sp: ring slots of the rows', columns' and predecessors' lists
+  auto schedule = [&](int sr, int sc, int spv, int b) {
+    const int32_t* trow = sh.ctt[sr];
+    const int32_t* tcol = sh.ctt[sc];
+    const int32_t* tprev = spv >= 0 ? sh.ctt[spv] : nullptr;
+    const int nrow = sh.ck[sr], ncol = sh.ck[sc], nprev = spv >= 0 ? sh.ck[spv] : 0;
+    CandRange rg[3];
+    if (a.sp.node) {
+      rg[0] = sh.crange[sr];
+      rg[1] = sh.crange[sc];
+      rg[2] = spv >= 0 ? sh.crange[spv] : CandRange{0, 0, 0, 0};
+    }
+    const CandRange* nodes = a.sp.node ? rg : nullptr;
     if constexpr (PACKED)
       build_schedule(trow, nrow, tcol, ncol, tprev, nprev, T, sh.sched[b], &sh.nch[b], lane, sh.pstart[b],
-                     &sh.ptot[b]);
+                     &sh.ptot[b], nodes);
     else
-      build_schedule(trow, nrow, tcol, ncol, tprev, nprev, T, sh.sched[b], &sh.nch[b], lane);
+      build_schedule(trow, nrow, tcol, ncol, tprev, nprev, T, sh.sched[b], &sh.nch[b], lane, nullptr, nullptr,
+                     nodes);
   };
 
   auto load_slot = [&](int j) {
@@ -396,7 +424,10 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
         sh.ctt[sl][lane] = ro(a.s.t + n);
         sh.cu[sl][lane] = a.lambda1 * ro(a.U + (long long)j * a.us + n);
       }
-      if (lane == 0) sh.ck[sl] = k;
+      if (lane == 0) {
+        sh.ck[sl] = k;
+        sh.crange[sl] = c.r;
+      }
     }
   };
 
@@ -405,7 +436,7 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
   load_slot(1);
   load_slot(2);
   __syncthreads();
-  if (wv == kBuilder) schedule(sh.ctt[0], sh.ck[0], sh.ctt[1], sh.ck[1], nullptr, 0, 1);
+  if (wv == kBuilder) schedule(0, 1, -1, 1);
   __syncthreads();
 
   float vr[RPW], ar[RPW];
@@ -472,16 +503,18 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
         if (ch < nprev && pi[s] >= 0) sh.va[pi[s]] = make_float2(vr[s], ar[s]);
       }
     }
-    if (wv == kBuilder) schedule(sh.ctt[s1], Kp, sh.ctt[s0], Kn, sh.ctt[s2], Kq, cur);
+    if (wv == kBuilder) schedule(s1, s0, s2, cur);
     {
       // the (a_{i-2}, a_i) direction of row k, column c; a pair is used only
       // if some z_{i-1} fits strictly between its frames and within T of
-      // both: 2 <= t_i - t_{i-2} <= 2T - 2.  Under the span reading a pair
-      // whose frames are TS or more apart gets +inf, which takes its terms
-      // out of every minimum.
+      // both: 2 <= t_i - t_{i-2} <= 2T - 2 (node order: between its nodes,
+      // so the frames may be equal).  Under the span reading a pair whose
+      // frames are TS or more apart gets +inf, which takes its terms out of
+      // every minimum.
+      const int gap_min = a.sp.node ? 0 : 2;
       const auto direction = [&](int k, int c, int tc, float2 pc) {
         const int gap = tc - sh.ctt[s2][k];
-        if (gap >= 2 && (T <= 0 || gap <= 2 * T - 2)) {
+        if (gap >= gap_min && (T <= 0 || gap <= 2 * T - 2)) {
           if (TS > 0 && gap >= TS) {
             sh.ct[k * KL + c] = INF;
             return;
@@ -786,6 +819,7 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
     } else {
       const float2 xr = make_float2(__shfl(Lr.xy.x, r), __shfl(Lr.xy.y, r));
       const int tr = __shfl(Lr.t, r);
+      const int nr = __shfl(Lr.node, r);
       if (DUMMY) teps = vp[r * VS + Kc];
       if (DUMMY && c == kEps) {
         // V_i(r, eps) = l1 W^d + min(V_{i-1}(eps, r), min_k V_{i-1}(k, r))
@@ -797,7 +831,7 @@ __device__ void backtrack_wave(const MatchView& a, const float* vtm, int r, int 
         const bool same = xa.x == xr.x && xa.y == xr.y;
         float bm, be;
         cell_consts<UNS>(th, neg_dir<DEGEN>(xr, xa), bm, be);
-        if (lane < nk && admissible(Lk.t, tr, T) && span_ok(Lk.t, tc, TS))
+        if (lane < nk && consecutive_ok(a.sp, T, Lk.node, Lk.t, nr, tr) && span_ok(Lk.t, tc, TS))
           tot = relax<DEGEN, UNS>(vcol, neg_dir<DEGEN>(Lk.xy, xr), neg_dir<DEGEN>(Lk.xy, xa), bm, be, th, same, a.w);
       }
     }
@@ -1068,7 +1102,7 @@ __device__ void rescore_wave(const ModelView& m, const SceneView& s, const Searc
     const int n = ro(z + i);
     const int nj = i >= 1 ? ro(z + (i - 1)) : kDummyNode;
     const int nk = i >= 2 ? ro(z + (i - 2)) : kDummyNode;
-    if (n != kDummyNode && nj != kDummyNode && !admissible(ro(s.t + nj), ro(s.t + n), T)) bad = 1;
+    if (n != kDummyNode && nj != kDummyNode && !consecutive_ok(sp, T, nj, ro(s.t + nj), n, ro(s.t + n))) bad = 1;
     // the span reading (no dummies): the triangle's first and last frames
     if (TS > 0 && i >= 2 && !span_ok(ro(s.t + ro(z + (i - 2))), ro(s.t + n), TS)) bad = 1;
     if (i >= 2 && (n == kDummyNode || nj == kDummyNode || nk == kDummyNode)) {

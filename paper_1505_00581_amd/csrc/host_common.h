@@ -169,7 +169,8 @@ inline bool sparse_scene(int32_t S, int32_t F) { return (long long)S <= 3LL * F;
 // rule and the span reading of closeness.
 inline stm::SearchParams search_params(const stm_params* p, int32_t window) {
   return stm::SearchParams{p->T, window, p->k_max, (p->flags & STM_K_DENSITY) ? 1 : 0,
-                           (p->flags & STM_CLOSENESS_SPAN) ? 1 : 0, (p->flags & STM_ANGLE_UNSIGNED) ? 1 : 0};
+                           (p->flags & STM_CLOSENESS_SPAN) ? 1 : 0, (p->flags & STM_ANGLE_UNSIGNED) ? 1 : 0,
+                           (p->flags & STM_CAUSAL_NODE) ? 1 : 0};
 }
 // lambda1 * W^d in FP32, the dummy's unary term in the recursion.
 inline float dummy_cost32(const stm_params* p) {

@@ -753,8 +753,8 @@ int stm_plan_run_pruned(stm_plan* p, stm_pruner* P, int32_t topk, float* energy3
   if (topk < 1 || topk > 64) return fail(STM_EINVAL, "topk must be in [1, 64]");
   if (p->bf16) return fail(STM_EUNSUPPORTED, "pruned runs of plans with the BF16 unary table are not built");
   if (dummy_on(&p->params)) return fail(STM_EUNSUPPORTED, "pruned runs of plans with dummy assignments are not built");
-  if (p->params.flags & STM_ANGLE_UNSIGNED)
-    return fail(STM_EUNSUPPORTED, "pruned runs of plans with unsigned angles are not built");
+  if (p->params.flags & (STM_ANGLE_UNSIGNED | STM_CAUSAL_NODE))
+    return fail(STM_EUNSUPPORTED, "pruned runs of plans with unsigned angles or node-order causality are not built");
   if (p->row_off.back() > 0 && (!energy32 || !assign)) return fail(STM_EINVAL, "energy32 and assign are required");
   STM_HIP(hipSetDevice(p->ctx->device));
   const int kp = std::min<int>(topk, p->params.k_max);
@@ -987,6 +987,8 @@ int stm_plan_run_lists(stm_plan* p, const int32_t* const* cand, const int32_t* c
                        float* energy32, double* energy64, double* energy_u64, int32_t* assign, void* hip_stream) {
   err().clear();
   if (!p || !cand || !count) return fail(STM_EINVAL, "null plan or lists");
+  if (p->params.flags & STM_CAUSAL_NODE)
+    return fail(STM_EUNSUPPORTED, "node-order causality on given lists is not built");
   if (kc < 1 || kc > p->params.k_max) return fail(STM_EINVAL, "list stride kc must be in [1, k_max]");
   if (p->row_off.back() > 0 && (!energy32 || !assign)) return fail(STM_EINVAL, "energy32 and assign are required");
   STM_HIP(hipSetDevice(p->ctx->device));

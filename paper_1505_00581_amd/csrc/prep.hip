@@ -139,6 +139,7 @@ __global__ void k_model_angles(ModelView m, float2* __restrict__ theta) {
 __global__ void k_count(ModelView m, SceneView s, SearchParams sp, int32_t tau0,
                         unsigned long long* __restrict__ counts) {
   __shared__ int32_t tt[3][64];
+  __shared__ int32_t nn[3][64];  // node ids (node-order causality)
   __shared__ int32_t kk[3];
   const int32_t tau = tau0 + blockIdx.x, lane = threadIdx.x;
   unsigned long long dc = 0, fc = 0, dr = 0, fr = 0;
@@ -146,7 +147,10 @@ __global__ void k_count(ModelView m, SceneView s, SearchParams sp, int32_t tau0,
     const CandRange c = point_candidates(s.fstart, s.F, tau + m.t[i] - m.t[0], sp);
     const int32_t k = c.k1 + c.k2;
     __syncthreads();
-    if (lane < k) tt[i % 3][lane] = s.t[cand_node(c, lane)];
+    if (lane < k) {
+      tt[i % 3][lane] = s.t[cand_node(c, lane)];
+      nn[i % 3][lane] = cand_node(c, lane);
+    }
     if (lane == 0) kk[i % 3] = k;
     __syncthreads();
     if (i >= 1) {
@@ -154,19 +158,21 @@ __global__ void k_count(ModelView m, SceneView s, SearchParams sp, int32_t tau0,
       const int32_t T = pair_limit(sp), TS = span_limit(sp);
       // lane = candidate r of point i-1
       if (lane < kp) {
-        const int32_t tr = tt[(i - 1) % 3][lane];
+        const int32_t tr = tt[(i - 1) % 3][lane], nr = nn[(i - 1) % 3][lane];
         const int32_t* tcur = tt[i % 3];
+        const int32_t* ncur = nn[i % 3];
         int32_t na = 0;
-        for (int32_t a = 0; a < kc; ++a) na += admissible(tr, tcur[a], T);
+        for (int32_t a = 0; a < kc; ++a) na += consecutive_ok(sp, T, nr, tr, ncur[a], tcur[a]);
         dc += kc;
         fc += na;
         if (i >= 2) {
           const int32_t kq = kk[(i - 2) % 3];
           const int32_t* tprev = tt[(i - 2) % 3];
+          const int32_t* nprev = nn[(i - 2) % 3];
           dr += (unsigned long long)kq * kc;
           if (TS <= 0) {
             int32_t nk = 0;
-            for (int32_t q = 0; q < kq; ++q) nk += admissible(tprev[q], tr, T);
+            for (int32_t q = 0; q < kq; ++q) nk += consecutive_ok(sp, T, nprev[q], tprev[q], nr, tr);
             fr += (unsigned long long)nk * na;
           } else {
             // span reading: for each admissible predecessor, the admissible

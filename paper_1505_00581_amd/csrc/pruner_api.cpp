@@ -557,8 +557,8 @@ int stm_match_pruned(stm_ctx* ctx, stm_pruner* P, const stm_points* model, const
   if (P->ctx != ctx) return fail(STM_EINVAL, "the pruner belongs to another context");
   if (topk < 1 || topk > kSlots) return fail(STM_EINVAL, "topk must be in [1, 64]");
   if (params && dummy_on(params)) return fail(STM_EUNSUPPORTED, "pruned matching with dummy assignments is not built");
-  if (params && (params->flags & STM_ANGLE_UNSIGNED))
-    return fail(STM_EUNSUPPORTED, "pruned matching with unsigned angles is not built");
+  if (params && (params->flags & (STM_ANGLE_UNSIGNED | STM_CAUSAL_NODE)))
+    return fail(STM_EUNSUPPORTED, "pruned matching with unsigned angles or node-order causality is not built");
   Prepared pr;
   if ((rc = pair_inputs(P, model, scene, params, hip_stream, pr))) return rc;
   if ((rc = check_range(pr, tau_begin, tau_end))) return rc;
@@ -616,6 +616,8 @@ int stm_match_lists(stm_ctx* ctx, const stm_points* model, const stm_points* sce
                     int32_t tau_begin, int32_t tau_end, const int32_t* cand, const int32_t* count, int32_t kc,
                     float* energy32, double* energy64, double* energy_u64, int32_t* assign, void* hip_stream) {
   err().clear();
+  if (params && (params->flags & STM_CAUSAL_NODE))
+    return fail(STM_EUNSUPPORTED, "node-order causality on given lists is not built");
   Prepared pr;
   int rc = prepare(ctx, model, scene, params, hip_stream, pr);
   if (rc) return rc;

@@ -30,6 +30,7 @@ struct SearchParams {
   int32_t T, W, K, kdensity;
   int32_t span;  // closeness as the span of each triangle (Section 3.4, Eq. 14)
   int32_t uns;   // unsigned triangle angles (the magnitudes of Eq. 6's angles)
+  int32_t node;  // causality by scene node order, z_{i-1} < z_i (equal frames allowed)
 };
 
 // Closeness limit of consecutive points: T of Eq. 8, or under the span reading
@@ -153,6 +154,20 @@ __device__ __forceinline__ int32_t cand_node(const CandRange& c, int32_t a) {
 __device__ __forceinline__ bool admissible(int32_t tp_prev, int32_t tp_cur, int32_t T) {
   return tp_prev < tp_cur && (T <= 0 || tp_cur - tp_prev < T);
 }
+
+// The same for consecutive points (z_prev, z_cur) under the search's reading
+// of causality: frames as above, or with node order increasing node ids and
+// Eq. 8's closeness.
+__device__ __forceinline__ bool consecutive_ok(const SearchParams& sp, int32_t T, int32_t n_prev, int32_t t_prev,
+                                               int32_t n_cur, int32_t t_cur) {
+  return sp.node ? n_prev < n_cur && (T <= 0 || t_cur - t_prev < T) : admissible(t_prev, t_cur, T);
+}
+
+// Entries <= x (below: < x) of the ascending windowed list c of scene nodes.
+__device__ __forceinline__ int32_t range_count_le(const CandRange& c, int32_t x) {
+  return min(max(x - c.s1 + 1, 0), c.k1) + min(max(x - c.s2 + 1, 0), c.k2);
+}
+__device__ __forceinline__ int32_t range_count_lt(const CandRange& c, int32_t x) { return range_count_le(c, x - 1); }
 
 // The span reading's condition on a triangle's first and last scene frames
 // (limit from span_limit; 0: always true).
