@@ -143,23 +143,25 @@ __device__ __forceinline__ bool chunk_cell(const Chunk& c, int lane, int& r, int
 // step's cell count, also stored in *ptot.
 __device__ void build_schedule(const int32_t* trow, int nrow, const int32_t* tcol, int ncol,
                                const int32_t* tprev, int nprev, int T, uint2* out, int32_t* nout,
-                               int lane, int16_t* pstart = nullptr, int32_t* ptot = nullptr,
-                               const CandRange* nodes = nullptr) {
+                               int lane, int16_t* pstart, int32_t* ptot, const CandRange* ring, int sr, int sc,
+                               int sp) {
   const int f = lane < nrow ? trow[lane] : 0;
-  // node-order causality (nodes: the windowed ranges of the rows', the
-  // columns' and the predecessors' lists): every row is a group of its own,
-  // its columns the nodes above its own within T frames, its predecessors the
-  // nodes below it within T frames
-  const bool start = lane < nrow && (nodes || lane == 0 || trow[lane - 1] != f);
+  // node-order causality (ring: the windowed node ranges of the candidate
+  // ring in LDS, sr, sc, sp: the rows', columns' and predecessors' slots;
+  // null for frame order): every row is a group of its own, its columns the
+  // nodes above its own within T frames, its predecessors the nodes below it
+  // within T frames
+  const bool node = ring != nullptr;
+  const bool start = lane < nrow && (node || lane == 0 || trow[lane - 1] != f);
   const unsigned long long starts = __ballot(start);
   int nchunk = 0, nr = 0, nc = 0, clo = 0, chi = 0, lo = 0, hi = 0;
-  if (nodes) {
+  if (node) {
     if (start) {
-      const int nd = cand_node(nodes[0], lane);
-      clo = range_count_le(nodes[1], nd);
+      const int nd = cand_node(ring[sr], lane);
+      clo = range_count_le(ring[sc], nd);
       chi = T > 0 ? count_lt(tcol, ncol, f > 0x7fffffff - T ? 0x7fffffff : f + T) : ncol;
       if (tprev) {
-        hi = range_count_lt(nodes[2], nd);
+        hi = range_count_lt(ring[sp], nd);
         lo = T > 0 ? count_lt(tprev, nprev, f - T + 1) : 0;
       }
     }
@@ -398,19 +400,13 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
     const int32_t* tcol = sh.ctt[sc];
     const int32_t* tprev = spv >= 0 ? sh.ctt[spv] : nullptr;
     const int nrow = sh.ck[sr], ncol = sh.ck[sc], nprev = spv >= 0 ? sh.ck[spv] : 0;
-    CandRange rg[3];
-    if (a.sp.node) {
-      rg[0] = sh.crange[sr];
-      rg[1] = sh.crange[sc];
-      rg[2] = spv >= 0 ? sh.crange[spv] : CandRange{0, 0, 0, 0};
-    }
-    const CandRange* nodes = a.sp.node ? rg : nullptr;
+    const CandRange* ring = a.sp.node ? sh.crange : nullptr;
     if constexpr (PACKED)
       build_schedule(trow, nrow, tcol, ncol, tprev, nprev, T, sh.sched[b], &sh.nch[b], lane, sh.pstart[b],
-                     &sh.ptot[b], nodes);
+                     &sh.ptot[b], ring, sr, sc, spv);
     else
       build_schedule(trow, nrow, tcol, ncol, tprev, nprev, T, sh.sched[b], &sh.nch[b], lane, nullptr, nullptr,
-                     nodes);
+                     ring, sr, sc, spv);
   };
 
   auto load_slot = [&](int j) {
