@@ -6,7 +6,7 @@ pin the GPU pruner's features, forward pass, loss, gradients and Adam step.
 The pruner is not part of the paper.  It scores each candidate scene node n
 of a model point i at an offset tau and keeps the best k, so that the exact
 recursion (Section 2.2) runs on shorter candidate lists; the exact recursion
-stays the fallback and the judge of the energy gap.
+stays the fallback and the reference for the energy gap.
 
 Input of one (tau, i, n): x = [D f_i (D), D g_n (D), phi (8)], D = descriptor
 dim (the descriptors are L1-normalised, so the factor D brings their entries

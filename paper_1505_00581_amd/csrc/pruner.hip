@@ -2,7 +2,7 @@
 // listwise loss, backward, Adam) and the BF16 inference kernel with top-k
 // selection.  Not part of the paper: it shortens the candidate lists the
 // exact recursion (Section 2.2) runs on; the exact recursion stays the
-// fallback and the judge of the energy gap.
+// fallback and the reference for the energy gap.
 //
 // One group = the candidates of one model point i at one offset tau; a group
 // occupies 64 rows (one per candidate slot; slots past the list are invalid).

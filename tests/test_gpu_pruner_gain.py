@@ -1,7 +1,7 @@
 """What the trained pruner gains over pruning without it (MI355X).
 
 The network is trained on the GPU by its own kernels on labels from the exact
-recursion (realistic single-scene workloads, seeds 100-129), then judged on a
+recursion (realistic single-scene workloads, seeds 100-129), then evaluated on a
 held-out seed against the exact matching, beside two rules that need no
 training: the k candidates with the smallest unary cost U, and the k nearest
 in time (the windowed rule capped at k).  Measured gaps, recalls and fallback

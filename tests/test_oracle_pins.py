@@ -413,7 +413,7 @@ def _lists_array(lists, M, K):
 
 
 def test_recursion_on_given_lists_equals_brute_force():
-    """The explicit-list entry point (used to judge pruned matchings) against
+    """The explicit-list entry point (used to check pruned matchings) against
     enumeration over random subsets of the windowed lists."""
     rng = np.random.default_rng(7)
     feasible = 0
