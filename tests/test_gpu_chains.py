@@ -68,6 +68,20 @@ def test_small_multipoint_all_offsets(ctx, seed, n_chains):
     assert st["feasible"] > 0
 
 
+@pytest.mark.parametrize("reading", ["angle_unsigned", "causal_node"])
+def test_alternative_readings(ctx, reading):
+    import dataclasses
+    w = synth.multipoint(3, n_models=1, frames=(12, 20), per_frame=3, n_frames=70, clutter_per_frame=4,
+                         window=2, k_max=16, width=160.0, height=120.0, planted_per_model=2)
+    m, s, sal = w.models[0], w.scenes[0], w.saliency[0]
+    p = dataclasses.replace(w.params, **{reading: True})
+    res = ctx.match_chains(m, s, p, sal, 3)
+    ora = C.match_chains(m, s, p, sal, 3)
+    st = check(m, s, p, res, ora)
+    say(f"[chains {reading}] {st}")
+    assert st["feasible"] > 0
+
+
 def test_one_point_per_frame_equals_stm_match(ctx):
     w = synth.config1(5)
     m, s, p = w.models[0], w.scenes[0], w.params

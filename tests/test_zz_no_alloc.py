@@ -51,7 +51,7 @@ def _same(ctx, m, s, p, tau=(None, None)):
     return int(ref["energy32"].numel()), int(torch.isfinite(ref["energy32"]).sum())
 
 
-@pytest.mark.parametrize("variant", ["plain", "dummy", "bf16"])
+@pytest.mark.parametrize("variant", ["plain", "dummy", "bf16", "unsigned", "node"])
 def test_noalloc_equals_stm_match_two_calls(ctx, variant):
     w = synth.config1(0)
     m, s, p = w.models[0], w.scenes[0], w.params
@@ -59,6 +59,10 @@ def test_noalloc_equals_stm_match_two_calls(ctx, variant):
         p = dataclasses.replace(p, w_dummy=0.5)
     elif variant == "bf16":
         p = dataclasses.replace(p, unary_bf16=True)
+    elif variant == "unsigned":
+        p = dataclasses.replace(p, angle_unsigned=True)
+    elif variant == "node":
+        p = dataclasses.replace(p, causal_node=True)
     say(f"noalloc {variant}: plain workload, all offsets")
     n1, f1 = _same(ctx, m, s, p)
     # second call: a smaller model and scene
