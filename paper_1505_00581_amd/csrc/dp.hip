@@ -666,19 +666,28 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
     }
     if constexpr (DUMMY) {
       // the epsilon cells of step i, from step i-1's cells and epsilon cells
-      if (wv == kBuilder) {
-        const float cw = a.cw;
-        if (lane < Kp) {
-          // V_i(r, eps): over the admissible predecessors of row r, no D^g
-          const int f = sh.ctt[s1][lane];
+      const float cw = a.cw;
+      // V_i(r, eps): over the admissible predecessors of row r, no D^g; eight
+      // lanes per row split its predecessors, the rows spread over the waves
+      for (int r0 = wv * 8; r0 < Kp; r0 += NW * 8) {
+        const int r = r0 + (lane >> 3), sub = lane & 7;
+        float m = INF;
+        if (r < Kp) {
+          const int f = sh.ctt[s1][r];
           const int hi = count_lt(sh.ctt[s2], Kq, f);
           const int lo = T > 0 ? count_lt(sh.ctt[s2], Kq, f - T + 1) : 0;
-          float m = sh.de[prv][lane];
-          for (int k = lo; k < hi; ++k) m = fminf(m, sh.va[k * KL + lane].x);
-          const float v = cw + m;
-          sh.df[cur][lane] = v;
-          if (vt) vt[Kc * VS + lane] = v;
+          for (int k = lo + sub; k < hi; k += 8) m = fminf(m, sh.va[k * KL + r].x);
         }
+        m = fminf(m, __shfl_xor(m, 1));
+        m = fminf(m, __shfl_xor(m, 2));
+        m = fminf(m, __shfl_xor(m, 4));
+        if (r < Kp && sub == 0) {
+          const float v = cw + fminf(sh.de[prv][r], m);
+          sh.df[cur][r] = v;
+          if (vt) vt[Kc * VS + r] = v;
+        }
+      }
+      if (wv == kBuilder) {
         float m = lane < Kq ? sh.df[prv][lane] : INF;
         for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
         m = fminf(m, sh.dg[prv]);
