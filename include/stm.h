@@ -104,6 +104,10 @@ extern "C" {
                                  consecutive points.  Consecutive points are then at
                                  most T - 2 frames apart.  No effect with T <= 0;
                                  not with STM_DUMMY (STM_EUNSUPPORTED).             */
+#define STM_TRELLIS_STEPWISE 0x20u  /* trellis (stm_trellis_*) only: one launch per
+                                 step even where the band fits one workgroup's LDS
+                                 and all steps would run in one launch; the two give
+                                 the same bits                                      */
 #define STM_ANGLE_UNSIGNED 0x40u  /* the angles of Eq. 6 read as magnitudes in [0, pi]
                                  (unoriented), so that a triangle and its mirror
                                  image match; the default reads them oriented
@@ -122,10 +126,6 @@ extern "C" {
                                  stm_match_noalloc, stm_match_chains); not with
                                  STM_DUMMY, STM_CLOSENESS_SPAN, given lists, the
                                  pruner or the trellis (STM_EUNSUPPORTED)             */
-#define STM_TRELLIS_STEPWISE 0x20u  /* trellis (stm_trellis_*) only: one launch per
-                                 step even where the band fits one workgroup's LDS
-                                 and all steps would run in one launch; the two give
-                                 the same bits                                      */
 
 /* Node id of a dummy assignment in assignment rows (STM_DUMMY); -1 marks the
  * rows of infeasible offsets. */
