@@ -63,6 +63,15 @@
 // 64 in the final argmin and in backtracking (after every candidate, so ties
 // go to candidates) and index K in the value tables, whose rows then have
 // K + 1 entries.
+//
+// Alternative readings.  Unsigned angles (a template variant): the terms
+// compare magnitudes, the scene's angles at z_{i-1} and z_i being wrap(pi +
+// anew - A) and wrap(anew - C) of the same stored directions (dp_math.h).
+// Node-order causality (a run-time switch of the schedule): consecutive points
+// take increasing node ids, so within a frame every row has its own columns
+// (the nodes above it) and its own predecessors (the nodes below it); every row
+// is then a group of its own, its ranges counted from the windowed lists' node
+// ranges, and the chunk loop is unchanged.
 #include <math.h>
 
 #include "dp_math.h"
