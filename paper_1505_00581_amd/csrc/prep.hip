@@ -96,17 +96,28 @@ __global__ __launch_bounds__(kBlock) void k_unary_f32(ModelView m, SceneView s, 
   float acc[kUnaryRows];
 #pragma unroll
   for (int r = 0; r < kUnaryRows; ++r) acc[r] = 0.0f;
+  // the scene tile of dimensions [d0, d0 + 32) is read into registers one tile
+  // ahead, so that its global reads overlap the arithmetic of the tile before.
+  // Thread t reads dimension t % 32 of the tile for points t / 32 + 8 j.
+  constexpr int kStride = kBlock / kUnaryTile;
+  const int32_t tdd = threadIdx.x % kUnaryTile, tp = threadIdx.x / kUnaryTile;
+  const float* src = s.desc + (long long)(n0 + tp) * dim + tdd;
+  const long long jstep = (long long)kStride * dim;
+  float pre[kUnaryTile];
+  const auto fetch = [&](int32_t d0) {
+    const bool dok = tdd < min(kUnaryTile, dim - d0);
+#pragma unroll
+    for (int32_t j = 0; j < kUnaryTile; ++j)
+      pre[j] = dok && n0 + tp + kStride * j < s.S ? src[j * jstep + d0] : 0.0f;
+  };
+  fetch(0);
   for (int32_t d0 = 0; d0 < dim; d0 += kUnaryTile) {
     const int32_t w = min(kUnaryTile, dim - d0);
     __syncthreads();  // the previous tile is consumed (and fm is written, first time)
-#pragma unroll 4
-    for (int32_t j = 0; j < kUnaryTile; ++j) {
-      const int32_t e = threadIdx.x + kBlock * j;  // point e / 32, dimension e % 32 of the tile
-      const int32_t p = e / kUnaryTile, dd = e % kUnaryTile;
-      const int32_t np = n0 + p;
-      gt[p][dd] = np < s.S && dd < w ? s.desc[(long long)np * dim + d0 + dd] : 0.0f;
-    }
+#pragma unroll
+    for (int32_t j = 0; j < kUnaryTile; ++j) gt[tp + kStride * j][tdd] = pre[j];
     __syncthreads();
+    if (d0 + kUnaryTile < dim) fetch(d0 + kUnaryTile);
     for (int32_t dd = 0; dd < w; ++dd) {
       const float v = gt[threadIdx.x][dd];
 #pragma unroll
