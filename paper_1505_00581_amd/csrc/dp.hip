@@ -418,23 +418,45 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
                      ring, sr, sc, spv);
   };
 
-  auto load_slot = [&](int j) {
+  // The candidates of list j, read by wave 0 in two halves: fetch_slot issues
+  // the reads into registers (its frame boundaries, then its nodes' position,
+  // frame and unary cost) a step before commit_slot stores them into ring slot
+  // j & 3, so that their latency overlaps the recursion of the step between.
+  struct SlotRegs {
+    Cands c;
+    float2 xy;
+    int32_t t;
+    float u;
+  };
+  auto fetch_slot = [&](int j) {
+    SlotRegs f;
     if (wv == 0) {
-      const Cands c = cands_of(a, j);
-      const int k = c.count();
+      f.c = cands_of(a, j);
+      if (lane < f.c.count()) {
+        const int n = f.c.node(lane);
+        f.xy = ro(a.s.xy + n);
+        f.t = ro(a.s.t + n);
+        f.u = ro(a.U + (long long)j * a.us + n);
+      }
+    }
+    return f;
+  };
+  auto commit_slot = [&](int j, const SlotRegs& f) {
+    if (wv == 0) {
+      const int k = f.c.count();
       const int sl = j & 3;
       if (lane < k) {
-        const int n = c.node(lane);
-        sh.cxy[sl][lane] = ro(a.s.xy + n);
-        sh.ctt[sl][lane] = ro(a.s.t + n);
-        sh.cu[sl][lane] = a.lambda1 * ro(a.U + (long long)j * a.us + n);
+        sh.cxy[sl][lane] = f.xy;
+        sh.ctt[sl][lane] = f.t;
+        sh.cu[sl][lane] = a.lambda1 * f.u;
       }
       if (lane == 0) {
         sh.ck[sl] = k;
-        sh.crange[sl] = c.r;
+        sh.crange[sl] = f.c.r;
       }
     }
   };
+  auto load_slot = [&](int j) { commit_slot(j, fetch_slot(j)); };
 
   if (threadIdx.x == 0) sh.flag = 0;
   load_slot(0);
@@ -443,6 +465,8 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
   __syncthreads();
   if (wv == kBuilder) schedule(0, 1, -1, 1);
   __syncthreads();
+  SlotRegs next;  // list i + 1 in flight during step i - 1's recursion and step i's phase 1
+  if (3 < M) next = fetch_slot(3);
 
   float vr[RPW], ar[RPW];
   int pi[RPW];  // LDS index (row * KL + column) of each slot's cell, -1: none
@@ -561,8 +585,9 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
         }
       }
     }
-    if (i + 1 < M) load_slot(i + 1);
+    if (i + 1 < M) commit_slot(i + 1, next);
     __syncthreads();
+    if (i + 2 < M) next = fetch_slot(i + 2);
 
     // Phase 2: the minima over a_{i-2} of every admissible cell, chunk by chunk.
     const float2 th = ro(a.theta + i);
@@ -607,8 +632,8 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           vnew = (sh.cu[s0][col] + q) + best;
           if (valid && vt) vt[col * VS + r] = vnew;
           pi[s] = valid ? r * KL + col : -1;
-        } else {
-          pi[s] = -1;
+          vr[s] = vnew;
+          ar[s] = anew;
         }
       } else {
         if (ch < nch) {
@@ -666,12 +691,12 @@ __device__ DPResult dp_forward(DPShared<NW, KL, DUMMY, PACKED>& sh, const MatchV
           vnew = (sh.cu[s0][col] + q) + best;
           if (valid && vt) vt[col * VS + r] = vnew;
           pi[s] = valid ? r * KL + col : -1;
-        } else {
-          pi[s] = -1;
+          vr[s] = vnew;
+          ar[s] = anew;
         }
       }
-      vr[s] = vnew;
-      ar[s] = anew;
+      // a slot past the step's chunk count keeps stale registers: every reader
+      // (publication, the final minimum) checks the slot against that count
     }
     if constexpr (DUMMY) {
       // the epsilon cells of step i, from step i-1's cells and epsilon cells
