@@ -116,17 +116,20 @@ int tr_enqueue(stm_trellis* p, float* e32, double* e64, double* eu, int32_t* as,
 
 // Tiles of a step from the band's ranges (host copies): narrow bands take up
 // to 64 consecutive rows whose successors span at most 128 nodes and hold at
-// most 1024 cells; a row with more than 128 successors starts a block of up to
-// 32 rows cut into 32-column windows.  Tiles without cells are left out.
+// most kCells cells (at most 1024); a row with more than 128 successors starts
+// a block of up to kCells / 32 rows cut into 32-column windows.  Tiles without
+// cells are left out.
 std::vector<stm::TrellisTile> make_tiles(const std::vector<int32_t>& slo, const std::vector<int32_t>& shi,
-                                         const std::vector<int32_t>& plo, const std::vector<int32_t>& phi) {
-  constexpr int kRows = stm::kTrellisTileRows, kCols = stm::kTrellisTileCols, kCells = stm::kTrellisTileCells;
+                                         const std::vector<int32_t>& plo, const std::vector<int32_t>& phi,
+                                         int kCells) {
+  constexpr int kRows = stm::kTrellisTileRows, kCols = stm::kTrellisTileCols;
   // rows wider than kCols: kWideRows rows by kWideCols-column windows.  Staging
   // k predecessors loads k (rows + columns) values for k rows x columns
   // relaxations, fewest for a square window (32 x 32: 48.5 -> 47.6 ms on the
   // whole-video trellis without a closeness limit, against 16 x 64; 8 x 128
   // took 58 ms)
-  constexpr int kWideCols = 32, kWideRows = kCells / kWideCols;
+  constexpr int kWideCols = 32;
+  const int kWideRows = kCells / kWideCols;
   std::vector<stm::TrellisTile> out;
   const int32_t n = static_cast<int32_t>(slo.size());
   int32_t r0 = 0;
@@ -299,7 +302,18 @@ int stm_trellis_create(stm_ctx* ctx, const stm_points* models, int32_t n_models,
   p->Q = ends[0];
   p->QC = ends[1];
   p->fused = !(params->flags & STM_TRELLIS_STEPWISE) && stm::trellis_fits_fused(p->Q, p->QC, n);
-  const std::vector<stm::TrellisTile> tiles = make_tiles(slo, shi, plo, phi);
+  // Tiles of 1024 cells, or smaller while a step launch would have fewer than
+  // kFewTiles workgroups: one workgroup per CU leaves its waves' latency
+  // exposed, more and smaller tiles hide it at the price of staging each
+  // predecessor for fewer cells.
+  constexpr int kMinTileCells = 256;
+  constexpr long long kFewTiles = 1024;
+  int tile_cells = stm::kTrellisTileCells;
+  std::vector<stm::TrellisTile> tiles = make_tiles(slo, shi, plo, phi, tile_cells);
+  while (tile_cells > kMinTileCells && (long long)tiles.size() * n_models < kFewTiles) {
+    tile_cells /= 2;
+    tiles = make_tiles(slo, shi, plo, phi, tile_cells);
+  }
   p->n_tiles = static_cast<int32_t>(tiles.size());
   TR_ALLOC(p->tiles, stm::TrellisTile, std::max<size_t>(1, tiles.size()));
   if (!tiles.empty())

@@ -245,29 +245,37 @@ def test_fused_run_equals_stepwise_launches(ctx, video):
 
 
 def test_step_launch_variants_agree(ctx, video):
-    """Step launches of many workgroups stage fewer predecessors at a time at a
-    higher occupancy than small ones; the terms and minima are the same, so a
-    model's rows from a 50-model run (the wide variant) equal those of a run
-    of that model alone (the small variant) bit for bit."""
+    """Tiles and step-launch variants change no bit.  A step launch of many
+    workgroups stages fewer predecessors at a time at a higher occupancy than a
+    small one, and a trellis whose step launches would have fewer than 1024
+    workgroups is cut into smaller tiles (down to 256 cells).  A model's rows
+    from a 50-model run (1024-cell tiles, the many-workgroup variant) equal
+    those of a run of that model alone (smaller tiles) bit for bit, on the
+    whole video (still many workgroups) and on a 200-node block (the
+    small-launch variant)."""
     import torch
     s = video.scenes[0]
     ds = stm.DevicePoints.from_host(s)
     dms = [stm.DevicePoints.from_host(m) for m in video.models]
     p = dataclasses.replace(video.params, T=0)
-    tr = stm.Trellis(ctx, dms, ds, p)
-    assert tr.info()["tiles"] * len(dms) >= 1024
-    out = tr.run()
-    torch.cuda.synchronize()
-    for q in (0, 7, 49):
-        one = stm.Trellis(ctx, [dms[q]], ds, p)
-        assert one.info()["tiles"] < 1024
-        r = one.run()
+    for n1, small in ((s.n, False), (200, True)):
+        tr = stm.Trellis(ctx, dms, ds, p, 0, n1)
+        assert tr.info()["tiles"] * len(dms) >= 1024
+        out = tr.run()
         torch.cuda.synchronize()
-        assert to_np(r["energy32"])[0] == to_np(out["energy32"])[q]
-        assert to_np(r["energy64"])[0] == to_np(out["energy64"])[q]
-        np.testing.assert_array_equal(to_np(one.model_rows(r, 0)), to_np(tr.model_rows(out, q)))
-        one.close()
-    tr.close()
+        for q in (0, 7, 49):
+            one = stm.Trellis(ctx, [dms[q]], ds, p, 0, n1)
+            n_one = one.info()["tiles"]
+            assert n_one > tr.info()["tiles"]
+            assert (n_one < 1024) == small
+            r = one.run()
+            torch.cuda.synchronize()
+            assert to_np(r["energy32"])[0] == to_np(out["energy32"])[q]
+            assert to_np(r["energy64"])[0] == to_np(out["energy64"])[q]
+            np.testing.assert_array_equal(to_np(one.model_rows(r, 0)), to_np(tr.model_rows(out, q)))
+            one.close()
+        say(f"  nodes 0..{n1}: {tr.info()['tiles']} tiles for 50 models, {n_one} for one")
+        tr.close()
 
 
 def test_graph_replays_equal_direct_launches(ctx, video):
