@@ -269,29 +269,51 @@ void k_trellis_step(TrellisRun a, int32_t i) {
   const int cgroups = (CW + 63) >> 6;  // 64-column groups of the window: 1 or 2
   for (int32_t k0 = tl.k0; k0 < tl.k1; k0 += kChunk) {
     const int32_t nk = min(kChunk, tl.k1 - k0);
-    for (int kk = wv; kk < kChunk; kk += kThreads / 64) {
-      if (lane < R) {
-        const int32_t k = k0 + kk;
-        float2 v = make_float2(INF, 0.f);
-        if (kk < nk && k >= sh.plo[lane] && k < sh.phi[lane]) {
-          const long long off = b.rowoff[k] + (tl.r0 + lane - b.s_lo[k]);
-          v = make_float2(Vp[off], b.A[off]);
-        }
-        sh.va[kk][lane] = v;
+    // rows kk = wv, wv + 4, ... of the chunk: the reads of each table are all
+    // issued before its first store (fixed trip counts, unrolled; a lane
+    // without a value reads index 0 and stores the default), so that a chunk
+    // waits for two rounds of reads instead of one per row
+    constexpr int kWaves = kThreads / 64;
+    constexpr int kPerWave = kChunk / kWaves;
+    static_assert(kChunk % kWaves == 0, "staged rows split evenly over the waves");
+    {
+      float2 sv[kPerWave];
+      bool ok[kPerWave];
+#pragma unroll
+      for (int s = 0; s < kPerWave; ++s) {
+        const int kk = wv + kWaves * s;
+        const int32_t k = kk < nk ? k0 + kk : tl.k1 - 1;  // wave-uniform, inside the band
+        ok[s] = kk < nk && lane < R && k >= sh.plo[lane] && k < sh.phi[lane];
+        const long long off = ok[s] ? b.rowoff[k] + (tl.r0 + lane - b.s_lo[k]) : 0;
+        sv[s] = make_float2(Vp[off], b.A[off]);
       }
+#pragma unroll
+      for (int s = 0; s < kPerWave; ++s)
+        if (lane < R) sh.va[wv + kWaves * s][lane] = ok[s] ? sv[s] : make_float2(INF, 0.f);
     }
-    for (int it = wv; it < kChunk * cgroups; it += kThreads / 64) {
-      const int kk = cgroups == 2 ? it >> 1 : it;
-      const int col = (it - kk * cgroups) * 64 + lane;
-      if (col < CW) {
-        const int32_t k = k0 + kk, c = tl.c0 + col;
-        float v = 0.f;
-        if (kk < nk) {
-          const int32_t qlo = b.q_lo[k], qhi = b.q_hi[k];
-          if (c >= qlo && c < qhi) v = b.C[b.qoff[k] + (c - qlo)];
+    {
+      float sc[kPerWave][2];
+      bool ok[kPerWave][2];
+#pragma unroll
+      for (int s = 0; s < kPerWave; ++s) {
+        const int kk = wv + kWaves * s;
+        const int32_t k = kk < nk ? k0 + kk : tl.k1 - 1;
+        const int32_t qlo = b.q_lo[k], qhi = b.q_hi[k];
+        const long long qo = b.qoff[k];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          const int32_t c = tl.c0 + g * 64 + lane;
+          ok[s][g] = kk < nk && g < cgroups && c < tl.c1 && c >= qlo && c < qhi;
+          sc[s][g] = b.C[ok[s][g] ? qo + (c - qlo) : 0];
         }
-        sh.ct[kk][col] = v;
       }
+#pragma unroll
+      for (int s = 0; s < kPerWave; ++s)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          const int col = g * 64 + lane;
+          if (g < cgroups && col < CW) sh.ct[wv + kWaves * s][col] = ok[s][g] ? sc[s][g] : 0.f;
+        }
     }
     __syncthreads();
 #pragma unroll
