@@ -396,9 +396,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_trellis_fused(TrellisRun a) {
   const float INF = __builtin_inff();
   int2* kin = reinterpret_cast<int2*>(pool);           // (rowoff - s_lo, qoff - q_lo) of node k
   int2* prg = kin + n;                                 // predecessors [p_lo, p_hi) of node r
-  float* V = reinterpret_cast<float*>(prg + n);        // V_{i-1} of every cell
-  float* A = V + Q;                                    // A(r, c) of every cell
-  float* C = A + Q;                                    // C(k, c) of every two-step pair
+  float2* VA = reinterpret_cast<float2*>(prg + n);     // (V_{i-1}, A(r, c)) of every cell: one read per term
+  float* C = reinterpret_cast<float*>(VA + Q);         // C(k, c) of every two-step pair
   int16_t* crow = reinterpret_cast<int16_t*>(C + QC);  // row of every cell
   for (int32_t k = tid; k < n; k += kFusedThreads) {
     const int32_t r0 = static_cast<int32_t>(b.rowoff[k]), r1 = static_cast<int32_t>(b.rowoff[k + 1]);
@@ -406,7 +405,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_trellis_fused(TrellisRun a) {
     prg[k] = make_int2(b.p_lo[k], b.p_hi[k]);
     for (int32_t q = r0; q < r1; ++q) crow[q] = static_cast<int16_t>(k);
   }
-  for (int32_t q = tid; q < Q; q += kFusedThreads) A[q] = b.A[q];
+  for (int32_t q = tid; q < Q; q += kFusedThreads) VA[q].y = b.A[q];
   for (int32_t q = tid; q < QC; q += kFusedThreads) C[q] = b.C[q];
   __syncthreads();
 
@@ -427,7 +426,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_trellis_fused(TrellisRun a) {
     lo[j] = valid ? p.x : 0;
     hi[j] = valid ? p.y : 0;
     dt[j] = a.t[c] - a.t[r];
-    arc[j] = valid ? A[q] : 0.f;
+    arc[j] = valid ? VA[q].y : 0.f;
     if (DEGEN) {
       const float2 xr = a.xy[r], xc = a.xy[c];
       same[j] = xr.x == xc.x && xr.y == xc.y;
@@ -436,7 +435,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_trellis_fused(TrellisRun a) {
     }
     if (valid) {
       const float v = first_value(a, md.U[r], md.U[n + c], dtm1, dt[j]);
-      V[q] = v;
+      VA[q].x = v;
       md.V[q] = v;
     }
   }
@@ -463,7 +462,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_trellis_fused(TrellisRun a) {
         for (int32_t k = lo[j]; k < hi[j]; ++k) {
           const int2 kk = kin[k];
           const int32_t off = kk.x + r;  // cell (k, r)
-          best = fminf(best, relax<DEGEN>(V[off], A[off], C[kk.y + c], bm, be, th, same[j], a.w));
+          const float2 va = VA[off];
+          best = fminf(best, relax<DEGEN>(va.x, va.y, C[kk.y + c], bm, be, th, same[j], a.w));
         }
         nv[j] = step_value(__fmul_rn(a.lambda1, Ui[c]), qw, dtm, dt[j], best);
       }
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_trellis_fused(TrellisRun a) {
     for (int j = 0; j < kFusedSlots; ++j) {
       const int32_t q = tid + kFusedThreads * j;
       if (q < Q) {
-        V[q] = nv[j];
+        VA[q].x = nv[j];
         Vi[q] = nv[j];
       }
     }
