@@ -316,6 +316,7 @@ hipError_t launch_rescore_batch(const PairDev* pairs, const int2* items, int n_i
 constexpr int kTrellisTileRows = 64;
 constexpr int kTrellisTileCols = 128;
 constexpr int kTrellisTileCells = 1024;
+constexpr int kTrellisSmallTileCells = 256;  // tiles of launches with few workgroups
 struct TrellisTile {
   int32_t r0, r1, c0, c1, k0, k1, ncell, pad;
 };
@@ -369,9 +370,10 @@ hipError_t launch_trellis_dirs(const TrellisBand& b, int32_t n, const float2* xy
                                int32_t* flag, hipStream_t st);
 // Steps 1..M-1 of every model, then the optimum and backtracking (degen: the
 // variant that handles coincident points; fused: every step in one workgroup
-// per model, for bands that trellis_fits_fused accepts).
-hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_max, bool degen, bool fused,
-                              hipStream_t st);
+// per model, for bands that trellis_fits_fused accepts; tile_cells: the cell
+// cap the tiles were cut with, kTrellisTileCells or kTrellisSmallTileCells).
+hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t tile_cells, int32_t m_max, bool degen,
+                              bool fused, hipStream_t st);
 // Whether a band of n nodes, Q cells and QC two-step pairs fits one
 // workgroup's LDS for the fused run.
 bool trellis_fits_fused(long long Q, long long QC, int32_t n);

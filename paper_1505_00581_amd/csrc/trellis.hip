@@ -39,7 +39,6 @@ namespace stm {
 namespace {
 
 constexpr int kThreads = 256;                    // threads of a step workgroup
-constexpr int kSlots = kTrellisTileCells / kThreads;  // cells per thread
 // Predecessors staged in LDS at a time and the occupancy target of a step
 // launch: launches of many workgroups (several per CU) take 20 at a time at six
 // waves per SIMD (80 registers), smaller ones 24 at five; on the whole video
@@ -181,11 +180,13 @@ struct StepShared {
   int32_t tc[kTrellisTileCols];
 };
 
-// V_i for the tile blockIdx.x of model blockIdx.y (skipped when i >= M).
-template <bool DEGEN, int KC, int WAVES>
+// V_i for the tile blockIdx.x of model blockIdx.y (skipped when i >= M); tiles
+// of at most SLOTS * 256 cells, SLOTS cells per thread.
+template <bool DEGEN, int KC, int WAVES, int SLOTS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WAVES)))
 void k_trellis_step(TrellisRun a, int32_t i) {
   constexpr int kChunk = KC;
+  constexpr int kSlots = SLOTS;  // cells per thread
   __shared__ StepShared<KC> sh;
   const TrellisModel md = a.models[blockIdx.y];
   const int32_t M = md.m.M;
@@ -269,52 +270,53 @@ void k_trellis_step(TrellisRun a, int32_t i) {
   const int cgroups = (CW + 63) >> 6;  // 64-column groups of the window: 1 or 2
   for (int32_t k0 = tl.k0; k0 < tl.k1; k0 += kChunk) {
     const int32_t nk = min(kChunk, tl.k1 - k0);
-    // rows kk = wv, wv + 4, ... of the chunk: the reads of each table are all
-    // issued before its first store (fixed trip counts, unrolled; a lane
-    // without a value reads index 0 and stores the default), so that a chunk
-    // waits for two rounds of reads instead of one per row
+    // rows kk = wv, wv + 4, ... of the chunk: every read of a table (of both
+    // tables with one cell per thread, whose registers allow it) is issued
+    // before the first store (fixed trip counts, unrolled; a lane without a
+    // value reads index 0 and stores the default), so that a chunk waits for
+    // one or two rounds of reads instead of one per row
     constexpr int kWaves = kThreads / 64;
     constexpr int kPerWave = kChunk / kWaves;
     static_assert(kChunk % kWaves == 0, "staged rows split evenly over the waves");
-    {
-      float2 sv[kPerWave];
-      bool ok[kPerWave];
+    float2 sv[kPerWave];
+    bool okv[kPerWave];
 #pragma unroll
-      for (int s = 0; s < kPerWave; ++s) {
-        const int kk = wv + kWaves * s;
-        const int32_t k = kk < nk ? k0 + kk : tl.k1 - 1;  // wave-uniform, inside the band
-        ok[s] = kk < nk && lane < R && k >= sh.plo[lane] && k < sh.phi[lane];
-        const long long off = ok[s] ? b.rowoff[k] + (tl.r0 + lane - b.s_lo[k]) : 0;
-        sv[s] = make_float2(Vp[off], b.A[off]);
-      }
+    for (int s = 0; s < kPerWave; ++s) {
+      const int kk = wv + kWaves * s;
+      const int32_t k = kk < nk ? k0 + kk : tl.k1 - 1;  // wave-uniform, inside the band
+      okv[s] = kk < nk && lane < R && k >= sh.plo[lane] && k < sh.phi[lane];
+      const long long off = okv[s] ? b.rowoff[k] + (tl.r0 + lane - b.s_lo[k]) : 0;
+      sv[s] = make_float2(Vp[off], b.A[off]);
+    }
+    const auto store_va = [&]() {
 #pragma unroll
       for (int s = 0; s < kPerWave; ++s)
-        if (lane < R) sh.va[wv + kWaves * s][lane] = ok[s] ? sv[s] : make_float2(INF, 0.f);
-    }
-    {
-      float sc[kPerWave][2];
-      bool ok[kPerWave][2];
+        if (lane < R) sh.va[wv + kWaves * s][lane] = okv[s] ? sv[s] : make_float2(INF, 0.f);
+    };
+    if constexpr (SLOTS > 1) store_va();
+    float sc[kPerWave][2];
+    bool okc[kPerWave][2];
 #pragma unroll
-      for (int s = 0; s < kPerWave; ++s) {
-        const int kk = wv + kWaves * s;
-        const int32_t k = kk < nk ? k0 + kk : tl.k1 - 1;
-        const int32_t qlo = b.q_lo[k], qhi = b.q_hi[k];
-        const long long qo = b.qoff[k];
+    for (int s = 0; s < kPerWave; ++s) {
+      const int kk = wv + kWaves * s;
+      const int32_t k = kk < nk ? k0 + kk : tl.k1 - 1;
+      const int32_t qlo = b.q_lo[k], qhi = b.q_hi[k];
+      const long long qo = b.qoff[k];
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          const int32_t c = tl.c0 + g * 64 + lane;
-          ok[s][g] = kk < nk && g < cgroups && c < tl.c1 && c >= qlo && c < qhi;
-          sc[s][g] = b.C[ok[s][g] ? qo + (c - qlo) : 0];
-        }
+      for (int g = 0; g < 2; ++g) {
+        const int32_t c = tl.c0 + g * 64 + lane;
+        okc[s][g] = kk < nk && g < cgroups && c < tl.c1 && c >= qlo && c < qhi;
+        sc[s][g] = b.C[okc[s][g] ? qo + (c - qlo) : 0];
       }
-#pragma unroll
-      for (int s = 0; s < kPerWave; ++s)
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          const int col = g * 64 + lane;
-          if (g < cgroups && col < CW) sh.ct[wv + kWaves * s][col] = ok[s][g] ? sc[s][g] : 0.f;
-        }
     }
+    if constexpr (SLOTS == 1) store_va();
+#pragma unroll
+    for (int s = 0; s < kPerWave; ++s)
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int col = g * 64 + lane;
+        if (g < cgroups && col < CW) sh.ct[wv + kWaves * s][col] = okc[s][g] ? sc[s][g] : 0.f;
+      }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSlots; ++j) {
@@ -594,8 +596,8 @@ bool trellis_fits_fused(long long Q, long long QC, int32_t n) {
   return Q > 0 && Q <= (long long)kFusedThreads * kFusedSlots && n <= 32767 && fused_bytes(Q, QC, n) <= kFusedLds;
 }
 
-hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_max, bool degen, bool fused,
-                              hipStream_t st) {
+hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t tile_cells, int32_t m_max, bool degen,
+                              bool fused, hipStream_t st) {
   if (a.n_models <= 0) return hipSuccess;
   if (fused) {
     if (!trellis_fits_fused(a.Q, a.QC, a.n)) return hipErrorInvalidValue;
@@ -609,17 +611,25 @@ hipError_t launch_trellis_run(const TrellisRun& a, int32_t n_tiles, int32_t m_ma
     hipLaunchKernelGGL(k_trellis_first, dim3(a.n, a.n_models), dim3(64), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (tile_cells != kTrellisTileCells && tile_cells != kTrellisSmallTileCells) return hipErrorInvalidValue;
+    const bool small_tiles = tile_cells == kTrellisSmallTileCells;
     for (int32_t i = 2; i < m_max && n_tiles > 0; ++i) {
       const dim3 grid(n_tiles, a.n_models);
+      // (1024-cell tiles are cut only for launches of many workgroups)
       const bool many = (long long)n_tiles * a.n_models >= kManyTiles;
-      if (degen && many)
-        hipLaunchKernelGGL((k_trellis_step<true, kChunkWide, kWavesWide>), grid, dim3(kThreads), 0, st, a, i);
+      constexpr int kS = kTrellisSmallTileCells / kThreads, kL = kTrellisTileCells / kThreads;
+      if (degen && !small_tiles)
+        hipLaunchKernelGGL((k_trellis_step<true, kChunkWide, kWavesWide, kL>), grid, dim3(kThreads), 0, st, a, i);
+      else if (degen && many)
+        hipLaunchKernelGGL((k_trellis_step<true, kChunkWide, kWavesWide, kS>), grid, dim3(kThreads), 0, st, a, i);
       else if (degen)
-        hipLaunchKernelGGL((k_trellis_step<true, kChunkSmall, kWavesSmall>), grid, dim3(kThreads), 0, st, a, i);
+        hipLaunchKernelGGL((k_trellis_step<true, kChunkSmall, kWavesSmall, kS>), grid, dim3(kThreads), 0, st, a, i);
+      else if (!small_tiles)
+        hipLaunchKernelGGL((k_trellis_step<false, kChunkWide, kWavesWide, kL>), grid, dim3(kThreads), 0, st, a, i);
       else if (many)
-        hipLaunchKernelGGL((k_trellis_step<false, kChunkWide, kWavesWide>), grid, dim3(kThreads), 0, st, a, i);
+        hipLaunchKernelGGL((k_trellis_step<false, kChunkWide, kWavesWide, kS>), grid, dim3(kThreads), 0, st, a, i);
       else
-        hipLaunchKernelGGL((k_trellis_step<false, kChunkSmall, kWavesSmall>), grid, dim3(kThreads), 0, st, a, i);
+        hipLaunchKernelGGL((k_trellis_step<false, kChunkSmall, kWavesSmall, kS>), grid, dim3(kThreads), 0, st, a, i);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }

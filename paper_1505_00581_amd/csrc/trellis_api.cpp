@@ -30,7 +30,7 @@ struct stm_trellis {
   stm::TrellisBand band{};
   long long Q = 0, QC = 0;
   stm::TrellisTile* tiles = nullptr;
-  int32_t n_tiles = 0;
+  int32_t n_tiles = 0, tile_cells = 0;
   stm::TrellisModel* models_dev = nullptr;
   stm::PairDev* pairs_dev = nullptr;
   int2* items_dev = nullptr;
@@ -107,7 +107,7 @@ int tr_enqueue(stm_trellis* p, float* e32, double* e64, double* eu, int32_t* as,
   a.e32 = e32;
   a.assign = as;
   if (timed) STM_HIP(hipEventRecord(p->ev_k0, st));
-  STM_HIP(stm::launch_trellis_run(a, p->n_tiles, p->m_max, p->degen, p->fused, st));
+  STM_HIP(stm::launch_trellis_run(a, p->n_tiles, p->tile_cells, p->m_max, p->degen, p->fused, st));
   if (timed) STM_HIP(hipEventRecord(p->ev_k1, st));
   STM_HIP(stm::launch_rescore_batch(p->pairs_dev, p->items_dev, p->n_models, p->sp, p->params.lambda1,
                                     p->params.lambda2, p->params.lambda3, 0.0, as, e64, eu, st));
@@ -302,18 +302,19 @@ int stm_trellis_create(stm_ctx* ctx, const stm_points* models, int32_t n_models,
   p->Q = ends[0];
   p->QC = ends[1];
   p->fused = !(params->flags & STM_TRELLIS_STEPWISE) && stm::trellis_fits_fused(p->Q, p->QC, n);
-  // Tiles of 1024 cells, or smaller while a step launch would have fewer than
+  // Tiles of 1024 cells, or of 256 when a step launch would have fewer than
   // kFewTiles workgroups: one workgroup per CU leaves its waves' latency
   // exposed, more and smaller tiles hide it at the price of staging each
-  // predecessor for fewer cells.
-  constexpr int kMinTileCells = 256;
+  // predecessor for fewer cells (and with one cell per thread the step kernel
+  // has the registers to issue a chunk's reads in one round).
   constexpr long long kFewTiles = 1024;
   int tile_cells = stm::kTrellisTileCells;
   std::vector<stm::TrellisTile> tiles = make_tiles(slo, shi, plo, phi, tile_cells);
-  while (tile_cells > kMinTileCells && (long long)tiles.size() * n_models < kFewTiles) {
-    tile_cells /= 2;
+  if ((long long)tiles.size() * n_models < kFewTiles) {
+    tile_cells = stm::kTrellisSmallTileCells;
     tiles = make_tiles(slo, shi, plo, phi, tile_cells);
   }
+  p->tile_cells = tile_cells;
   p->n_tiles = static_cast<int32_t>(tiles.size());
   TR_ALLOC(p->tiles, stm::TrellisTile, std::max<size_t>(1, tiles.size()));
   if (!tiles.empty())
