@@ -19,8 +19,9 @@
 // workgroup takes one tile, a rectangle of rows [r0, r1) by columns [c0, c1)
 // holding at most 1024 cells (narrow bands: up to 64 consecutive rows whose
 // successors span at most 128 nodes; wide bands: 32 rows by a 32-column
-// window, so that a staged predecessor serves 32 rows and 32 columns), thread
-// t taking cells t, t + 256, ...  The predecessors of the
+// window, so that a staged predecessor serves 32 rows and 32 columns), or at
+// most 256 (8 rows by 32 columns) when 1024-cell tiles would give a launch few
+// workgroups, thread t taking cells t, t + 256, ...  The predecessors of the
 // tile's rows, a contiguous node range, are staged 20 or 24 at a time in LDS: the
 // previous values with their directions va[k][r] (+inf where k is no
 // predecessor of r) and the directions C[k][c] of the window's columns.  A
