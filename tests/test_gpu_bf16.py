@@ -17,6 +17,7 @@ from scipy.spatial.distance import cdist
 
 import oracle
 import paper_1505_00581_amd as stm
+from parity_check import to_np
 from paper_1505_00581_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -99,3 +100,32 @@ def test_bf16_matching_against_oracle(ctx):
         f"assignment agreement {agree / n:.3f}")
     assert errs.max() < 5e-3 and errs.mean() < 1e-3
     assert gaps.mean() < 1e-3
+
+
+def test_bf16_plan_equals_per_model_calls(ctx):
+    """Split precision in a persistent plan (the unary tables of all models in
+    one BF16 MFMA pass per scene, graph-replayed) gives the rows of one
+    stm_match call per model bit for bit."""
+    import torch
+    w = synth.config2(3, n_models=3)
+    s = w.scenes[0]
+    keep = s.t < 400
+    s = synth.Points(np.ascontiguousarray(s.xy[keep]), np.ascontiguousarray(s.t[keep]),
+                     np.ascontiguousarray(s.desc[keep]), 400)
+    pbf = synth.Params(**{**w.params.__dict__, "unary_bf16": True})
+    ms = [m for m in w.models if int(m.t[-1] - m.t[0]) < 350]
+    assert ms
+    dms = [stm.DevicePoints.from_host(m) for m in ms]
+    ds = stm.DevicePoints.from_host(s)
+    plan = stm.Plan(ctx, dms, [ds], np.array([(i, 0) for i in range(len(ms))], np.int32), pbf)
+    out = plan.run()
+    out = plan.run(out)
+    torch.cuda.synchronize()
+    for q, dm in enumerate(dms):
+        res = ctx.match(dm, ds, pbf)
+        torch.cuda.synchronize()
+        rows = plan.pair_rows(out, q)
+        for got, key in zip(rows, ("energy32", "energy64", "energy_u64", "assign")):
+            np.testing.assert_array_equal(to_np(got).reshape(to_np(res[key]).shape), to_np(res[key]))
+    say(f"  BF16 plan over {len(ms)} models = per-model calls bit for bit")
+    plan.close()
