@@ -308,3 +308,37 @@ def test_graph_replays_equal_direct_launches(ctx, video):
         for k in ref:
             assert torch.equal(out[k], ref[k]), (T, k)
         tr.close()
+
+
+def test_whole_video_against_stored_oracle_optima(ctx, video):
+    """The whole 754-node video at full size, in the runs' own launch
+    configurations (at T = 10 one launch for every step; with no closeness
+    limit a lone model's step launches of 1,160 small tiles), against the FP64
+    oracle's optima that tests/golden/make_trellis_whole_video.py stored (the
+    oracle takes minutes on the no-limit trellis): energies within the
+    tolerance, assignments identical or of oracle energy equal to the optimum,
+    the FP64 re-score equal to the oracle's energy of the returned assignment."""
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(__file__), "golden", "trellis_whole_video.json")) as f:
+        gold = json.load(f)
+    s = video.scenes[0]
+    ds = stm.DevicePoints.from_host(s)
+    for T in sorted({r["T"] for r in gold["rows"]}):
+        rows = [r for r in gold["rows"] if r["T"] == T]
+        qs = [r["model"] for r in rows]
+        p = dataclasses.replace(video.params, T=T)
+        tr = stm.Trellis(ctx, [stm.DevicePoints.from_host(video.models[q]) for q in qs], ds, p)
+        info = tr.info()
+        out = tr.run()
+        torch.cuda.synchronize()
+        for j, (q, g) in enumerate(zip(qs, rows)):
+            m = video.models[q]
+            res = _rows(tr, out, j)
+            ora = dict(energy=np.array([g["energy"]]), energy_u=np.array([g["energy_u"]]),
+                       assign=np.array([g["assign"]], np.int32))
+            st = check(m, s, p, res, ora)
+            assert st["feasible"] == 1
+            say(f"  T={T} model {q}: {st}, fused={info['fused']}, tiles={info['tiles']}")
+        tr.close()
