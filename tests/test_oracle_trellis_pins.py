@@ -104,3 +104,28 @@ def test_exact_copy_in_clutter_is_found_with_zero_energy():
     z = r["assign"][0]
     assert (s.t[z] == tau0 + m.t - m.t[0]).all()
     np.testing.assert_allclose(s.xy[z], copy, atol=1e-6)
+
+
+def test_stored_whole_video_rows_are_the_oracles():
+    """The full-size trellis fixture (tests/golden/trellis_whole_video.json)
+    holds the oracle's own results: its T = 10 rows recomputed now agree bit
+    for bit (the row without a closeness limit takes the oracle minutes and is
+    left to the script that wrote it), and every stored assignment's literal
+    energy equals its stored optimum."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "trellis_whole_video.json")) as f:
+        gold = json.load(f)
+    w = synth.paper_blocks(0, n_models=50)
+    s = w.scenes[0]
+    for r in gold["rows"]:
+        p = dataclasses.replace(w.params, T=r["T"])
+        m = w.models[r["model"]]
+        z = np.array([r["assign"]], np.int32)
+        e, eu = oracle.energies(m, s, p, z)
+        assert abs(e[0] - r["energy"]) <= 1e-12 * max(1.0, abs(r["energy"]))
+        assert abs(eu[0] - r["energy_u"]) <= 1e-12 * max(1.0, abs(r["energy_u"]))
+        if r["T"] == 10:
+            o = oracle.match_trellis(m, s, p)
+            assert o["energy"][0] == r["energy"]
+            np.testing.assert_array_equal(o["assign"][0], z[0])
